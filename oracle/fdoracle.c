@@ -1,0 +1,369 @@
+/*
+ * FP64 CPU oracle for the memory-efficient superposition adjoint method
+ * (Herrmann, Buerchner, Kudela, Kollmannsberger, arXiv:2509.15744).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant with the GPU library.
+ *
+ * Everything is double precision, with plain loops; OpenMP only distributes
+ * independent cells over threads (no cell's arithmetic is reordered).
+ *
+ * Discretisation (paper Sec. 3.1, Eq. FDstencil2 with rho^-1 = 1 and
+ * kappa = c^2, extended to a 2r-th order central Laplacian):
+ *
+ *   u^{n+1} = 2 u^n - u^{n-1} + coef * (L u^n + f^n),   coef = dt^2 c^2
+ *
+ *   (L u)_i = dx^-2 sum_axes sum_{j=1..r} a_j [(u_{i+j} - u_i) + (u_{i-j} - u_i)]
+ *
+ * Homogeneous Neumann walls (paper Eq. BC) through ghost cells (paper
+ * Sec. 3.1): the grid is cell-centred and a ghost index mirrors about the
+ * half-cell face, -1-j -> j and n+j -> n-1-j.
+ *
+ * Time origin: u^{-1} = u^0 = 0 (paper Eq. IC; Alg. 1 starts from two zero
+ * levels).  Forward steps n = 0..nt-1 produce u^1..u^nt; the point force at
+ * step n is f^n = sum_s wavelet[n][s] delta_{x_s} / dx^d (paper Eq. source1
+ * with a discrete delta).  Receivers record u^1..u^nt; traces row n-1 holds
+ * level n.
+ *
+ * Misfit (paper Eq. cost1, time integral as dt * sum):
+ *   J = dt/2 sum_{n=1..nt} sum_r (u^n(x_r) - obs^n_r)^2
+ * Adjoint force (paper Eq. adjointSource1, scaled so that it enters the same
+ * step as f):  fdag^n_r = -(u^n(x_r) - obs^n_r) / dt, injected without 1/dx^d.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int ndim;      /* 1, 2 or 3 */
+    long n[3];     /* extents, axis 0 slowest; unused trailing axes have extent 1 */
+    long stride[3];
+    long ncell;
+    double dx;
+    int r;         /* stencil radius: order / 2 */
+    double w[9];   /* w[j] = a_j / dx^2, j = 1..r */
+} grid_t;
+
+static int make_grid(grid_t* g, int ndim, const long* shape, double dx, int r, const double* a)
+{
+    if (ndim < 1 || ndim > 3 || r < 1 || r > 8 || !(dx > 0.0)) return -1;
+    g->ndim = ndim;
+    for (int ax = 0; ax < 3; ++ax) g->n[ax] = ax < ndim ? shape[ax] : 1;
+    for (int ax = 0; ax < ndim; ++ax)
+        if (g->n[ax] < r) return -1;   /* the single mirror needs n >= r */
+    g->stride[2] = 1;
+    g->stride[1] = g->n[2];
+    g->stride[0] = g->n[1] * g->n[2];
+    g->ncell = g->n[0] * g->n[1] * g->n[2];
+    g->dx = dx;
+    g->r = r;
+    for (int j = 1; j <= r; ++j) g->w[j] = a[j - 1] / (dx * dx);
+    return 0;
+}
+
+/* Ghost cell index: half-sample mirror about the wall faces. */
+static long mirror(long i, long n)
+{
+    if (i < 0) return -1 - i;
+    if (i >= n) return 2 * n - 1 - i;
+    return i;
+}
+
+/* (L u) at one cell, straight from the definition above. */
+static double lap_at(const grid_t* g, const double* u, long cell)
+{
+    long pos[3];
+    long rem = cell;
+    for (int ax = 0; ax < 3; ++ax) {
+        pos[ax] = rem / g->stride[ax];
+        rem -= pos[ax] * g->stride[ax];
+    }
+    const double ui = u[cell];
+    double s = 0.0;
+    for (int ax = 0; ax < g->ndim; ++ax) {
+        for (int j = 1; j <= g->r; ++j) {
+            long ip = mirror(pos[ax] + j, g->n[ax]);
+            long im = mirror(pos[ax] - j, g->n[ax]);
+            double up = u[cell + (ip - pos[ax]) * g->stride[ax]];
+            double um = u[cell + (im - pos[ax]) * g->stride[ax]];
+            s += g->w[j] * ((up - ui) + (um - ui));
+        }
+    }
+    return s;
+}
+
+void orc_laplacian(int ndim, const long* shape, double dx, int r, const double* a,
+                   const double* u, double* out)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, shape, dx, r, a)) return;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < g.ncell; ++i) out[i] = lap_at(&g, u, i);
+}
+
+/* propagateStep (paper Alg. 1): u_next = 2 u_cur - u_prev + coef * L u_cur.
+ * Point forces are added afterwards by add_point_forces(). */
+static void propagate_step(const grid_t* g, const double* coef, const double* u_prev,
+                           const double* u_cur, double* u_next)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < g->ncell; ++i)
+        u_next[i] = 2.0 * u_cur[i] - u_prev[i] + coef[i] * lap_at(g, u_cur, i);
+}
+
+/* u_next += coef * (point force), one force value per listed cell. */
+static void add_point_forces(const double* coef, double* u_next, int npt, const long* cell,
+                             const double* value, double scale)
+{
+    for (int p = 0; p < npt; ++p) u_next[cell[p]] += coef[cell[p]] * value[p] * scale;
+}
+
+static double inv_cell_volume(const grid_t* g)
+{
+    return 1.0 / pow(g->dx, (double)g->ndim);
+}
+
+/* Source-free propagation from given levels; on return u_prev holds level
+ * nsteps-1 and u_cur level nsteps (relative to the inputs as levels -1, 0). */
+int orc_propagate(int ndim, const long* shape, double dx, int r, const double* a,
+                  const double* coef, double* u_prev, double* u_cur, int nsteps)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, shape, dx, r, a)) return -1;
+    double* u_next = malloc(sizeof(double) * g.ncell);
+    if (!u_next) return -2;
+    for (int n = 0; n < nsteps; ++n) {
+        propagate_step(&g, coef, u_prev, u_cur, u_next);
+        memcpy(u_prev, u_cur, sizeof(double) * g.ncell);
+        memcpy(u_cur, u_next, sizeof(double) * g.ncell);
+    }
+    free(u_next);
+    return 0;
+}
+
+static double* coef_from_speed(const grid_t* g, const double* c, double dt)
+{
+    double* coef = malloc(sizeof(double) * g->ncell);
+    if (!coef) return NULL;
+    for (long i = 0; i < g->ncell; ++i) coef[i] = dt * dt * c[i] * c[i];
+    return coef;
+}
+
+/* Forward solve.  traces [nt][nrec] (may be NULL); hist [(nt+1)][ncell] holds
+ * levels 0..nt (may be NULL); last2 [2][ncell] receives u^{nt-1}, u^nt (may be
+ * NULL). */
+int orc_forward(int ndim, const long* shape, double dx, int r, const double* a,
+                const double* c, double dt, int nt,
+                int nsrc, const long* src, const double* wavelet,
+                int nrec, const long* rec,
+                double* traces, double* hist, double* last2)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, shape, dx, r, a) || nt < 1) return -1;
+    double* coef = coef_from_speed(&g, c, dt);
+    double* um = calloc(g.ncell, sizeof(double));   /* u^{n-1} */
+    double* u0 = calloc(g.ncell, sizeof(double));   /* u^n     */
+    double* up = calloc(g.ncell, sizeof(double));   /* u^{n+1} */
+    if (!coef || !um || !u0 || !up) { free(coef); free(um); free(u0); free(up); return -2; }
+    const double vol = inv_cell_volume(&g);
+    if (hist) memset(hist, 0, sizeof(double) * g.ncell);   /* level 0 */
+    for (int n = 0; n < nt; ++n) {
+        propagate_step(&g, coef, um, u0, up);
+        add_point_forces(coef, up, nsrc, src, wavelet + (long)n * nsrc, vol);
+        if (traces)
+            for (int q = 0; q < nrec; ++q) traces[(long)n * nrec + q] = up[rec[q]];
+        if (hist) memcpy(hist + (long)(n + 1) * g.ncell, up, sizeof(double) * g.ncell);
+        double* t = um; um = u0; u0 = up; up = t;   /* delete u^{n-1} */
+    }
+    if (last2) {
+        memcpy(last2, um, sizeof(double) * g.ncell);
+        memcpy(last2 + g.ncell, u0, sizeof(double) * g.ncell);
+    }
+    free(coef); free(um); free(u0); free(up);
+    return 0;
+}
+
+/* J = dt/2 sum (traces - obs)^2 in index order; resid (may be NULL) = traces - obs. */
+double orc_misfit(int nt, int nrec, double dt, const double* traces, const double* obs,
+                  double* resid)
+{
+    double s = 0.0;
+    for (long i = 0; i < (long)nt * nrec; ++i) {
+        double rho = traces[i] - obs[i];
+        if (resid) resid[i] = rho;
+        s += rho * rho;
+    }
+    return 0.5 * dt * s;
+}
+
+/* Backward (adjoint) sweep of the same operator (the problem is self-adjoint,
+ * paper Sec. 2.2, Eq. adjointequation1):
+ *   mu^{nt} = mu^{nt+1} = 0,
+ *   mu^{j-1} = 2 mu^j - mu^{j+1} + coef * (L mu^j + fdag^j),  j = nt..1,
+ * with fdag [nt][nrec] (row j-1 = force at level j) injected at the receivers
+ * without cell-volume scaling.  hist [(nt+1)][ncell] receives mu^0..mu^nt (may
+ * be NULL); mu_src [nt][nsrc] receives mu^n at the source cells for n = 0..nt-1
+ * (may be NULL). */
+int orc_adjoint(int ndim, const long* shape, double dx, int r, const double* a,
+                const double* c, double dt, int nt,
+                int nrec, const long* rec, const double* fdag,
+                double* hist, int nsrc, const long* src, double* mu_src)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, shape, dx, r, a) || nt < 1) return -1;
+    double* coef = coef_from_speed(&g, c, dt);
+    double* mp = calloc(g.ncell, sizeof(double));   /* mu^{j+1} */
+    double* m0 = calloc(g.ncell, sizeof(double));   /* mu^j     */
+    double* mm = calloc(g.ncell, sizeof(double));   /* mu^{j-1} */
+    if (!coef || !mp || !m0 || !mm) { free(coef); free(mp); free(m0); free(mm); return -2; }
+    if (hist) memset(hist + (long)nt * g.ncell, 0, sizeof(double) * g.ncell);
+    for (int j = nt; j >= 1; --j) {
+        propagate_step(&g, coef, mp, m0, mm);
+        add_point_forces(coef, mm, nrec, rec, fdag + (long)(j - 1) * nrec, 1.0);
+        if (hist) memcpy(hist + (long)(j - 1) * g.ncell, mm, sizeof(double) * g.ncell);
+        if (mu_src)
+            for (int s = 0; s < nsrc; ++s) mu_src[(long)(j - 1) * nsrc + s] = mm[src[s]];
+        double* t = mp; mp = m0; m0 = mm; mm = t;
+    }
+    free(coef); free(mp); free(m0); free(mm);
+    return 0;
+}
+
+/* Exact discrete adjoint gradient with the full forward history stored.
+ *   dJ/dm_i = -sum_{n=0}^{nt-1} (mu^{n+1} - mu^n)_i (u^{n+1} - u^n)_i,  m = 1/c^2
+ *   dJ/dc_i = -(2 / c_i^3) dJ/dm_i
+ * (paper Eq. kernel2, mass term, as the discrete bilinear form in the time
+ * differences; Eq. gradientgamma per grid point).  sum_dmu2 (may be NULL)
+ * receives sum_n (mu^{n+1} - mu^n)_i^2, the k^2 term of Eq. superposedkernel1. */
+int orc_exact_gradient(int ndim, const long* shape, double dx, int r, const double* a,
+                       const double* c, double dt, int nt,
+                       int nsrc, const long* src, const double* wavelet,
+                       int nrec, const long* rec, const double* obs,
+                       double* grad_c, double* J, double* sum_dmu2, double* traces_out)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, shape, dx, r, a) || nt < 1) return -1;
+    const long N = g.ncell;
+    double* uh = malloc(sizeof(double) * (size_t)(nt + 1) * N);
+    double* mh = malloc(sizeof(double) * (size_t)(nt + 1) * N);
+    double* tr = malloc(sizeof(double) * (size_t)nt * nrec);
+    double* fd = malloc(sizeof(double) * (size_t)nt * nrec);
+    if (!uh || !mh || !tr || !fd) { free(uh); free(mh); free(tr); free(fd); return -2; }
+    int rc = orc_forward(ndim, shape, dx, r, a, c, dt, nt, nsrc, src, wavelet, nrec, rec,
+                         tr, uh, NULL);
+    if (!rc) {
+        double Jv = orc_misfit(nt, nrec, dt, tr, obs, fd);
+        if (J) *J = Jv;
+        for (long i = 0; i < (long)nt * nrec; ++i) fd[i] = -fd[i] / dt;
+        rc = orc_adjoint(ndim, shape, dx, r, a, c, dt, nt, nrec, rec, fd, mh, 0, NULL, NULL);
+    }
+    if (!rc) {
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < N; ++i) {
+            double gm = 0.0, s2 = 0.0;
+            for (int n = 0; n < nt; ++n) {
+                double du = uh[(long)(n + 1) * N + i] - uh[(long)n * N + i];
+                double dm = mh[(long)(n + 1) * N + i] - mh[(long)n * N + i];
+                gm -= dm * du;
+                s2 += dm * dm;
+            }
+            grad_c[i] = -2.0 / (c[i] * c[i] * c[i]) * gm;
+            if (sum_dmu2) sum_dmu2[i] = s2;
+        }
+        if (traces_out) memcpy(traces_out, tr, sizeof(double) * (size_t)nt * nrec);
+    }
+    free(uh); free(mh); free(tr); free(fd);
+    return rc;
+}
+
+/* Memory-efficient mixed-kernel computation, paper Alg. 1, in the paper's
+ * order: forward solve with adjoint force, cost and kernel increments; scale
+ * the stored adjoint forces by k; superposed solve backwards in time with
+ * kernel increments; return the cost and the approximate gradient.
+ *
+ * Kernel in the parameter m = 1/c^2 for a pair of level sequences (a, b):
+ *   K(a, b)_i = -sum_{n=0}^{nt-1} (a^{n+1} - a^n)_i (b^{n+1} - b^n)_i,
+ * and the approximation (paper Eq. superposedkernel)
+ *   dJ/dm ~ (K(v, v) - K(u, u)) / (2k),  v = u + k mu (paper Sec. 4).
+ *
+ * The superposed end levels are v^nt = u^nt and v^{nt-1} = u^{nt-1} +
+ * k coef fdag^nt at the receivers: the exact-adjoint end level mu^{nt-1}
+ * = coef fdag^nt is kept, so that v = u + k mu holds level by level.
+ * traces [nt][nrec] may be NULL. */
+int orc_superposition(int ndim, const long* shape, double dx, int r, const double* a,
+                      const double* c, double dt, int nt,
+                      int nsrc, const long* src, const double* wavelet,
+                      int nrec, const long* rec, const double* obs, double k,
+                      double* grad_c, double* J, double* traces)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, shape, dx, r, a) || nt < 1 || k == 0.0) return -1;
+    const long N = g.ncell;
+    const double vol = inv_cell_volume(&g);
+    double* coef = coef_from_speed(&g, c, dt);
+    double* Kt = calloc(N, sizeof(double));                   /* K~ */
+    double* um = calloc(N, sizeof(double));
+    double* u0 = calloc(N, sizeof(double));
+    double* up = calloc(N, sizeof(double));
+    double* fdag = calloc((size_t)nt * nrec, sizeof(double)); /* row n-1: level n */
+    if (!coef || !Kt || !um || !u0 || !up || !fdag) {
+        free(coef); free(Kt); free(um); free(u0); free(up); free(fdag);
+        return -2;
+    }
+    double cost = 0.0;
+
+    /* forward in time: solve, adjoint force, cost, -K(u,u) increment */
+    for (int n = 0; n < nt; ++n) {
+        propagate_step(&g, coef, um, u0, up);
+        add_point_forces(coef, up, nsrc, src, wavelet + (long)n * nsrc, vol);
+        double inc = 0.0;
+        for (int q = 0; q < nrec; ++q) {
+            double rho = up[rec[q]] - obs[(long)n * nrec + q];
+            if (traces) traces[(long)n * nrec + q] = up[rec[q]];
+            fdag[(long)n * nrec + q] = -rho / dt;
+            inc += rho * rho;
+        }
+        cost += 0.5 * dt * inc;
+        for (long i = 0; i < N; ++i) {
+            double du = up[i] - u0[i];
+            Kt[i] -= -du * du;          /* K~ <- K~ - K(u,u) increment */
+        }
+        double* t = um; um = u0; u0 = up; up = t;
+    }
+    /* now um = u^{nt-1}, u0 = u^nt */
+
+    /* scale the adjoint forces: fdag <- k fdag */
+    for (long i = 0; i < (long)nt * nrec; ++i) fdag[i] *= k;
+
+    /* superposed end levels: v^{nt} = u^{nt}, v^{nt-1} = u^{nt-1} + coef k fdag^{nt} */
+    double* vp = u0;   /* v^{j+1} */
+    double* v0 = um;   /* v^j     */
+    double* vm = up;   /* v^{j-1} */
+    add_point_forces(coef, v0, nrec, rec, fdag + (long)(nt - 1) * nrec, 1.0);
+    for (long i = 0; i < N; ++i) {
+        double dv = vp[i] - v0[i];
+        Kt[i] += -dv * dv;              /* interval [nt-1, nt] of K(v,v) */
+    }
+
+    /* backward in time: superposed solve with f^j + k fdag^j, +K(v,v) increment */
+    for (int j = nt - 1; j >= 1; --j) {
+        propagate_step(&g, coef, vp, v0, vm);
+        add_point_forces(coef, vm, nsrc, src, wavelet + (long)j * nsrc, vol);
+        add_point_forces(coef, vm, nrec, rec, fdag + (long)(j - 1) * nrec, 1.0);
+        for (long i = 0; i < N; ++i) {
+            double dv = v0[i] - vm[i];
+            Kt[i] += -dv * dv;          /* interval [j-1, j] */
+        }
+        double* t = vp; vp = v0; v0 = vm; vm = t;
+    }
+
+    for (long i = 0; i < N; ++i) {
+        double dJdm = Kt[i] / (2.0 * k);
+        grad_c[i] = -2.0 / (c[i] * c[i] * c[i]) * dJdm;
+    }
+    if (J) *J = cost;
+    free(coef); free(Kt); free(um); free(u0); free(up); free(fdag);
+    return 0;
+}

@@ -1,0 +1,252 @@
+"""Seeded synthetic inputs for the acoustic sensitivity workloads.
+
+This module only generates inputs (wave-speed fields, source wavelets,
+source and receiver cells, time step); it holds none of the method's
+arithmetic and is the one piece shared by the GPU path and the oracle.
+Every generator is deterministic in its seed.
+
+The paper's own inputs (a CT-scanned specimen and acquisition files
+published separately) are not available; these recipes stand in for them
+with the same structure: smooth heterogeneous media, a point source near the
+top face and a line or plane of receivers.
+
+Conventions: grids are C-order with axis 0 the depth (slowest) axis and the
+last axis contiguous; cells are addressed by flat C-order indices (int64);
+the wavelet is ``[nt, nsrc]`` with row n at t = n dt; dx = 1.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    """One sensitivity problem: model, acquisition and time axis."""
+    name: str
+    shape: tuple
+    order: int
+    dtype: str                 # "f32" or "f64": arithmetic type of the GPU fields
+    dx: float
+    dt: float
+    nt: int
+    c: object                  # numpy array (or torch tensor for device-generated grids)
+    c_ref: object              # model whose traces serve as the observed data
+    src: np.ndarray            # int64 [nsrc] flat cells
+    rec: np.ndarray            # int64 [nrec] flat cells
+    wavelet: np.ndarray        # float64 [nt, nsrc]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ndim(self):
+        return len(self.shape)
+
+    @property
+    def ncell(self):
+        return int(np.prod(self.shape))
+
+
+def ricker(nt: int, dt: float, f_peak: float, t0: float | None = None) -> np.ndarray:
+    """Ricker wavelet w(t) = (1 - 2 pi^2 f^2 tau^2) exp(-pi^2 f^2 tau^2), tau = t - t0,
+    sampled at t = n dt, n = 0..nt-1; t0 defaults to 1.5 / f_peak."""
+    if t0 is None:
+        t0 = 1.5 / f_peak
+    t = np.arange(nt, dtype=np.float64) * dt
+    a = (math.pi * f_peak * (t - t0)) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def flat(shape, coords) -> np.ndarray:
+    coords = np.asarray(coords, dtype=np.int64).reshape(-1, len(shape))
+    return np.ravel_multi_index(tuple(coords.T), tuple(shape)).astype(np.int64)
+
+
+def time_step(c_max: float, dx: float, courant: float) -> float:
+    """dt from the Courant number c_max dt / dx."""
+    return courant * dx / c_max
+
+
+# ---------------------------------------------------------------------------
+# media
+# ---------------------------------------------------------------------------
+
+def smooth_noise(shape, sigma: float, seed: int) -> np.ndarray:
+    """White Gaussian noise, Gaussian-smoothed (reflecting edges), scaled to max |P| = 1."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    p = gaussian_filter(rng.standard_normal(shape), sigma=sigma, mode="reflect")
+    return p / np.abs(p).max()
+
+
+def layered_speed(shape, n_layers: int, c_lo: float, c_hi: float, seed: int) -> np.ndarray:
+    """Piecewise-constant speed along axis 0: interfaces at sorted uniform depths,
+    layer speeds uniform in [c_lo, c_hi]."""
+    rng = np.random.default_rng(seed)
+    n0 = shape[0]
+    cuts = np.sort(rng.uniform(0.0, n0, size=n_layers - 1))
+    speeds = rng.uniform(c_lo, c_hi, size=n_layers)
+    depth = np.arange(n0) + 0.5
+    layer = np.searchsorted(cuts, depth)
+    prof = speeds[layer]
+    return np.broadcast_to(prof.reshape((n0,) + (1,) * (len(shape) - 1)), shape).copy()
+
+
+def layered_perturbed(shape, seed: int, n_layers=8, c_lo=1.5, c_hi=4.5, sigma=8.0, amp=0.05):
+    """Layered medium times (1 + amp P) with P smoothed noise; returns (c, c_layers)."""
+    base = layered_speed(shape, n_layers, c_lo, c_hi, seed)
+    pert = smooth_noise(shape, sigma, seed + 1)
+    return base * (1.0 + amp * pert), base
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+
+def inclusion_2d(n: int = 128, nt: int = 600, order: int = 4, dtype: str = "f64",
+                 radius: float = 16.0, c_in: float = 1.2, courant: float = 0.5,
+                 nrec: int = 32) -> Problem:
+    """Homogeneous c = 1 with a circular inclusion of speed ``c_in``; Ricker source
+    at the top centre (20 cells per wavelength at c = 1), receivers on the bottom row;
+    observed data come from the inclusion-free medium."""
+    shape = (n, n)
+    i, j = np.meshgrid(np.arange(n) + 0.0, np.arange(n) + 0.0, indexing="ij")
+    ctr = (n - 1) / 2.0
+    c = np.where((i - ctr) ** 2 + (j - ctr) ** 2 <= radius ** 2, c_in, 1.0)
+    c_ref = np.ones(shape)
+    dt = time_step(c.max(), 1.0, courant)
+    f_peak = 1.0 / 20.0
+    step = max(1, n // nrec)
+    rec = flat(shape, [[n - 1, step * q + step // 2] for q in range(nrec)])
+    src = flat(shape, [[0, n // 2]])
+    return Problem("inclusion2d", shape, order, dtype, 1.0, dt, nt, c, c_ref, src, rec,
+                   ricker(nt, dt, f_peak).reshape(nt, 1),
+                   meta={"courant": courant, "f_peak": f_peak})
+
+
+def layered_2d(n: int = 2048, nt: int = 4000, order: int = 8, dtype: str = "f32",
+               seed: int = 2, courant: float = 0.5, rec_every: int = 4,
+               src_cols=None) -> Problem:
+    """Eight random layers (c in [1.5, 4.5]) times a 5% smoothed (sigma = 8) perturbation;
+    Ricker source(s) on the top row at 20 cells per wavelength of the slowest speed;
+    receivers on the top row every ``rec_every`` cells; observed data from the
+    unperturbed layers."""
+    shape = (n, n)
+    c, c_ref = layered_perturbed(shape, seed)
+    dt = time_step(c.max(), 1.0, courant)
+    f_peak = c.min() / 20.0
+    if src_cols is None:
+        src_cols = [n // 2]
+    src = flat(shape, [[0, s] for s in src_cols])
+    rec = flat(shape, [[0, rec_every * q + rec_every // 2] for q in range(n // rec_every)])
+    w = ricker(nt, dt, f_peak)
+    wavelet = np.repeat(w.reshape(nt, 1), len(src), axis=1)
+    return Problem("layered2d", shape, order, dtype, 1.0, dt, nt, c, c_ref, src, rec, wavelet,
+                   meta={"courant": courant, "f_peak": f_peak, "seed": seed})
+
+
+def smooth_3d(n: int = 256, nt: int = 2000, order: int = 8, dtype: str = "f32", seed: int = 4,
+              sigma: float = 6.0, courant: float = 0.4, rec_every: int = 8) -> Problem:
+    """Smooth random speed in [1, 3] (white noise, Gaussian sigma, affine map); Ricker
+    source at the centre of the top face (f = 1/20); receiver grid on the face
+    x0 = 0 every ``rec_every`` cells; observed data from c = 2."""
+    shape = (n, n, n)
+    p = smooth_noise(shape, sigma, seed)
+    c = 1.0 + (p - p.min()) * (2.0 / (p.max() - p.min()))
+    c_ref = np.full(shape, 2.0)
+    dt = time_step(3.0, 1.0, courant)
+    f_peak = 1.0 / 20.0
+    src = flat(shape, [[0, n // 2, n // 2]])
+    h = rec_every // 2
+    rec = flat(shape, [[0, rec_every * a + h, rec_every * b + h]
+                       for a in range(n // rec_every) for b in range(n // rec_every)])
+    return Problem("smooth3d", shape, order, dtype, 1.0, dt, nt, c, c_ref, src, rec,
+                   ricker(nt, dt, f_peak).reshape(nt, 1),
+                   meta={"courant": courant, "f_peak": f_peak, "seed": seed})
+
+
+def layered_3d(n: int = 1024, nt: int = 3000, order: int = 8, dtype: str = "f32", seed: int = 5,
+               courant: float = 0.4, rec_every: int = 8, shots=None, device=None) -> Problem:
+    """3D version of the layered recipe (layers along axis 0, 5% smoothed perturbation,
+    sigma = 8); source(s) on the top face; receiver plane on x0 = 0 every ``rec_every``
+    cells.  With ``device`` (a torch device) the field is generated there, which keeps
+    billion-cell grids off the host; c and c_ref are then torch tensors."""
+    shape = (n, n, n)
+    if device is None:
+        c, c_ref = layered_perturbed(shape, seed)
+        c_min, c_max = float(c.min()), float(c.max())
+    else:
+        c, c_ref = _layered_perturbed_torch(shape, seed, device)
+        c_min, c_max = float(c.min()), float(c.max())
+    dt = time_step(c_max, 1.0, courant)
+    f_peak = c_min / 20.0
+    if shots is None:
+        shots = [(n // 2, n // 2)]
+    src = flat(shape, [[0, a, b] for (a, b) in shots])
+    h = rec_every // 2
+    rec = flat(shape, [[0, rec_every * a + h, rec_every * b + h]
+                       for a in range(n // rec_every) for b in range(n // rec_every)])
+    w = ricker(nt, dt, f_peak)
+    wavelet = np.repeat(w.reshape(nt, 1), len(src), axis=1)
+    return Problem("layered3d", shape, order, dtype, 1.0, dt, nt, c, c_ref, src, rec, wavelet,
+                   meta={"courant": courant, "f_peak": f_peak, "seed": seed})
+
+
+def _layered_perturbed_torch(shape, seed, device, n_layers=8, c_lo=1.5, c_hi=4.5,
+                             sigma=8.0, amp=0.05):
+    """Device-side twin of ``layered_perturbed`` for grids too large for host smoothing:
+    same recipe, torch's generator instead of numpy's (float32 result)."""
+    import torch
+    base_prof = layered_speed((shape[0], 1), n_layers, c_lo, c_hi, seed)[:, 0]
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 1)
+    p = torch.randn(shape, generator=g, device=device, dtype=torch.float32)
+    rad = int(math.ceil(4 * sigma))
+    x = torch.arange(-rad, rad + 1, device=device, dtype=torch.float32)
+    ker = torch.exp(-0.5 * (x / sigma) ** 2)
+    ker = ker / ker.sum()
+    for ax in range(len(shape)):
+        p = _smooth_axis(p, ker, rad, ax)
+    p = p / p.abs().max()
+    base = torch.as_tensor(base_prof, device=device, dtype=torch.float32)
+    base = base.view((shape[0],) + (1,) * (len(shape) - 1)).expand(shape)
+    c = base * (1.0 + amp * p)
+    return c.contiguous(), base.contiguous()
+
+
+def _smooth_axis(p, ker, rad, ax):
+    """1D convolution of ``p`` along ``ax`` with reflecting padding, in slabs."""
+    import torch
+    import torch.nn.functional as F
+    moved = p.movedim(ax, -1)
+    shp = moved.shape
+    flat2 = moved.reshape(-1, shp[-1])
+    out = torch.empty_like(flat2)
+    step = max(1, (1 << 26) // shp[-1])
+    w = ker.view(1, 1, -1)
+    for s in range(0, flat2.shape[0], step):
+        blk = flat2[s:s + step].unsqueeze(1)
+        blk = F.pad(blk, (rad, rad), mode="reflect")
+        out[s:s + step] = F.conv1d(blk, w).squeeze(1)
+    return out.view(shp).movedim(-1, ax).contiguous()
+
+
+def small_random(shape, order: int = 8, nt: int = 60, dtype: str = "f32", seed: int = 0,
+                 nsrc: int = 2, nrec: int = 7, courant: float = 0.4) -> Problem:
+    """Tiny heterogeneous problem with random cells for sources and receivers
+    (duplicates and wall cells included on purpose), for parity edge cases."""
+    rng = np.random.default_rng(seed)
+    c = 1.0 + rng.random(shape)
+    c_ref = np.full(shape, 1.5)
+    dt = time_step(c.max(), 1.0, courant)
+    n = int(np.prod(shape))
+    src = rng.integers(0, n, size=nsrc).astype(np.int64)
+    rec = rng.integers(0, n, size=nrec).astype(np.int64)
+    if nrec >= 2:
+        rec[-1] = rec[0]                       # a duplicate receiver
+    if nsrc >= 1 and nrec >= 3:
+        rec[1] = src[0]                        # a receiver on a source cell
+    wavelet = rng.standard_normal((nt, nsrc))
+    return Problem("random", tuple(shape), order, dtype, 1.0, dt, nt, c, c_ref, src, rec,
+                   wavelet, meta={"courant": courant, "seed": seed})
