@@ -1,0 +1,168 @@
+/*
+ * fdwave: memory-efficient adjoint sensitivities of the scalar acoustic wave
+ * equation on AMD MI355X (gfx950).
+ *
+ * Method: Herrmann, Buerchner, Kudela, Kollmannsberger, "A Memory Efficient
+ * Adjoint Method to Enable Billion Parameter Optimization on a Single GPU in
+ * Dynamic Problems", arXiv:2509.15744.  The sensitivity is the mixed kernel
+ * of the superposed field v = u + k u_dagger (Sec. 4, Eq. superposedkernel),
+ * computed by Algorithm 1: a forward sweep that accumulates K(u,u), then a
+ * backward sweep of the superposed field that accumulates K(v,v), so that no
+ * forward history is stored.
+ *
+ * Physics and discretisation (Sec. 2.3, Eq. wavetopopt with rho^-1 = 1 and
+ * kappa = c^2; Sec. 3.1, Eq. FDstencil2 extended to a 2r-th order central
+ * Laplacian):
+ *
+ *     u^{n+1} = 2 u^n - u^{n-1} + dt^2 c^2 (L u^n + f^n)
+ *     (L u)_i = dx^-2 sum_axes sum_{j=1..r} a_j [(u_{i+j} - u_i) + (u_{i-j} - u_i)]
+ *
+ * with homogeneous Neumann walls (Eq. BC) as half-sample mirror ghost cells
+ * (Sec. 3.1): a ghost index -1-j reads cell j and n+j reads cell n-1-j.
+ *
+ * Time axis: u^{-1} = u^0 = 0 (Eq. IC).  Forward steps n = 0..nt-1 produce
+ * u^1..u^nt.  The point force of step n is f^n = wavelet[n][s] / dx^d at
+ * source cell s (Eq. source1).  Receivers record u^1..u^nt: row n-1 of every
+ * [nt][nrec] trace array holds level n.
+ *
+ * Misfit (Eq. cost1 with the time integral as dt * sum):
+ *     J = dt/2 sum_{n=1..nt} sum_r (u^n(x_r) - obs^n_r)^2
+ * Gradient: dJ/dc per cell, dJ/dc = -(2/c^3) dJ/dm with m = 1/c^2, and the
+ * kernel in m for level sequences a, b is K(a,b) = -sum_n (a^{n+1}-a^n)(b^{n+1}-b^n)
+ * (the mass term of Eq. kernel2 in discrete form).  The approximation is
+ *     dJ/dm ~ (K(v,v) - K(u,u)) / (2k)
+ * and differs from the exact discrete adjoint by k/2 K(mu,mu) (Eq.
+ * superposedkernel1).
+ *
+ * Layouts: every grid array is C-order [n0][n1] or [n0][n1][n2], last axis
+ * contiguous, axis 0 the depth axis.  Cells are named by flat C-order int64
+ * indices.
+ *
+ * Ownership: the caller owns every pointer passed in; the library never
+ * frees or retains one after a call returns.  Arrays marked DEVICE live in
+ * the current HIP device's memory; arrays marked HOST are read during the
+ * call only.  Temporary device memory is taken stream-ordered on `stream`
+ * and released before the call returns.
+ *
+ * Streams: all device work is enqueued on `stream` (a hipStream_t; NULL is
+ * the null stream).  Calls that return a host value (J, c_max) synchronise
+ * that stream before returning.
+ *
+ * Errors: every entry point returns FD_OK (0) or a positive FD_E_* code and
+ * leaves a message for fd_last_error() in the calling thread.  Outputs are
+ * unspecified after an error.  No C++ exception crosses this interface.
+ */
+#ifndef FDWAVE_H
+#define FDWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FD_OK 0
+#define FD_E_ARG 1        /* null pointer, bad ndim/order/dtype, shape < r, index out of range, nt < 1, k = 0 ... */
+#define FD_E_CFL 2        /* c_max dt / dx above the leapfrog stability limit */
+#define FD_E_NOMEM 3      /* device allocation failed */
+#define FD_E_DEVICE 4     /* a HIP call failed; fd_last_error() carries its text */
+#define FD_E_NONFINITE 5  /* non-finite or non-positive speed, or a non-finite result */
+
+#define FD_F32 0
+#define FD_F64 1
+
+typedef struct fd_grid {
+    int32_t ndim;       /* 2 or 3 */
+    int64_t shape[3];   /* extents n0, n1[, n2]; each >= order/2; shape[2] ignored when ndim = 2 */
+    double dx;          /* cell size, > 0, the same on every axis */
+    int32_t order;      /* space order: 2, 4 or 8 */
+    int32_t dtype;      /* FD_F32 or FD_F64: element type of every field, wavelet and trace array */
+} fd_grid;
+
+typedef struct fd_acq {
+    int32_t nsrc;             /* number of point sources, >= 0 */
+    const int64_t* src_cell;  /* HOST [nsrc] flat cell of each source (repeats allowed) */
+    const void* wavelet;      /* DEVICE [nt][nsrc] source time functions, row n at t = n dt */
+    int32_t nrec;             /* number of receivers, >= 0 */
+    const int64_t* rec_cell;  /* HOST [nrec] flat cell of each receiver (repeats allowed) */
+} fd_acq;
+
+/* Optional timing record, filled by a call whose fd_opts.timing points here: HIP events
+ * on `stream` bracket the step launches of each sweep (one step kernel per time step). */
+typedef struct fd_timing {
+    double fwd_ms;          /* device time from the first to the last forward step launch */
+    int32_t fwd_launches;   /* forward step launches in that interval */
+    double bwd_ms;          /* the same for the superposed backward sweep */
+    int32_t bwd_launches;
+} fd_timing;
+
+typedef struct fd_opts {
+    int32_t acc_dtype;  /* sensitivity accumulator: FD_F64 (default) or FD_F32 (f32 grids only) */
+    int32_t variant;    /* kernel tile variant; 0 lets the library choose (see fd_variant_count) */
+    fd_timing* timing;  /* HOST, may be NULL: when set, the call also synchronises `stream` */
+} fd_opts;
+
+/* Caller-owned device state that carries one gradient from its forward sweep
+ * (fd_sens_forward) to its backward sweep (fd_sens_backward). */
+typedef struct fd_state {
+    void* u_a;       /* DEVICE [ncell] grid dtype */
+    void* u_b;       /* DEVICE [ncell] grid dtype */
+    void* acc;       /* DEVICE [ncell] accumulator dtype: K(u,u) - K(v,v) in progress */
+    void* residual;  /* DEVICE [nt][nrec] grid dtype: u^n(x_r) - obs^n_r */
+} fd_state;
+
+/* Message of the last failed call in this thread ("" if none). */
+const char* fd_last_error(void);
+
+/* Largest stable Courant number c_max dt / dx for the leapfrog with the order-`order`
+ * central stencil in `ndim` dimensions (2 / sqrt(ndim * |symbol(pi)|)); 0 if invalid. */
+double fd_cfl_limit(int32_t ndim, int32_t order);
+
+/* Number of kernel tile variants for `ndim` (valid fd_opts.variant values are 1..count). */
+int32_t fd_variant_count(int32_t ndim);
+
+/* Forward solve (Alg. 1 forward loop without cost or kernel): traces DEVICE [nt][nrec]
+ * receive u^1..u^nt at the receivers.  c DEVICE [ncell] is the wave speed. */
+int fd_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int32_t nt,
+               void* traces, const fd_opts* opts, void* stream);
+
+/* Misfit J = dt/2 sum (traces - observed)^2 (Eq. cost1) over [nt][nrec] DEVICE arrays of
+ * `dtype`; residual_or_null DEVICE [nt][nrec] receives traces - observed; J_host receives J
+ * (reduced in fixed order in double precision). */
+int fd_misfit(int32_t nt, int32_t nrec, int32_t dtype, double dt, const void* traces,
+              const void* observed, void* residual_or_null, double* J_host, void* stream);
+
+/* Memory-efficient sensitivity (Alg. 1): J and grad_c DEVICE [ncell] = dJ/dc at factor k
+ * (k != 0, finite; the same k gives the same result on every call).  observed DEVICE
+ * [nt][nrec]; traces_or_null DEVICE [nt][nrec]. */
+int fd_adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
+                           int32_t nt, const void* observed, double k, void* grad_c,
+                           double* J_host, void* traces_or_null, const fd_opts* opts,
+                           void* stream);
+
+/* First half of fd_adjoint_sensitivity: the forward sweep with cost, adjoint force and
+ * K(u,u) accumulation; leaves u^{nt-1}, u^nt, the accumulator and the residuals in
+ * `state` (all four arrays overwritten).  J_host may be NULL. */
+int fd_sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
+                    int32_t nt, const void* observed, const fd_state* state,
+                    void* traces_or_null, double* J_host, const fd_opts* opts, void* stream);
+
+/* Second half: the superposed backward sweep from `state` (consumed: its arrays are
+ * overwritten) and grad_c = grad_scale * dJ/dc.  Same grid, c, acq, dt, nt and opts
+ * as the fd_sens_forward call that filled `state`. */
+int fd_sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
+                     int32_t nt, double k, const fd_state* state, double grad_scale,
+                     void* grad_c, const fd_opts* opts, void* stream);
+
+/* Source-free steps (test hook for closed-form solutions): on entry u_prev, u_cur DEVICE
+ * [ncell] hold levels -1 and 0; on return they hold levels nsteps-1 and nsteps.
+ * coef DEVICE [ncell] is dt^2 c^2 itself (no CFL check). */
+int fd_propagate(const fd_grid* grid, const void* coef, void* u_prev, void* u_cur,
+                 int32_t nsteps, const fd_opts* opts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDWAVE_H */

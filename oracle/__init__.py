@@ -138,6 +138,8 @@ def _load():
         lib.orc_exact_gradient.restype = I
         lib.orc_superposition.argtypes = grid + [P, D, I, I, P, P, I, P, P, D, P, P, P]
         lib.orc_superposition.restype = I
+        lib.orc_num_threads.argtypes = []
+        lib.orc_num_threads.restype = I
         _lib = lib
     return _lib
 
@@ -298,6 +300,11 @@ def fd_gradient(c, dx, order, dt, nt, src, wavelet, rec, observed, cells, eps=1e
         jm = misfit_of_speed(cm.reshape(c.shape), dx, order, dt, nt, src, wavelet, rec, observed)
         out[q] = (jp - jm) / (2.0 * eps)
     return out
+
+
+def num_threads() -> int:
+    """Threads used by the oracle's parallel cell loops."""
+    return int(_load().orc_num_threads())
 
 
 def cfl_limit(ndim: int, order: int) -> float:

@@ -1,0 +1,77 @@
+// Internal interfaces between the fdwave host runtime and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdw {
+
+// A source or receiver point inside one block's region, sorted by plane.
+struct Event {
+    int32_t plane;  // coordinate along the marching axis (axis 0)
+    int32_t lane;   // position inside the block tile: ly * TZ + lz
+    int32_t kind;   // EV_SRC or EV_REC
+    int32_t idx;    // source or receiver number
+};
+enum { EV_SRC = 0, EV_REC = 1 };
+
+// Arguments of one leapfrog step over the whole grid.
+struct StepArgs {
+    const void* ucur;    // level n (backward: j)
+    void* unew;          // level n-1 on entry, n+1 on return (backward: j+1 -> j-1)
+    const void* c;       // wave speed, or dt^2 c^2 itself when coef_direct
+    void* acc;           // sensitivity accumulator (used when acc_sign != 0)
+    int32_t n0, n1, n2;  // extents; 2D grids run with n1 = 1
+    double w[8];         // a_j / dx^2, j = 1..r
+    double dt2;          // dt^2
+    int32_t coef_direct; // 1: c already holds dt^2 c^2
+    int32_t acc_sign;    // 0: no accumulation, +1: acc += d^2, -1: acc -= d^2
+    // events
+    const int32_t* blk_off;  // [nblk + 1] ranges into ev
+    const Event* ev;
+    const void* wavelet;     // [nt][nsrc]
+    int32_t nsrc;
+    int32_t row_src;         // wavelet row injected in this step
+    double inv_vol;          // 1 / dx^d
+    int32_t sample;          // forward: write traces and residuals at receivers
+    int32_t inject_rec;      // backward: inject rec_scale * residual at receivers
+    void* traces;            // [nt][nrec] or null
+    void* resid;             // [nt][nrec]
+    const void* obs;         // [nt][nrec]
+    int32_t nrec;
+    int32_t row_rec;         // trace row written (forward) or residual row injected (backward)
+    double rec_scale;        // -k / dt
+    // block decomposition
+    int32_t nty, ntz, chunk_len, nblk;
+};
+
+// Tile shape of one kernel variant.
+struct Variant {
+    int32_t tz;      // tile width along the contiguous axis (threads along z)
+    int32_t ty;      // tile height along axis 1 (3D only)
+    int32_t chunk;   // planes marched per block along axis 0 (0: whole axis)
+};
+
+int variant_count(int ndim);
+Variant variant_shape(int ndim, int variant);  // variant in 1..count
+
+// Launches one step; returns a hipError_t.
+hipError_t launch_step(int ndim, int r, int dtype, int acc_dtype, int variant, int nblk,
+                       const StepArgs& a, hipStream_t s);
+
+// Misc kernels.  All return hipError_t of the launch.
+hipError_t launch_speed_stats(int dtype, const void* c, int64_t n, double* d_out3, double* d_part,
+                              hipStream_t s);
+hipError_t launch_sum_squares(int dtype, const void* x, const void* y, void* diff_out, int64_t n,
+                              double* d_part, double* d_out, hipStream_t s);
+hipError_t launch_terminal(int dtype, int acc_dtype, int nuniq, const int64_t* ucell,
+                           const int32_t* uoff, const int32_t* uidx, const void* c, double dt2,
+                           const void* u_last, void* u_prev, void* acc, const void* resid_row,
+                           double rec_scale, hipStream_t s);
+hipError_t launch_finalize(int dtype, int acc_dtype, int64_t n, const void* acc, const void* c,
+                           double scale, void* grad, hipStream_t s);
+
+constexpr int kReduceBlocks = 512;
+constexpr int kReduceThreads = 256;
+
+}  // namespace fdw

@@ -1,0 +1,57 @@
+"""Shared helpers of the GPU parity tests: oracle references and tensor plumbing."""
+import functools
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def say(*args):
+    """Name the case before a GPU step (flushed, so it survives a lost box)."""
+    print("[case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def to_dev(x, dtype):
+    import torch
+    t = torch.as_tensor(np.ascontiguousarray(x), dtype=dtype)
+    return t.cuda()
+
+
+def torch_dtype(code):
+    import torch
+    return torch.float64 if code == "f64" else torch.float32
+
+
+class OracleCase:
+    """Oracle results for one problem: observed data, traces, J, gradients."""
+
+    def __init__(self, p, k=None, gap=None, exact=True):
+        self.p = p
+        self.obs, _, _ = oracle.forward(p.c_ref, p.dx, p.order, p.dt, p.nt, p.src, p.wavelet, p.rec)
+        if exact:
+            self.g_exact, self.J, self.s2, self.traces = oracle.exact_gradient(
+                p.c, p.dx, p.order, p.dt, p.nt, p.src, p.wavelet, p.rec, self.obs)
+            gap1 = np.linalg.norm(self.s2 / p.c ** 3) / np.linalg.norm(self.g_exact)
+            if k is None:
+                k = gap / gap1
+            self.gap_per_k = gap1
+        self.k = k
+        self.g_approx, self.J_approx, self.traces_approx = oracle.superposition_gradient(
+            p.c, p.dx, p.order, p.dt, p.nt, p.src, p.wavelet, p.rec, self.obs, k)
+        if not exact:
+            self.traces = self.traces_approx
+            self.J = self.J_approx
+
+
+@functools.lru_cache(maxsize=16)
+def cached_case(key, builder, k=None, gap=None, exact=True):
+    return OracleCase(builder(), k=k, gap=gap, exact=exact)

@@ -1,0 +1,133 @@
+"""The C-ABI library loads, exports every entry point that include/fdwave.h declares,
+and rejects bad arguments before any device work.  No GPU needed: every call here
+returns from host-side validation (or is a pure host function)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdwave.h")
+
+
+@pytest.fixture(scope="module")
+def fdw():
+    from paper_2509_15744_amd import fdwave
+    return fdwave
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_three_paper_calls():
+    names = _declared()
+    for n in ("fd_forward", "fd_adjoint_sensitivity", "fd_misfit"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(fdw):
+    lib = ctypes.CDLL(fdw.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_cfl_limits(fdw):
+    want = {(2, 2): 1 / np.sqrt(2), (3, 2): 1 / np.sqrt(3), (2, 4): 0.612372, (3, 4): 0.5,
+            (2, 8): 0.554632, (3, 8): 0.452856}
+    for (d, p), v in want.items():
+        assert abs(fdw.fd_cfl_limit(d, p) - v) < 1e-5
+    assert fdw.fd_cfl_limit(3, 6) == 0.0
+    assert fdw.fd_variant_count(2) >= 1 and fdw.fd_variant_count(3) >= 1
+    assert fdw.fd_variant_count(1) == 0
+
+
+def _call_forward(fdw, grid, nt=10, dt=0.1, acq=None, opts=None):
+    if acq is None:
+        acq = fdw.fd_acq()
+    return fdw.lib().fd_forward(ctypes.byref(grid) if grid is not None else None, None,
+                                ctypes.byref(acq), dt, nt, None,
+                                ctypes.byref(opts) if opts is not None else None, None)
+
+
+def test_grid_validation(fdw):
+    ok = fdw.make_grid((16, 16), 1.0, 8, fdw.FD_F32)
+    cases = [
+        (None, "grid is null"),
+        (fdw.make_grid((16,), 1.0, 8, fdw.FD_F32), "ndim"),
+        (fdw.make_grid((16, 16), 1.0, 6, fdw.FD_F32), "order"),
+        (fdw.make_grid((16, 16), 1.0, 8, 7), "dtype"),
+        (fdw.make_grid((16, 16), 0.0, 8, fdw.FD_F32), "dx"),
+        (fdw.make_grid((16, 16), float("nan"), 8, fdw.FD_F32), "dx"),
+        (fdw.make_grid((3, 16), 1.0, 8, fdw.FD_F32), "extent"),
+        (fdw.make_grid((16, 16, 2), 1.0, 8, fdw.FD_F32), "extent"),
+    ]
+    for g, msg in cases:
+        rc = _call_forward(fdw, g)
+        assert rc == fdw.FD_E_ARG
+        assert msg in fdw.lib().fd_last_error().decode()
+    # time axis
+    assert _call_forward(fdw, ok, nt=0) == fdw.FD_E_ARG
+    assert "nt" in fdw.lib().fd_last_error().decode()
+    assert _call_forward(fdw, ok, dt=-1.0) == fdw.FD_E_ARG
+    # options
+    o = fdw.make_opts(None, 99)
+    assert _call_forward(fdw, ok, opts=o) == fdw.FD_E_ARG
+    assert "variant" in fdw.lib().fd_last_error().decode()
+
+
+def test_acquisition_validation(fdw):
+    g = fdw.make_grid((16, 16), 1.0, 4, fdw.FD_F64)
+    src = np.array([3, 256], dtype=np.int64)       # 256 is outside a 16 x 16 grid
+    a = fdw.fd_acq()
+    a.nsrc = 2
+    a.src_cell = src.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    assert _call_forward(fdw, g, acq=a) == fdw.FD_E_ARG
+    assert "source cell 1 out of range" in fdw.lib().fd_last_error().decode()
+    rec = np.array([-1], dtype=np.int64)
+    b = fdw.fd_acq()
+    b.nrec = 1
+    b.rec_cell = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    assert _call_forward(fdw, g, acq=b) == fdw.FD_E_ARG
+    assert "receiver cell 0 out of range" in fdw.lib().fd_last_error().decode()
+    c = fdw.fd_acq()
+    c.nrec = 2                                      # count without cells
+    assert _call_forward(fdw, g, acq=c) == fdw.FD_E_ARG
+
+
+def test_sensitivity_rejects_bad_k(fdw):
+    g = fdw.make_grid((16, 16), 1.0, 4, fdw.FD_F64)
+    a = fdw.fd_acq()
+    J = ctypes.c_double()
+    for k in (0.0, float("inf"), float("nan")):
+        rc = fdw.lib().fd_adjoint_sensitivity(ctypes.byref(g), None, ctypes.byref(a), 0.1, 10, None, k,
+                                              None, ctypes.byref(J), None, None, None)
+        assert rc == fdw.FD_E_ARG
+        assert "k must be" in fdw.lib().fd_last_error().decode()
+
+
+def test_misfit_validation(fdw):
+    J = ctypes.c_double()
+    assert fdw.lib().fd_misfit(10, 3, 5, 0.1, None, None, None, ctypes.byref(J), None) == fdw.FD_E_ARG
+    assert fdw.lib().fd_misfit(0, 3, 0, 0.1, None, None, None, ctypes.byref(J), None) == fdw.FD_E_ARG
+    assert fdw.lib().fd_misfit(10, -1, 0, 0.1, None, None, None, ctypes.byref(J), None) == fdw.FD_E_ARG
+    assert fdw.lib().fd_misfit(10, 3, 0, 0.1, None, None, None, None, None) == fdw.FD_E_ARG
+
+
+def test_error_message_is_thread_local_and_cleared(fdw):
+    import threading
+    assert _call_forward(fdw, None) == fdw.FD_E_ARG
+    seen = []
+
+    def other():
+        seen.append(fdw.lib().fd_last_error().decode())
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen == [""]
+    assert fdw.lib().fd_last_error().decode() != ""
