@@ -68,10 +68,10 @@ def cpu_baseline(p, c_dev, args, wl, torch):
     shape = p.shape
     if len(shape) == 3:
         crop = (min(256, shape[0]), min(512, shape[1]), min(512, shape[2]))
-        nt_s = 10
+        nt_s = 30
     else:
         crop = (min(1024, shape[0]), min(2048, shape[1]))
-        nt_s = 40
+        nt_s = 400
     sx = [int(s) for s in np.unravel_index(int(p.src[0]), shape)]
     lo = [max(0, min(sx[a] - crop[a] // 2, shape[a] - crop[a])) for a in range(len(shape))]
     sl = tuple(slice(lo[a], lo[a] + crop[a]) for a in range(len(shape)))

@@ -101,6 +101,7 @@ typedef struct fd_opts {
     int32_t acc_dtype;  /* sensitivity accumulator: FD_F64 (default) or FD_F32 (f32 grids only) */
     int32_t variant;    /* kernel tile variant; 0 lets the library choose (see fd_variant_count) */
     fd_timing* timing;  /* HOST, may be NULL: when set, the call also synchronises `stream` */
+    int32_t chunk;      /* planes of axis 0 marched per block; 0 lets the library choose */
 } fd_opts;
 
 /* Caller-owned device state that carries one gradient from its forward sweep

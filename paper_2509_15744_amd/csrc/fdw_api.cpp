@@ -67,6 +67,7 @@ int check_dev(const void* p, size_t bytes, const char* what)
 struct Geo {
     fd_timing* timing = nullptr;
     int ndim, r, dtype, acc_dtype, variant;
+    int chunk = 0;       // requested planes per block (0: library choice)
     int n0, n1, n2;      // internal extents (2D: n1 = 1)
     int64_t ncell;
     double dx, inv_vol;
@@ -85,12 +86,13 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
         if (n[ax] < r) return fail(FD_E_ARG, "every extent must be >= order/2");
         if (n[ax] > (1 << 30)) return fail(FD_E_ARG, "extent too large");
     }
+    if (n[1] * n[2] >= ((int64_t)1 << 31)) return fail(FD_E_ARG, "plane normal to axis 0 too large");
     Geo G;
     G.ndim = g->ndim;
     G.r = r;
     G.dtype = g->dtype;
     G.acc_dtype = FD_F64;
-    G.variant = 1;
+    G.variant = g->ndim == 3 ? 3 : 1;   // measured best default tile (64 x 8 in 3D)
     if (o) {
         if (o->acc_dtype != FD_F32 && o->acc_dtype != FD_F64)
             return fail(FD_E_ARG, "acc_dtype must be FD_F32 or FD_F64");
@@ -101,6 +103,8 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
             G.variant = o->variant;
         }
         G.timing = o->timing;
+        if (o->chunk < 0) return fail(FD_E_ARG, "chunk is negative");
+        G.chunk = o->chunk;
     }
     if (G.dtype == FD_F64) G.acc_dtype = FD_F64;
     G.n0 = (int)n[0];
@@ -215,12 +219,19 @@ int make_plan(const Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Sc
     P->ntz = (G.n2 + v.tz - 1) / v.tz;
     P->nty = (G.n1 + v.ty - 1) / v.ty;
     const int64_t tiles = (int64_t)P->ntz * P->nty;
-    // split axis 0 into chunks so that the launch holds >= ~2048 blocks, keeping
-    // chunks >= 8 r planes (the queue warm-up re-reads 2r planes per chunk)
-    int64_t want = (2048 + tiles - 1) / tiles;
-    int64_t maxch = std::max<int64_t>(1, G.n0 / (8 * G.r));
-    int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
-    P->chunk = (int)((G.n0 + nch - 1) / nch);
+    if (G.chunk > 0) {
+        P->chunk = std::min(G.chunk, G.n0);
+    } else {
+        // split axis 0 so that the launch holds ~4M threads (several rounds of resident
+        // blocks: a short last round leaves the chip idle), keeping chunks >= 16 r
+        // planes in 3D (each chunk re-reads 2r planes to fill its queue)
+        const int64_t want_blocks = ((int64_t)4 << 20) / v.threads;
+        const int64_t want = (want_blocks + tiles - 1) / tiles;
+        const int min_chunk = G.ndim == 3 ? 16 * G.r : 2 * G.r;
+        const int64_t maxch = std::max<int64_t>(1, G.n0 / min_chunk);
+        const int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
+        P->chunk = (int)((G.n0 + nch - 1) / nch);
+    }
     P->nch = (G.n0 + P->chunk - 1) / P->chunk;
     const int64_t nblk = tiles * P->nch;
     if (nblk > (1 << 28)) return fail(FD_E_ARG, "grid too large for the block decomposition");

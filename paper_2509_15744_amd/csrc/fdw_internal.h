@@ -49,7 +49,7 @@ struct StepArgs {
 struct Variant {
     int32_t tz;      // tile width along the contiguous axis (threads along z)
     int32_t ty;      // tile height along axis 1 (3D only)
-    int32_t chunk;   // planes marched per block along axis 0 (0: whole axis)
+    int32_t threads; // threads per block
 };
 
 int variant_count(int ndim);

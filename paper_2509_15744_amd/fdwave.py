@@ -47,7 +47,7 @@ class fd_timing(ctypes.Structure):
 
 class fd_opts(ctypes.Structure):
     _fields_ = [("acc_dtype", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("timing", ctypes.POINTER(fd_timing))]
+                ("timing", ctypes.POINTER(fd_timing)), ("chunk", ctypes.c_int32)]
 
 
 class fd_state(ctypes.Structure):
@@ -143,8 +143,9 @@ class Acquisition:
         self.c = a
 
 
-def make_opts(acc_dtype=None, variant=0, timing: "fd_timing | None" = None) -> fd_opts:
+def make_opts(acc_dtype=None, variant=0, timing: "fd_timing | None" = None, chunk=0) -> fd_opts:
     o = fd_opts()
+    o.chunk = int(chunk)
     if timing is not None:
         o.timing = ctypes.pointer(timing)
     if acc_dtype is None or acc_dtype in ("f64", torch.float64, FD_F64):
@@ -166,13 +167,13 @@ def fd_variant_count(ndim: int) -> int:
 
 
 def fd_forward(c, dx, order, src, wavelet, rec, dt, nt, traces=None, acc_dtype=None, variant=0,
-               timing=None):
+               timing=None, chunk=0):
     """Receiver traces [nt, nrec] of the forward solve."""
     acq = Acquisition(src, wavelet, rec)
     if traces is None:
         traces = torch.empty((nt, len(acq.rec)), dtype=c.dtype, device=c.device)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
-    o = make_opts(acc_dtype, variant, timing)
+    o = make_opts(acc_dtype, variant, timing, chunk)
     _raise(_lib.fd_forward(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt),
                            _dev(traces, "traces"), ctypes.byref(o), _stream()))
     return traces
@@ -189,13 +190,13 @@ def fd_misfit(traces, observed, dt, residual=None) -> float:
 
 
 def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k, grad=None,
-                           traces=None, acc_dtype=None, variant=0, timing=None):
+                           traces=None, acc_dtype=None, variant=0, timing=None, chunk=0):
     """(grad_c, J) of the memory-efficient method at factor ``k``."""
     acq = Acquisition(src, wavelet, rec)
     if grad is None:
         grad = torch.empty_like(c)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
-    o = make_opts(acc_dtype, variant, timing)
+    o = make_opts(acc_dtype, variant, timing, chunk)
     J = ctypes.c_double()
     _raise(_lib.fd_adjoint_sensitivity(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt),
                                        int(nt), _dev(observed, "observed"), float(k),
@@ -225,10 +226,10 @@ class SweepState:
 
 
 def fd_sens_forward(c, dx, order, src, wavelet, rec, dt, nt, observed, state: SweepState,
-                    traces=None, acc_dtype=None, variant=0, timing=None) -> float:
+                    traces=None, acc_dtype=None, variant=0, timing=None, chunk=0) -> float:
     acq = Acquisition(src, wavelet, rec)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
-    o = make_opts(acc_dtype, variant, timing)
+    o = make_opts(acc_dtype, variant, timing, chunk)
     st = state.c_struct()
     J = ctypes.c_double()
     _raise(_lib.fd_sens_forward(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt),
@@ -238,12 +239,12 @@ def fd_sens_forward(c, dx, order, src, wavelet, rec, dt, nt, observed, state: Sw
 
 
 def fd_sens_backward(c, dx, order, src, wavelet, rec, dt, nt, k, state: SweepState, grad_scale=1.0,
-                     grad=None, acc_dtype=None, variant=0, timing=None):
+                     grad=None, acc_dtype=None, variant=0, timing=None, chunk=0):
     acq = Acquisition(src, wavelet, rec)
     if grad is None:
         grad = torch.empty_like(c)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
-    o = make_opts(acc_dtype, variant, timing)
+    o = make_opts(acc_dtype, variant, timing, chunk)
     st = state.c_struct()
     _raise(_lib.fd_sens_backward(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt),
                                  float(k), ctypes.byref(st), float(grad_scale), _dev(grad, "grad"),
@@ -251,10 +252,10 @@ def fd_sens_backward(c, dx, order, src, wavelet, rec, dt, nt, k, state: SweepSta
     return grad
 
 
-def fd_propagate(coef, u_prev, u_cur, nsteps, dx, order, variant=0):
+def fd_propagate(coef, u_prev, u_cur, nsteps, dx, order, variant=0, chunk=0):
     """In place: (u_prev, u_cur) advance by ``nsteps`` source-free steps."""
     g = make_grid(coef.shape, dx, order, _dtype_code(coef))
-    o = make_opts(None, variant)
+    o = make_opts(None, variant, None, chunk)
     _raise(_lib.fd_propagate(ctypes.byref(g), _dev(coef, "coef"), _dev(u_prev, "u_prev"),
                              _dev(u_cur, "u_cur"), int(nsteps), ctypes.byref(o), _stream()))
     return u_prev, u_cur

@@ -216,20 +216,18 @@ def _layered_perturbed_torch(shape, seed, device, n_layers=8, c_lo=1.5, c_hi=4.5
 
 
 def _smooth_axis(p, ker, rad, ax):
-    """1D convolution of ``p`` along ``ax`` with reflecting padding, in slabs."""
+    """1D convolution of ``p`` along ``ax`` with reflecting edges (numpy's and
+    scipy's "reflect": the edge sample repeats), as a sum of shifted slices."""
     import torch
-    import torch.nn.functional as F
-    moved = p.movedim(ax, -1)
-    shp = moved.shape
-    flat2 = moved.reshape(-1, shp[-1])
-    out = torch.empty_like(flat2)
-    step = max(1, (1 << 26) // shp[-1])
-    w = ker.view(1, 1, -1)
-    for s in range(0, flat2.shape[0], step):
-        blk = flat2[s:s + step].unsqueeze(1)
-        blk = F.pad(blk, (rad, rad), mode="reflect")
-        out[s:s + step] = F.conv1d(blk, w).squeeze(1)
-    return out.view(shp).movedim(-1, ax).contiguous()
+    n = p.shape[ax]
+    idx = torch.arange(-rad, n + rad, device=p.device)
+    idx = torch.where(idx < 0, -1 - idx, idx)
+    idx = torch.where(idx >= n, 2 * n - 1 - idx, idx)
+    padded = torch.index_select(p, ax, idx)
+    out = torch.zeros_like(p)
+    for j in range(2 * rad + 1):
+        out.add_(padded.narrow(ax, j, n), alpha=float(ker[j]))
+    return out
 
 
 def small_random(shape, order: int = 8, nt: int = 60, dtype: str = "f32", seed: int = 0,

@@ -187,6 +187,41 @@ def test_variants_are_bitwise_identical(fdw):
             assert out[1] == ref[1]
 
 
+def test_chunking_is_bitwise_identical(fdw):
+    """The axis-0 chunk length (planes per block) changes only the decomposition."""
+    p = wl.small_random((37, 20, 70), order=8, nt=12, dtype="f32", seed=10)
+    case = OracleCase(p, k=0.05, exact=False)
+    dt_ = torch.float32
+    c, w, obs = to_dev(p.c, dt_), to_dev(p.wavelet, dt_), to_dev(case.obs, dt_)
+    ref = None
+    for chunk in (0, 1, 5, 16, 37, 1000):
+        say("chunk", chunk)
+        st = fdw.SweepState(c, p.nt, len(p.rec))
+        J = fdw.fd_sens_forward(c, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, obs, st,
+                                chunk=chunk)
+        g = fdw.fd_sens_backward(c, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, case.k, st,
+                                 chunk=chunk)
+        out = (J, g.cpu().numpy())
+        if ref is None:
+            ref = out
+            assert rel(out[1], case.g_approx) < 1e-4
+        else:
+            assert out[0] == ref[0] and np.array_equal(out[1], ref[1])
+
+
+def test_timing_record(fdw):
+    p = wl.small_random((16, 16, 64), order=8, nt=9, dtype="f32", seed=12)
+    dt_ = torch.float32
+    c, w = to_dev(p.c, dt_), to_dev(p.wavelet, dt_)
+    obs = torch.zeros((p.nt, len(p.rec)), dtype=dt_, device="cuda")
+    tf, tb = fdw.fd_timing(), fdw.fd_timing()
+    st = fdw.SweepState(c, p.nt, len(p.rec))
+    fdw.fd_sens_forward(c, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, obs, st, timing=tf)
+    fdw.fd_sens_backward(c, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, 0.1, st, timing=tb)
+    assert tf.fwd_launches == 9 and tb.bwd_launches == 8
+    assert tf.fwd_ms > 0 and tb.bwd_ms > 0
+
+
 def test_runs_are_deterministic(fdw):
     p = _layered_ragged()
     dt_ = torch.float32
