@@ -80,12 +80,20 @@ typedef struct fd_grid {
     int32_t dtype;      /* FD_F32 or FD_F64: element type of every field, wavelet and trace array */
 } fd_grid;
 
+/* Acquisition of one problem.  A batch of shots on the same medium is one acquisition
+ * whose sources and receivers carry shot numbers: each shot is its own wave field
+ * (driven by its own sources, recorded by its own receivers), J sums over all
+ * receivers and the gradient over all shots (one shared accumulator).  With nshot
+ * 0 or 1 there is one shot and the tag arrays are ignored. */
 typedef struct fd_acq {
     int32_t nsrc;             /* number of point sources, >= 0 */
     const int64_t* src_cell;  /* HOST [nsrc] flat cell of each source (repeats allowed) */
     const void* wavelet;      /* DEVICE [nt][nsrc] source time functions, row n at t = n dt */
     int32_t nrec;             /* number of receivers, >= 0 */
     const int64_t* rec_cell;  /* HOST [nrec] flat cell of each receiver (repeats allowed) */
+    int32_t nshot;            /* number of shots (0 or 1: a single shot) */
+    const int32_t* src_shot;  /* HOST [nsrc] shot of each source, in [0, nshot) */
+    const int32_t* rec_shot;  /* HOST [nrec] shot of each receiver, in [0, nshot) */
 } fd_acq;
 
 /* Optional timing record, filled by a call whose fd_opts.timing points here: HIP events
@@ -102,16 +110,32 @@ typedef struct fd_opts {
     int32_t variant;    /* kernel tile variant; 0 lets the library choose (see fd_variant_count) */
     fd_timing* timing;  /* HOST, may be NULL: when set, the call also synchronises `stream` */
     int32_t chunk;      /* planes of axis 0 marched per block; 0 lets the library choose */
+    int32_t max_group;  /* shots advanced per launch: 1, 2 or 4 (0: the largest the variant has) */
+    int32_t graph;      /* batched calls: 1 replays each sweep as one captured hipGraph */
 } fd_opts;
 
 /* Caller-owned device state that carries one gradient from its forward sweep
  * (fd_sens_forward) to its backward sweep (fd_sens_backward). */
 typedef struct fd_state {
-    void* u_a;       /* DEVICE [ncell] grid dtype */
-    void* u_b;       /* DEVICE [ncell] grid dtype */
+    void* u_a;       /* DEVICE [nshot][ncell] grid dtype */
+    void* u_b;       /* DEVICE [nshot][ncell] grid dtype */
     void* acc;       /* DEVICE [ncell] accumulator dtype: K(u,u) - K(v,v) in progress */
     void* residual;  /* DEVICE [nt][nrec] grid dtype: u^n(x_r) - obs^n_r */
 } fd_state;
+
+/* One independent problem of a batched call (its own medium, grid, acquisition, time
+ * axis and k).  All problems of one call share ndim, order and dtype. */
+typedef struct fd_problem {
+    fd_grid grid;
+    const void* c;          /* DEVICE [ncell] wave speed */
+    fd_acq acq;             /* single shot (nshot 0 or 1) */
+    double dt;
+    int32_t nt;
+    const void* observed;   /* DEVICE [nt][nrec] */
+    double k;
+    void* grad_c;           /* DEVICE [ncell] output dJ/dc */
+    void* traces;           /* DEVICE [nt][nrec] output, or NULL */
+} fd_problem;
 
 /* Message of the last failed call in this thread ("" if none). */
 const char* fd_last_error(void);
@@ -122,6 +146,13 @@ double fd_cfl_limit(int32_t ndim, int32_t order);
 
 /* Number of kernel tile variants for `ndim` (valid fd_opts.variant values are 1..count). */
 int32_t fd_variant_count(int32_t ndim);
+
+/* Shape of tile variant `variant` (1..count) for `ndim`: tile width along the contiguous
+ * axis and height along axis 1 in cells, threads per block, and cells per lane along the
+ * contiguous axis (a variant runs only on grids whose contiguous extent is a multiple of
+ * it).  Any output pointer may be NULL.  Returns FD_OK or FD_E_ARG. */
+int fd_variant_info(int32_t ndim, int32_t variant, int32_t* tile_z, int32_t* tile_y,
+                    int32_t* threads, int32_t* cells_per_lane);
 
 /* Forward solve (Alg. 1 forward loop without cost or kernel): traces DEVICE [nt][nrec]
  * receive u^1..u^nt at the receivers.  c DEVICE [ncell] is the wave speed. */
@@ -155,6 +186,14 @@ int fd_sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, doubl
 int fd_sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
                      int32_t nt, double k, const fd_state* state, double grad_scale,
                      void* grad_c, const fd_opts* opts, void* stream);
+
+/* Alg. 1 for `nprob` independent problems of uneven sizes in lock-step: every time
+ * step of all problems is one launch over the union of their tiles (problems that
+ * have no step there skip it), the backward sweeps are aligned at their ends, and
+ * with opts->graph each sweep is captured once into a hipGraph and replayed as one
+ * launch.  J_host [nprob] receives each problem's J.  Needs opts variant 0, 1 or 2. */
+int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, double* J_host,
+                                   const fd_opts* opts, void* stream);
 
 /* Source-free steps (test hook for closed-form solutions): on entry u_prev, u_cur DEVICE
  * [ncell] hold levels -1 and 0; on return they hold levels nsteps-1 and nsteps.

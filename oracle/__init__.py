@@ -138,6 +138,8 @@ def _load():
         lib.orc_exact_gradient.restype = I
         lib.orc_superposition.argtypes = grid + [P, D, I, I, P, P, I, P, P, D, P, P, P]
         lib.orc_superposition.restype = I
+        lib.orc_exact_gradient_ckpt.argtypes = grid + [P, D, I, I, P, P, I, P, P, I, P, P, P, P]
+        lib.orc_exact_gradient_ckpt.restype = I
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = I
         _lib = lib
@@ -259,6 +261,29 @@ def exact_gradient(c, dx, order, dt, nt, src, wavelet, rec, observed):
                                       observed.ctypes.data, grad.ctypes.data,
                                       ctypes.addressof(J), s2.ctypes.data, traces.ctypes.data),
            "exact_gradient")
+    return grad, J.value, s2, traces
+
+
+def exact_gradient_ckpt(c, dx, order, dt, nt, src, wavelet, rec, observed, seg=None):
+    """``exact_gradient`` with uniform checkpoints every ``seg`` levels instead of the
+    stored history (default seg ~ sqrt(nt)).  Returns ``(grad_c, J, sum_dmu2, traces)``."""
+    c = _f64(c)
+    src, rec = _i64(src), _i64(rec)
+    wavelet = _f64(np.asarray(wavelet).reshape(nt, len(src)))
+    observed = _f64(np.asarray(observed).reshape(nt, len(rec)))
+    if seg is None:
+        seg = max(1, int(round(np.sqrt(nt))))
+    grad = np.empty_like(c)
+    s2 = np.empty_like(c)
+    traces = np.empty((nt, len(rec)))
+    J = ctypes.c_double()
+    g, keep = _grid_args(c.shape, dx, order)
+    _check(_load().orc_exact_gradient_ckpt(*g, c.ctypes.data, float(dt), int(nt), len(src),
+                                           _ptr(src), wavelet.ctypes.data, len(rec), _ptr(rec),
+                                           observed.ctypes.data, int(seg), grad.ctypes.data,
+                                           ctypes.addressof(J), s2.ctypes.data,
+                                           traces.ctypes.data),
+           "exact_gradient_ckpt")
     return grad, J.value, s2, traces
 
 

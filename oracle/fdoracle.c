@@ -291,6 +291,97 @@ int orc_exact_gradient(int ndim, const long* shape, double dx, int r, const doub
     return rc;
 }
 
+/* The exact discrete adjoint gradient of orc_exact_gradient with the forward
+ * history replaced by checkpoints: the pair (u^{a-1}, u^a) is kept every `seg`
+ * levels, and each segment of levels a..b is recomputed from its checkpoint
+ * just before the backward sweep crosses it (uniform checkpointing, one extra
+ * forward solve).  Same outputs; memory ~ (2 nt/seg + seg) grids. */
+int orc_exact_gradient_ckpt(int ndim, const long* shape, double dx, int r, const double* a,
+                            const double* c, double dt, int nt,
+                            int nsrc, const long* src, const double* wavelet,
+                            int nrec, const long* rec, const double* obs, int seg,
+                            double* grad_c, double* J, double* sum_dmu2, double* traces_out)
+{
+    grid_t g;
+    if (make_grid(&g, ndim, shape, dx, r, a) || nt < 1 || seg < 1) return -1;
+    const long N = g.ncell;
+    const double vol = inv_cell_volume(&g);
+    const int nck = (nt + seg - 1) / seg;          /* checkpoints at a = 0, seg, 2 seg, ... */
+    double* coef = coef_from_speed(&g, c, dt);
+    double* ck = malloc(sizeof(double) * (size_t)nck * 2 * N);
+    double* sg = malloc(sizeof(double) * (size_t)(seg + 1) * N);   /* levels a..b */
+    double* um = calloc(N, sizeof(double));
+    double* u0 = calloc(N, sizeof(double));
+    double* up = calloc(N, sizeof(double));
+    double* fdag = malloc(sizeof(double) * (size_t)nt * nrec);
+    double* tr = malloc(sizeof(double) * (size_t)nt * nrec);
+    double* gm = calloc(N, sizeof(double));
+    double* s2 = calloc(N, sizeof(double));
+    if (!coef || !ck || !sg || !um || !u0 || !up || !fdag || !tr || !gm || !s2) {
+        free(coef); free(ck); free(sg); free(um); free(u0); free(up); free(fdag); free(tr);
+        free(gm); free(s2);
+        return -2;
+    }
+    /* forward solve, keeping checkpoints and the traces */
+    for (int n = 0; n < nt; ++n) {
+        if (n % seg == 0) {
+            memcpy(ck + (size_t)(n / seg) * 2 * N, um, sizeof(double) * N);
+            memcpy(ck + (size_t)(n / seg) * 2 * N + N, u0, sizeof(double) * N);
+        }
+        propagate_step(&g, coef, um, u0, up);
+        add_point_forces(coef, up, nsrc, src, wavelet + (long)n * nsrc, vol);
+        for (int q = 0; q < nrec; ++q) tr[(long)n * nrec + q] = up[rec[q]];
+        double* t = um; um = u0; u0 = up; up = t;
+    }
+    double Jv = orc_misfit(nt, nrec, dt, tr, obs, fdag);
+    for (long i = 0; i < (long)nt * nrec; ++i) fdag[i] = -fdag[i] / dt;
+
+    /* backward sweep segment by segment: mu^{j-1} from mu^j, mu^{j+1} */
+    double* mp = um; double* m0 = u0; double* mm = up;   /* reuse the three grids */
+    memset(mp, 0, sizeof(double) * N);
+    memset(m0, 0, sizeof(double) * N);
+    for (int s = nck - 1; s >= 0; --s) {
+        const int lo = s * seg;
+        const int hi = lo + seg < nt ? lo + seg : nt;
+        /* recompute levels lo..hi from the checkpoint (u^{lo-1}, u^lo) */
+        double* wm = malloc(sizeof(double) * N);
+        if (!wm) { Jv = NAN; break; }
+        memcpy(wm, ck + (size_t)s * 2 * N, sizeof(double) * N);
+        memcpy(sg, ck + (size_t)s * 2 * N + N, sizeof(double) * N);
+        for (int n = lo; n < hi; ++n) {
+            double* cur = sg + (size_t)(n - lo) * N;
+            double* nxt = sg + (size_t)(n - lo + 1) * N;
+            const double* prv = n == lo ? wm : sg + (size_t)(n - lo - 1) * N;
+            propagate_step(&g, coef, prv, cur, nxt);
+            add_point_forces(coef, nxt, nsrc, src, wavelet + (long)n * nsrc, vol);
+        }
+        free(wm);
+        for (int j = hi; j > lo; --j) {
+            propagate_step(&g, coef, mp, m0, mm);
+            add_point_forces(coef, mm, nrec, rec, fdag + (long)(j - 1) * nrec, 1.0);
+            const double* uj = sg + (size_t)(j - lo) * N;
+            const double* uj1 = sg + (size_t)(j - 1 - lo) * N;
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < N; ++i) {
+                double du = uj[i] - uj1[i];
+                double dm = m0[i] - mm[i];    /* mu^j - mu^{j-1} */
+                gm[i] -= dm * du;
+                s2[i] += dm * dm;
+            }
+            double* t = mp; mp = m0; m0 = mm; mm = t;
+        }
+    }
+    for (long i = 0; i < N; ++i) {
+        grad_c[i] = -2.0 / (c[i] * c[i] * c[i]) * gm[i];
+        if (sum_dmu2) sum_dmu2[i] = s2[i];
+    }
+    if (J) *J = Jv;
+    if (traces_out) memcpy(traces_out, tr, sizeof(double) * (size_t)nt * nrec);
+    free(coef); free(ck); free(sg); free(um); free(u0); free(up); free(fdag); free(tr);
+    free(gm); free(s2);
+    return isnan(Jv) ? -2 : 0;
+}
+
 /* Memory-efficient mixed-kernel computation, paper Alg. 1, in the paper's
  * order: forward solve with adjoint force, cost and kernel increments; scale
  * the stored adjoint forces by k; superposed solve backwards in time with

@@ -1,6 +1,8 @@
 // fdwave C-ABI: argument validation, CFL check, block plans, device scratch and the
 // time loops of the paper's Algorithm 1 (forward sweep, terminal hand-over,
-// superposed backward sweep, finalisation).  Kernels live in fdw_kernels.hip.
+// superposed backward sweep, finalisation), for one problem with one or more shots
+// and for batches of independent problems.  Kernels live in fdw_step.hip and
+// fdw_kernels.hip.
 
 #include <hip/hip_runtime.h>
 
@@ -68,6 +70,8 @@ struct Geo {
     fd_timing* timing = nullptr;
     int ndim, r, dtype, acc_dtype, variant;
     int chunk = 0;       // requested planes per block (0: library choice)
+    int max_group = 0;   // requested shots per launch (0: the variant's largest)
+    int graph = 0;
     int n0, n1, n2;      // internal extents (2D: n1 = 1)
     int64_t ncell;
     double dx, inv_vol;
@@ -92,7 +96,7 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
     G.r = r;
     G.dtype = g->dtype;
     G.acc_dtype = FD_F64;
-    G.variant = g->ndim == 3 ? 3 : 1;   // measured best default tile (64 x 8 in 3D)
+    G.variant = 1;   // one cell per lane: valid for every extent
     if (o) {
         if (o->acc_dtype != FD_F32 && o->acc_dtype != FD_F64)
             return fail(FD_E_ARG, "acc_dtype must be FD_F32 or FD_F64");
@@ -105,6 +109,10 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
         G.timing = o->timing;
         if (o->chunk < 0) return fail(FD_E_ARG, "chunk is negative");
         G.chunk = o->chunk;
+        if (o->max_group != 0 && o->max_group != 1 && o->max_group != 2 && o->max_group != 4)
+            return fail(FD_E_ARG, "max_group must be 0, 1, 2 or 4");
+        G.max_group = o->max_group;
+        G.graph = o->graph;
     }
     if (G.dtype == FD_F64) G.acc_dtype = FD_F64;
     G.n0 = (int)n[0];
@@ -127,15 +135,33 @@ int check_cells(int count, const int64_t* cells, int64_t ncell, const char* what
     return FD_OK;
 }
 
+int nshots(const fd_acq* a) { return a->nshot > 1 ? a->nshot : 1; }
+
+int check_tags(int count, const int32_t* tags, int nshot, const char* what)
+{
+    if (nshot <= 1 || count == 0) return FD_OK;
+    if (!tags) return fail(FD_E_ARG, std::string(what) + " shot tags are null");
+    for (int i = 0; i < count; ++i)
+        if (tags[i] < 0 || tags[i] >= nshot)
+            return fail(FD_E_ARG, std::string(what) + " " + std::to_string(i) + " has a shot out of range");
+    return FD_OK;
+}
+
 int check_acq(const fd_acq* a, const Geo& G, int nt)
 {
     if (!a) return fail(FD_E_ARG, "acq is null");
+    if (a->nshot < 0) return fail(FD_E_ARG, "nshot is negative");
     int rc = check_cells(a->nsrc, a->src_cell, G.ncell, "source");
     if (rc) return rc;
     rc = check_cells(a->nrec, a->rec_cell, G.ncell, "receiver");
     if (rc) return rc;
+    if ((rc = check_tags(a->nsrc, a->src_shot, a->nshot, "source"))) return rc;
+    if ((rc = check_tags(a->nrec, a->rec_shot, a->nshot, "receiver"))) return rc;
     return check_dev(a->wavelet, (size_t)nt * a->nsrc * dsize(G.dtype), "wavelet");
 }
+
+int src_shot(const fd_acq* a, int i) { return a->nshot > 1 ? a->src_shot[i] : 0; }
+int rec_shot(const fd_acq* a, int i) { return a->nshot > 1 ? a->rec_shot[i] : 0; }
 
 // Device scratch taken stream-ordered and released at scope exit.
 struct Scratch {
@@ -156,65 +182,78 @@ struct Scratch {
     }
 };
 
-// Host statistics of the speed field: max, min, non-finite count.
-int speed_stats(const Geo& G, const void* c, hipStream_t s, Scratch& sc, double* cmax, double* cmin)
-{
-    void* part = nullptr;
-    void* out = nullptr;
-    HIPCHK(sc.get(&part, sizeof(double) * 3 * fdw::kReduceBlocks));
-    HIPCHK(sc.get(&out, sizeof(double) * 3));
-    HIPCHK(fdw::launch_speed_stats(G.dtype, c, G.ncell, (double*)out, (double*)part, s));
-    double h[3];
-    HIPCHK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (h[2] > 0) return fail(FD_E_NONFINITE, "speed field has non-finite entries");
-    if (!(h[1] > 0.0)) return fail(FD_E_NONFINITE, "speed field must be positive");
-    *cmax = h[0];
-    *cmin = h[1];
-    return FD_OK;
-}
-
 double cfl_limit(int ndim, int order)
 {
     const double* a = weights(order);
     if (!a || (ndim < 1 || ndim > 3)) return 0.0;
     const int r = order / 2;
-    double a0 = 0.0, sym = 0.0;
+    double a0 = 0.0;
     for (int j = 1; j <= r; ++j) a0 -= 2.0 * a[j - 1];
-    sym = a0;
+    double sym = a0;
     for (int j = 1; j <= r; ++j) sym += 2.0 * a[j - 1] * ((j & 1) ? -1.0 : 1.0);
     return 2.0 / std::sqrt(ndim * std::fabs(sym));
 }
 
-int check_cfl(const Geo& G, double cmax, double dt)
+// Speed statistics of several fields with one synchronisation: each gets max, min and
+// a non-finite count; then the positivity, finiteness and CFL checks.
+int check_speeds(const std::vector<const Geo*>& geos, const std::vector<const void*>& cs,
+                 const std::vector<double>& dts, hipStream_t s, Scratch& sc)
 {
-    const double courant = cmax * dt / G.dx;
-    const double lim = cfl_limit(G.ndim, 2 * G.r);
-    if (courant > lim * (1.0 + 1e-12)) {
-        char buf[160];
-        snprintf(buf, sizeof buf, "Courant number %.6g exceeds the stability limit %.6g", courant, lim);
-        return fail(FD_E_CFL, buf);
+    const size_t m = geos.size();
+    void* part = nullptr;
+    void* out = nullptr;
+    HIPCHK(sc.get(&part, sizeof(double) * 3 * fdw::kReduceBlocks));
+    HIPCHK(sc.get(&out, sizeof(double) * 3 * m));
+    std::vector<double> h(3 * m);
+    for (size_t i = 0; i < m; ++i)
+        HIPCHK(fdw::launch_speed_stats(geos[i]->dtype, cs[i], geos[i]->ncell, (double*)out + 3 * i,
+                                       (double*)part, s));
+    HIPCHK(hipMemcpyAsync(h.data(), out, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (size_t i = 0; i < m; ++i) {
+        const std::string who = m > 1 ? "problem " + std::to_string(i) + ": " : "";
+        if (h[3 * i + 2] > 0) return fail(FD_E_NONFINITE, who + "speed field has non-finite entries");
+        if (!(h[3 * i + 1] > 0.0)) return fail(FD_E_NONFINITE, who + "speed field must be positive");
+        const Geo& G = *geos[i];
+        const double courant = h[3 * i] * dts[i] / G.dx;
+        const double lim = cfl_limit(G.ndim, 2 * G.r);
+        if (courant > lim * (1.0 + 1e-12)) {
+            char buf[200];
+            snprintf(buf, sizeof buf, "%sCourant number %.6g exceeds the stability limit %.6g",
+                     who.c_str(), courant, lim);
+            return fail(FD_E_CFL, buf);
+        }
     }
     return FD_OK;
 }
 
-// Block decomposition plus the per-block event lists of sources and receivers.
-struct Plan {
-    fdw::Variant v;
-    int nty, ntz, nch, chunk, nblk;
+// One shot group of a plan: shots [g0, g0 + size) and their events.
+struct Group {
+    int g0 = 0, size = 1;
     int32_t* d_off = nullptr;
     fdw::Event* d_ev = nullptr;
-    // distinct receiver cells (terminal hand-over)
+};
+
+// Block decomposition, shot groups with their per-block event lists, and the distinct
+// receiver cells (terminal hand-over).
+struct Plan {
+    fdw::Variant v;
+    int nty = 0, ntz = 0, nch = 0, chunk = 0, nblk = 0;
+    std::vector<Group> groups;
     int nuniq = 0;
     int64_t* d_ucell = nullptr;
     int32_t* d_uoff = nullptr;
     int32_t* d_uidx = nullptr;
+    int32_t* d_ushot = nullptr;
 };
 
 int make_plan(const Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch& sc, Plan* P)
 {
     fdw::Variant v = fdw::variant_shape(G.ndim, G.variant);
     if (v.tz == 0) return fail(FD_E_ARG, "invalid variant");
+    if (G.n2 % v.vz != 0)
+        return fail(FD_E_ARG, "variant " + std::to_string(G.variant) +
+                                  " needs the contiguous extent to be a multiple of " + std::to_string(v.vz));
     P->v = v;
     P->ntz = (G.n2 + v.tz - 1) / v.tz;
     P->nty = (G.n1 + v.ty - 1) / v.ty;
@@ -237,70 +276,98 @@ int make_plan(const Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Sc
     if (nblk > (1 << 28)) return fail(FD_E_ARG, "grid too large for the block decomposition");
     P->nblk = (int)nblk;
 
-    struct Item { int64_t key; fdw::Event e; };
-    std::vector<Item> items;
+    // shot groups: sizes 4, 2, 1 up to the variant's (and the caller's) largest
+    const int ns = acq ? nshots(acq) : 1;
+    int gmax = v.max_shots;
+    if (G.max_group > 0) gmax = std::min(gmax, G.max_group);
+    for (int g0 = 0; g0 < ns;) {
+        int sz = 4;
+        while (sz > gmax || g0 + sz > ns) sz >>= 1;
+        Group gr;
+        gr.g0 = g0;
+        gr.size = sz;
+        P->groups.push_back(gr);
+        g0 += sz;
+    }
+
     const int nsrc = acq ? acq->nsrc : 0;
     const int nrec = acq ? acq->nrec : 0;
-    items.reserve(nsrc + nrec);
-    auto add = [&](int64_t cell, int kind, int idx) {
-        const int64_t plane = (int64_t)G.n1 * G.n2;
-        const int x = (int)(cell / plane);
-        const int64_t rem = cell - (int64_t)x * plane;
-        const int y = (int)(rem / G.n2);
-        const int z = (int)(rem - (int64_t)y * G.n2);
-        const int ty = y / v.ty, tz = z / v.tz, ch = x / P->chunk;
-        const int64_t b = ((int64_t)ch * P->nty + ty) * P->ntz + tz;
-        fdw::Event e;
-        e.plane = x;
-        e.lane = (y - ty * v.ty) * v.tz + (z - tz * v.tz);
-        e.kind = kind;
-        e.idx = idx;
-        items.push_back({b, e});
-    };
-    for (int i = 0; i < nsrc; ++i) add(acq->src_cell[i], fdw::EV_SRC, i);
-    for (int i = 0; i < nrec; ++i) add(acq->rec_cell[i], fdw::EV_REC, i);
-    std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
-        if (a.key != b.key) return a.key < b.key;
-        if (a.e.plane != b.e.plane) return a.e.plane < b.e.plane;
-        if (a.e.lane != b.e.lane) return a.e.lane < b.e.lane;
-        if (a.e.kind != b.e.kind) return a.e.kind < b.e.kind;
-        return a.e.idx < b.e.idx;
-    });
-    std::vector<int32_t> off(P->nblk + 1, 0);
-    std::vector<fdw::Event> ev(items.size());
-    for (size_t i = 0; i < items.size(); ++i) {
-        off[items[i].key + 1]++;
-        ev[i] = items[i].e;
+    std::vector<std::vector<int32_t>> offs;
+    std::vector<std::vector<fdw::Event>> evs;
+    for (Group& gr : P->groups) {
+        struct Item { int64_t key; fdw::Event e; };
+        std::vector<Item> items;
+        auto add = [&](int64_t cell, int kind, int idx, int shot) {
+            if (shot < gr.g0 || shot >= gr.g0 + gr.size) return;
+            const int64_t plane = (int64_t)G.n1 * G.n2;
+            const int x = (int)(cell / plane);
+            const int64_t rem = cell - (int64_t)x * plane;
+            const int y = (int)(rem / G.n2);
+            const int z = (int)(rem - (int64_t)y * G.n2);
+            const int ty = y / v.ty, tz = z / v.tz, ch = x / P->chunk;
+            const int64_t b = ((int64_t)ch * P->nty + ty) * P->ntz + tz;
+            fdw::Event e;
+            e.plane = x;
+            e.lane = (y - ty * v.ty) * v.tz + (z - tz * v.tz);
+            e.kind = kind | ((shot - gr.g0) << 1);
+            e.idx = idx;
+            items.push_back({b, e});
+        };
+        for (int i = 0; i < nsrc; ++i) add(acq->src_cell[i], fdw::EV_SRC, i, src_shot(acq, i));
+        for (int i = 0; i < nrec; ++i) add(acq->rec_cell[i], fdw::EV_REC, i, rec_shot(acq, i));
+        std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+            if (a.key != b.key) return a.key < b.key;
+            if (a.e.plane != b.e.plane) return a.e.plane < b.e.plane;
+            if (a.e.lane != b.e.lane) return a.e.lane < b.e.lane;
+            if (a.e.kind != b.e.kind) return a.e.kind < b.e.kind;
+            return a.e.idx < b.e.idx;
+        });
+        std::vector<int32_t> off(P->nblk + 1, 0);
+        std::vector<fdw::Event> ev(items.size());
+        for (size_t i = 0; i < items.size(); ++i) {
+            off[items[i].key + 1]++;
+            ev[i] = items[i].e;
+        }
+        for (int b = 0; b < P->nblk; ++b) off[b + 1] += off[b];
+        HIPCHK(sc.get((void**)&gr.d_off, sizeof(int32_t) * off.size()));
+        HIPCHK(sc.get((void**)&gr.d_ev, sizeof(fdw::Event) * std::max<size_t>(1, ev.size())));
+        HIPCHK(hipMemcpyAsync(gr.d_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, s));
+        if (!ev.empty())
+            HIPCHK(hipMemcpyAsync(gr.d_ev, ev.data(), sizeof(fdw::Event) * ev.size(), hipMemcpyHostToDevice, s));
+        offs.push_back(std::move(off));
+        evs.push_back(std::move(ev));
     }
-    for (int b = 0; b < P->nblk; ++b) off[b + 1] += off[b];
 
-    HIPCHK(sc.get((void**)&P->d_off, sizeof(int32_t) * off.size()));
-    HIPCHK(sc.get((void**)&P->d_ev, sizeof(fdw::Event) * std::max<size_t>(1, ev.size())));
-    HIPCHK(hipMemcpyAsync(P->d_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, s));
-    if (!ev.empty())
-        HIPCHK(hipMemcpyAsync(P->d_ev, ev.data(), sizeof(fdw::Event) * ev.size(), hipMemcpyHostToDevice, s));
-
+    std::vector<int64_t> ucell;
+    std::vector<int32_t> uoff, uidx, ushot;
     if (want_uniq && nrec > 0) {
-        std::vector<std::pair<int64_t, int32_t>> rc(nrec);
-        for (int i = 0; i < nrec; ++i) rc[i] = {acq->rec_cell[i], i};
-        std::sort(rc.begin(), rc.end());
-        std::vector<int64_t> ucell;
-        std::vector<int32_t> uoff{0}, uidx(nrec);
+        struct R { int64_t cell; int32_t shot, idx; };
+        std::vector<R> rc(nrec);
+        for (int i = 0; i < nrec; ++i) rc[i] = {acq->rec_cell[i], rec_shot(acq, i), i};
+        std::sort(rc.begin(), rc.end(), [](const R& a, const R& b) {
+            if (a.cell != b.cell) return a.cell < b.cell;
+            if (a.shot != b.shot) return a.shot < b.shot;
+            return a.idx < b.idx;
+        });
+        uoff.push_back(0);
         for (int i = 0; i < nrec; ++i) {
-            if (i == 0 || rc[i].first != rc[i - 1].first) {
+            if (i == 0 || rc[i].cell != rc[i - 1].cell) {
                 if (i) uoff.push_back(i);
-                ucell.push_back(rc[i].first);
+                ucell.push_back(rc[i].cell);
             }
-            uidx[i] = rc[i].second;
+            uidx.push_back(rc[i].idx);
+            ushot.push_back(rc[i].shot);
         }
         uoff.push_back(nrec);
         P->nuniq = (int)ucell.size();
         HIPCHK(sc.get((void**)&P->d_ucell, sizeof(int64_t) * ucell.size()));
         HIPCHK(sc.get((void**)&P->d_uoff, sizeof(int32_t) * uoff.size()));
         HIPCHK(sc.get((void**)&P->d_uidx, sizeof(int32_t) * uidx.size()));
+        HIPCHK(sc.get((void**)&P->d_ushot, sizeof(int32_t) * ushot.size()));
         HIPCHK(hipMemcpyAsync(P->d_ucell, ucell.data(), sizeof(int64_t) * ucell.size(), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(P->d_uoff, uoff.data(), sizeof(int32_t) * uoff.size(), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(P->d_uidx, uidx.data(), sizeof(int32_t) * uidx.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(P->d_ushot, ushot.data(), sizeof(int32_t) * ushot.size(), hipMemcpyHostToDevice, s));
     }
     // the host vectors die with this frame: finish the copies first
     HIPCHK(hipStreamSynchronize(s));
@@ -312,20 +379,22 @@ fdw::StepArgs base_args(const Geo& G, const Plan& P, const void* c, double dt)
     fdw::StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.c = c;
+    a.shot_stride = G.ncell;
     a.n0 = G.n0; a.n1 = G.n1; a.n2 = G.n2;
     const double* w = weights(2 * G.r);
     for (int j = 0; j < G.r; ++j) a.w[j] = w[j] / (G.dx * G.dx);
     a.dt2 = dt * dt;
     a.inv_vol = G.inv_vol;
-    a.blk_off = P.d_off;
-    a.ev = P.d_ev;
+    a.active = 1;
     a.nty = P.nty; a.ntz = P.ntz; a.chunk_len = P.chunk; a.nblk = P.nblk;
     return a;
 }
 
-int step(const Geo& G, const Plan& P, const fdw::StepArgs& a, hipStream_t s)
+int step(const Geo& G, const Plan& P, const Group& gr, fdw::StepArgs a, hipStream_t s)
 {
-    HIPCHK(fdw::launch_step(G.ndim, G.r, G.dtype, G.acc_dtype, G.variant, P.nblk, a, s));
+    a.blk_off = gr.d_off;
+    a.ev = gr.d_ev;
+    HIPCHK(fdw::launch_step(G.ndim, G.r, G.dtype, G.acc_dtype, G.variant, gr.size, P.nblk, a, s));
     return FD_OK;
 }
 
@@ -372,18 +441,18 @@ int prepare(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, in
     if ((rc = check_acq(acq, *G, nt))) return rc;
     if ((rc = check_dev(c, G->ncell * dsize(G->dtype), "c"))) return rc;
     if (stats) {
-        double cmax, cmin;
-        if ((rc = speed_stats(*G, c, s, sc, &cmax, &cmin))) return rc;
-        if ((rc = check_cfl(*G, cmax, dt))) return rc;
+        if ((rc = check_speeds({G}, {c}, {dt}, s, sc))) return rc;
     }
     return FD_OK;
 }
 
+// Forward sweep of every shot group (Alg. 1 forward loop); the wavefields of shot s
+// live at ua/ub + s * ncell.  `acc` null: no kernel accumulation (plain forward).
 int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
                   const void* obs, void* ua, void* ub, void* acc, void* resid, void* traces,
                   hipStream_t s)
 {
-    const size_t fb = G.ncell * dsize(G.dtype);
+    const size_t fb = G.ncell * dsize(G.dtype) * nshots(acq);
     HIPCHK(hipMemsetAsync(ua, 0, fb, s));
     HIPCHK(hipMemsetAsync(ub, 0, fb, s));
     if (acc) HIPCHK(hipMemsetAsync(acc, 0, G.ncell * dsize(G.acc_dtype), s));
@@ -396,24 +465,27 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
     a.resid = resid;
     a.obs = obs;
     a.nrec = acq->nrec;
-    void* prev = ua;   // level n-1
-    void* cur = ub;    // level n
+    const size_t es = dsize(G.dtype);
     SweepTimer tm(G.timing != nullptr, s);
     tm.start();
-    for (int n = 0; n < nt; ++n) {
-        a.ucur = cur;
-        a.unew = prev;
-        a.acc_sign = (acc && n < nt - 1) ? 1 : 0;   // the last interval is settled at hand-over
-        a.row_src = n;
-        a.row_rec = n;
-        int rc = step(G, P, a, s);
-        if (rc) return rc;
-        std::swap(prev, cur);
+    for (const Group& gr : P.groups) {
+        char* prev = (char*)ua + (size_t)gr.g0 * G.ncell * es;   // level n-1
+        char* cur = (char*)ub + (size_t)gr.g0 * G.ncell * es;    // level n
+        for (int n = 0; n < nt; ++n) {
+            a.ucur = cur;
+            a.unew = prev;
+            a.acc_sign = (acc && n < nt - 1) ? 1 : 0;   // the last interval is settled at hand-over
+            a.row_src = n;
+            a.row_rec = n;
+            int rc = step(G, P, gr, a, s);
+            if (rc) return rc;
+            std::swap(prev, cur);
+        }
     }
     tm.stop();
     if (G.timing) {
         G.timing->fwd_ms = tm.ms();
-        G.timing->fwd_launches = nt;
+        G.timing->fwd_launches = nt * (int)P.groups.size();
     }
     return FD_OK;
 }
@@ -432,11 +504,7 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
     void* ul = nullptr;   // u^nt = v^nt
     final_levels(ua, ub, nt, &up, &ul);
     const double rec_scale = -k / dt;   // k fdag^n = -(k/dt) residual^n
-    if (acq->nrec > 0)
-        HIPCHK(fdw::launch_terminal(G.dtype, G.acc_dtype, P.nuniq, P.d_ucell, P.d_uoff, P.d_uidx, c,
-                                    dt * dt, ul, up, acc,
-                                    (const char*)resid + (size_t)(nt - 1) * acq->nrec * dsize(G.dtype),
-                                    rec_scale, s));
+    const size_t es = dsize(G.dtype);
     fdw::StepArgs a = base_args(G, P, c, dt);
     a.acc = acc;
     a.acc_sign = -1;
@@ -446,23 +514,31 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
     a.resid = resid;
     a.nrec = acq->nrec;
     a.rec_scale = rec_scale;
-    void* vj = up;    // v^j
-    void* vn = ul;    // v^{j+1}, overwritten by v^{j-1}
     SweepTimer tm(G.timing != nullptr && nt > 1, s);
-    tm.start();
-    for (int j = nt - 1; j >= 1; --j) {
-        a.ucur = vj;
-        a.unew = vn;
-        a.row_src = j;
-        a.row_rec = j - 1;
-        int rc = step(G, P, a, s);
-        if (rc) return rc;
-        std::swap(vj, vn);
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+        const Group& gr = P.groups[gi];
+        char* vj = (char*)up + (size_t)gr.g0 * G.ncell * es;   // v^j
+        char* vn = (char*)ul + (size_t)gr.g0 * G.ncell * es;   // v^{j+1}, overwritten by v^{j-1}
+        if (acq->nrec > 0)
+            HIPCHK(fdw::launch_terminal(G.dtype, G.acc_dtype, P.nuniq, P.d_ucell, P.d_uoff, P.d_uidx,
+                                        P.d_ushot, gr.g0, gr.size, G.ncell, c, dt * dt, vn, vj, acc,
+                                        (const char*)resid + (size_t)(nt - 1) * acq->nrec * es,
+                                        rec_scale, s));
+        if (gi == 0) tm.start();
+        for (int j = nt - 1; j >= 1; --j) {
+            a.ucur = vj;
+            a.unew = vn;
+            a.row_src = j;
+            a.row_rec = j - 1;
+            int rc = step(G, P, gr, a, s);
+            if (rc) return rc;
+            std::swap(vj, vn);
+        }
     }
     tm.stop();
     if (G.timing) {
         G.timing->bwd_ms = tm.ms();
-        G.timing->bwd_launches = nt - 1;
+        G.timing->bwd_launches = (nt - 1) * (int)P.groups.size();
     }
     return FD_OK;
 }
@@ -480,15 +556,15 @@ int misfit_sum(int dtype, const void* x, const void* y, void* diff, int64_t n, h
     return FD_OK;
 }
 
-int check_state(const fd_state* st, const Geo& G, int nt, int nrec)
+int check_state(const fd_state* st, const Geo& G, int nt, const fd_acq* acq)
 {
     if (!st) return fail(FD_E_ARG, "state is null");
-    const size_t fb = G.ncell * dsize(G.dtype);
+    const size_t fb = G.ncell * dsize(G.dtype) * nshots(acq);
     int rc;
     if ((rc = check_dev(st->u_a, fb, "state.u_a"))) return rc;
     if ((rc = check_dev(st->u_b, fb, "state.u_b"))) return rc;
     if ((rc = check_dev(st->acc, G.ncell * dsize(G.acc_dtype), "state.acc"))) return rc;
-    if ((rc = check_dev(st->residual, (size_t)nt * nrec * dsize(G.dtype), "state.residual"))) return rc;
+    if ((rc = check_dev(st->residual, (size_t)nt * acq->nrec * dsize(G.dtype), "state.residual"))) return rc;
     return FD_OK;
 }
 
@@ -501,7 +577,7 @@ int sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double d
     Geo G;
     int rc = prepare(grid, c, acq, dt, nt, opts, s, sc, &G, true);
     if (rc) return rc;
-    if (!own_state && (rc = check_state(st, G, nt, acq->nrec))) return rc;
+    if (!own_state && (rc = check_state(st, G, nt, acq))) return rc;
     const size_t tb = (size_t)nt * acq->nrec * dsize(G.dtype);
     if ((rc = check_dev(observed, tb, "observed"))) return rc;
     if (traces && (rc = check_dev(traces, tb, "traces"))) return rc;
@@ -530,13 +606,216 @@ int sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double 
     if (rc) return rc;
     if (!(k != 0.0) || !std::isfinite(k)) return fail(FD_E_ARG, "k must be finite and non-zero");
     if (!std::isfinite(grad_scale)) return fail(FD_E_ARG, "grad_scale must be finite");
-    if (!own_state && (rc = check_state(st, G, nt, acq->nrec))) return rc;
+    if (!own_state && (rc = check_state(st, G, nt, acq))) return rc;
     if ((rc = check_dev(grad, G.ncell * dsize(G.dtype), "grad_c"))) return rc;
     Plan P;
     if ((rc = make_plan(G, acq, true, s, sc, &P))) return rc;
     if ((rc = backward_sweep(G, P, c, acq, dt, nt, k, st->u_a, st->u_b, st->acc, st->residual, s)))
         return rc;
     HIPCHK(fdw::launch_finalize(G.dtype, G.acc_dtype, G.ncell, st->acc, c, grad_scale / k, grad, s));
+    return FD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent problems
+// ---------------------------------------------------------------------------
+
+int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* opts, hipStream_t s)
+{
+    if (!probs || nprob < 1) return fail(FD_E_ARG, "need at least one problem");
+    if (!J_host) return fail(FD_E_ARG, "J_host is null");
+    if (opts && opts->variant > 2) return fail(FD_E_ARG, "batched calls need variant 0, 1 or 2");
+    Scratch sc(s);
+    std::vector<Geo> G(nprob);
+    std::vector<Plan> P(nprob);
+    int rc;
+    for (int p = 0; p < nprob; ++p) {
+        const fd_problem& q = probs[p];
+        const std::string who = "problem " + std::to_string(p) + ": ";
+        if ((rc = check_grid(&q.grid, opts, &G[p]))) return fail(rc, who + g_err);
+        if (p > 0 && (G[p].ndim != G[0].ndim || G[p].r != G[0].r || G[p].dtype != G[0].dtype))
+            return fail(FD_E_ARG, who + "all problems need the same ndim, order and dtype");
+        if ((rc = check_time(q.dt, q.nt))) return fail(rc, who + g_err);
+        if (q.acq.nshot > 1) return fail(FD_E_ARG, who + "batched problems have one shot each");
+        if ((rc = check_acq(&q.acq, G[p], q.nt))) return fail(rc, who + g_err);
+        if (!(q.k != 0.0) || !std::isfinite(q.k)) return fail(FD_E_ARG, who + "k must be finite and non-zero");
+        const size_t fb = G[p].ncell * dsize(G[p].dtype);
+        const size_t tb = (size_t)q.nt * q.acq.nrec * dsize(G[p].dtype);
+        if ((rc = check_dev(q.c, fb, "c"))) return fail(rc, who + g_err);
+        if ((rc = check_dev(q.grad_c, fb, "grad_c"))) return fail(rc, who + g_err);
+        if ((rc = check_dev(q.observed, tb, "observed"))) return fail(rc, who + g_err);
+        if (q.traces && (rc = check_dev(q.traces, tb, "traces"))) return fail(rc, who + g_err);
+    }
+    {
+        std::vector<const Geo*> gs;
+        std::vector<const void*> cs;
+        std::vector<double> dts;
+        for (int p = 0; p < nprob; ++p) {
+            gs.push_back(&G[p]);
+            cs.push_back(probs[p].c);
+            dts.push_back(probs[p].dt);
+        }
+        if ((rc = check_speeds(gs, cs, dts, s, sc))) return rc;
+    }
+    int nt_max = 0;
+    std::vector<fd_state> st(nprob);
+    std::vector<int32_t> bstart(nprob + 1, 0);
+    for (int p = 0; p < nprob; ++p) {
+        if ((rc = make_plan(G[p], &probs[p].acq, true, s, sc, &P[p]))) return rc;
+        const size_t fb = G[p].ncell * dsize(G[p].dtype);
+        HIPCHK(sc.get(&st[p].u_a, fb));
+        HIPCHK(sc.get(&st[p].u_b, fb));
+        HIPCHK(sc.get(&st[p].acc, G[p].ncell * dsize(G[p].acc_dtype)));
+        HIPCHK(sc.get(&st[p].residual, (size_t)probs[p].nt * probs[p].acq.nrec * dsize(G[p].dtype)));
+        HIPCHK(hipMemsetAsync(st[p].u_a, 0, fb, s));
+        HIPCHK(hipMemsetAsync(st[p].u_b, 0, fb, s));
+        HIPCHK(hipMemsetAsync(st[p].acc, 0, G[p].ncell * dsize(G[p].acc_dtype), s));
+        bstart[p + 1] = bstart[p] + P[p].nblk;
+        nt_max = std::max(nt_max, probs[p].nt);
+    }
+    const int total = bstart[nprob];
+    // step argument tables: forward steps n = 0..nt_max-1, backward steps aligned at
+    // their ends (backward step i runs j = nt_p - 1 - i of problem p while j >= 1)
+    const int nfw = nt_max, nbw = nt_max - 1;
+    std::vector<fdw::StepArgs> tab((size_t)(nfw + std::max(nbw, 0)) * nprob);
+    for (int p = 0; p < nprob; ++p) {
+        const fd_problem& q = probs[p];
+        void *prev = st[p].u_a, *cur = st[p].u_b;
+        for (int n = 0; n < nfw; ++n) {
+            fdw::StepArgs a = base_args(G[p], P[p], q.c, q.dt);
+            a.blk_off = P[p].groups[0].d_off;
+            a.ev = P[p].groups[0].d_ev;
+            a.active = n < q.nt;
+            a.acc = st[p].acc;
+            a.acc_sign = n < q.nt - 1 ? 1 : 0;
+            a.wavelet = q.acq.wavelet;
+            a.nsrc = q.acq.nsrc;
+            a.sample = 1;
+            a.traces = q.traces;
+            a.resid = st[p].residual;
+            a.obs = q.observed;
+            a.nrec = q.acq.nrec;
+            a.row_src = a.row_rec = std::min(n, q.nt - 1);
+            a.ucur = cur;
+            a.unew = prev;
+            tab[(size_t)n * nprob + p] = a;
+            if (n < q.nt) std::swap(prev, cur);
+        }
+        void *up = nullptr, *ul = nullptr;
+        final_levels(st[p].u_a, st[p].u_b, q.nt, &up, &ul);
+        void *vj = up, *vn = ul;
+        for (int i = 0; i < nbw; ++i) {
+            const int j = q.nt - 1 - i;
+            fdw::StepArgs a = base_args(G[p], P[p], q.c, q.dt);
+            a.blk_off = P[p].groups[0].d_off;
+            a.ev = P[p].groups[0].d_ev;
+            a.active = j >= 1;
+            a.acc = st[p].acc;
+            a.acc_sign = -1;
+            a.wavelet = q.acq.wavelet;
+            a.nsrc = q.acq.nsrc;
+            a.inject_rec = 1;
+            a.resid = st[p].residual;
+            a.nrec = q.acq.nrec;
+            a.rec_scale = -q.k / q.dt;
+            a.row_src = std::max(j, 1);
+            a.row_rec = std::max(j - 1, 0);
+            a.ucur = vj;
+            a.unew = vn;
+            tab[(size_t)(nfw + i) * nprob + p] = a;
+            if (j >= 1) std::swap(vj, vn);
+        }
+    }
+    fdw::StepArgs* d_tab = nullptr;
+    int32_t* d_bstart = nullptr;
+    HIPCHK(sc.get((void**)&d_tab, sizeof(fdw::StepArgs) * tab.size()));
+    HIPCHK(sc.get((void**)&d_bstart, sizeof(int32_t) * bstart.size()));
+    HIPCHK(hipMemcpyAsync(d_tab, tab.data(), sizeof(fdw::StepArgs) * tab.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_bstart, bstart.data(), sizeof(int32_t) * bstart.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // the host tables die with this frame
+
+    const Geo& G0 = G[0];
+    // Graph capture needs a capturable stream: the legacy null stream is not one, so
+    // a graph-mode call on it works on a stream of its own (default priority), which
+    // is ordered after the null stream's earlier work by the synchronisation above.
+    struct OwnStream {
+        hipStream_t s = nullptr;
+        ~OwnStream() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } }
+    } own;
+    hipStream_t ws = s;
+    if (G0.graph && s == nullptr) {
+        HIPCHK(hipStreamCreate(&own.s));
+        ws = own.s;
+    }
+    auto sweep = [&](int first, int count) -> int {
+        for (int i = 0; i < count; ++i)
+            HIPCHK(fdw::launch_step_multi(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant,
+                                          d_tab + (size_t)(first + i) * nprob, d_bstart, nprob, total, ws));
+        return FD_OK;
+    };
+    // run a sweep directly, or capture it once into a graph and launch that
+    auto run = [&](int first, int count, double* ms) -> int {
+        SweepTimer tm(G0.timing != nullptr, ws);
+        if (!G0.graph) {
+            tm.start();
+            if ((rc = sweep(first, count))) return rc;
+            tm.stop();
+        } else {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            HIPCHK(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
+            int rc2 = sweep(first, count);
+            hipError_t e = hipStreamEndCapture(ws, &graph);
+            if (rc2) { if (graph) (void)hipGraphDestroy(graph); return rc2; }
+            HIPCHK(e);
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) { (void)hipGraphDestroy(graph); HIPCHK(e); }
+            tm.start();
+            e = hipGraphLaunch(exec, ws);
+            tm.stop();
+            hipError_t e2 = hipStreamSynchronize(ws);
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(e);
+            HIPCHK(e2);
+        }
+        if (ms) *ms = tm.ms();
+        return FD_OK;
+    };
+    double fms = 0.0, bms = 0.0;
+    if ((rc = run(0, nfw, &fms))) return rc;
+    for (int p = 0; p < nprob; ++p) {
+        const fd_problem& q = probs[p];
+        if (q.acq.nrec == 0) continue;
+        void *up = nullptr, *ul = nullptr;
+        final_levels(st[p].u_a, st[p].u_b, q.nt, &up, &ul);
+        HIPCHK(fdw::launch_terminal(G[p].dtype, G[p].acc_dtype, P[p].nuniq, P[p].d_ucell, P[p].d_uoff,
+                                    P[p].d_uidx, P[p].d_ushot, 0, 1, G[p].ncell, q.c, q.dt * q.dt,
+                                    ul, up, st[p].acc,
+                                    (const char*)st[p].residual +
+                                        (size_t)(q.nt - 1) * q.acq.nrec * dsize(G[p].dtype),
+                                    -q.k / q.dt, ws));
+    }
+    if (nbw > 0 && (rc = run(nfw, nbw, &bms))) return rc;
+    if (ws != s) HIPCHK(hipStreamSynchronize(ws));
+    if (G0.timing) {
+        G0.timing->fwd_ms = fms;
+        G0.timing->fwd_launches = nfw;
+        G0.timing->bwd_ms = bms;
+        G0.timing->bwd_launches = std::max(nbw, 0);
+    }
+    for (int p = 0; p < nprob; ++p) {
+        const fd_problem& q = probs[p];
+        HIPCHK(fdw::launch_finalize(G[p].dtype, G[p].acc_dtype, G[p].ncell, st[p].acc, q.c, 1.0 / q.k,
+                                    q.grad_c, s));
+        double ss = 0.0;
+        if ((rc = misfit_sum(G[p].dtype, st[p].residual, nullptr, nullptr, (int64_t)q.nt * q.acq.nrec, s,
+                             sc, &ss)))
+            return rc;
+        J_host[p] = 0.5 * q.dt * ss;
+        if (!std::isfinite(J_host[p]))
+            return fail(FD_E_NONFINITE, "problem " + std::to_string(p) + ": misfit is not finite");
+    }
     return FD_OK;
 }
 
@@ -553,6 +832,20 @@ int32_t fd_variant_count(int32_t ndim)
     return (ndim == 2 || ndim == 3) ? fdw::variant_count(ndim) : 0;
 }
 
+int fd_variant_info(int32_t ndim, int32_t variant, int32_t* tile_z, int32_t* tile_y,
+                    int32_t* threads, int32_t* cells_per_lane)
+{
+    g_err.clear();
+    if (ndim != 2 && ndim != 3) return fail(FD_E_ARG, "ndim must be 2 or 3");
+    const fdw::Variant v = fdw::variant_shape(ndim, variant);
+    if (v.tz == 0) return fail(FD_E_ARG, "variant out of range");
+    if (tile_z) *tile_z = v.tz;
+    if (tile_y) *tile_y = v.ty;
+    if (threads) *threads = v.threads;
+    if (cells_per_lane) *cells_per_lane = v.vz;
+    return FD_OK;
+}
+
 int fd_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int32_t nt,
                void* traces, const fd_opts* opts, void* stream)
 {
@@ -566,8 +859,8 @@ int fd_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
     Plan P;
     if ((rc = make_plan(G, acq, false, s, sc, &P))) return rc;
     void *ua = nullptr, *ub = nullptr;
-    HIPCHK(sc.get(&ua, G.ncell * dsize(G.dtype)));
-    HIPCHK(sc.get(&ub, G.ncell * dsize(G.dtype)));
+    HIPCHK(sc.get(&ua, G.ncell * dsize(G.dtype) * nshots(acq)));
+    HIPCHK(sc.get(&ub, G.ncell * dsize(G.dtype) * nshots(acq)));
     return forward_sweep(G, P, c, acq, dt, nt, nullptr, ua, ub, nullptr, nullptr, traces, s);
 }
 
@@ -624,16 +917,24 @@ int fd_adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq
     if ((rc = check_time(dt, nt))) return rc;
     if (!acq) return fail(FD_E_ARG, "acq is null");
     if (acq->nrec < 0) return fail(FD_E_ARG, "receiver count is negative");
+    if (acq->nshot < 0) return fail(FD_E_ARG, "nshot is negative");
     if (!(k != 0.0) || !std::isfinite(k)) return fail(FD_E_ARG, "k must be finite and non-zero");
     Scratch sc(s);
     fd_state st;
-    HIPCHK(sc.get(&st.u_a, G.ncell * dsize(G.dtype)));
-    HIPCHK(sc.get(&st.u_b, G.ncell * dsize(G.dtype)));
+    HIPCHK(sc.get(&st.u_a, G.ncell * dsize(G.dtype) * nshots(acq)));
+    HIPCHK(sc.get(&st.u_b, G.ncell * dsize(G.dtype) * nshots(acq)));
     HIPCHK(sc.get(&st.acc, G.ncell * dsize(G.acc_dtype)));
     HIPCHK(sc.get(&st.residual, (size_t)nt * acq->nrec * dsize(G.dtype)));
     if ((rc = sens_forward(grid, c, acq, dt, nt, observed, &st, traces_or_null, J_host, opts, s, true)))
         return rc;
     return sens_backward(grid, c, acq, dt, nt, k, &st, 1.0, grad_c, opts, s, true);
+}
+
+int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, double* J_host,
+                                   const fd_opts* opts, void* stream)
+{
+    g_err.clear();
+    return batched(probs, nprob, J_host, opts, (hipStream_t)stream);
 }
 
 int fd_propagate(const fd_grid* grid, const void* coef, void* u_prev, void* u_cur, int32_t nsteps,
@@ -660,7 +961,7 @@ int fd_propagate(const fd_grid* grid, const void* coef, void* u_prev, void* u_cu
     for (int n = 0; n < nsteps; ++n) {
         a.ucur = cur;
         a.unew = prev;
-        if ((rc = step(G, P, a, s))) return rc;
+        if ((rc = step(G, P, P.groups[0], a, s))) return rc;
         std::swap(prev, cur);
     }
     if (nsteps & 1) {   // newest level sits in u_prev: swap the two buffers' contents

@@ -9,23 +9,29 @@ namespace fdw {
 // A source or receiver point inside one block's region, sorted by plane.
 struct Event {
     int32_t plane;  // coordinate along the marching axis (axis 0)
-    int32_t lane;   // position inside the block tile: ly * TZ + lz
-    int32_t kind;   // EV_SRC or EV_REC
+    int32_t lane;   // position inside the block tile: ly * WZ + lz
+    int32_t kind;   // EV_SRC or EV_REC, plus (shot slot << 1)
     int32_t idx;    // source or receiver number
 };
 enum { EV_SRC = 0, EV_REC = 1 };
+__host__ __device__ inline int ev_kind(int k) { return k & 1; }
+__host__ __device__ inline int ev_shot(int k) { return k >> 1; }
 
-// Arguments of one leapfrog step over the whole grid.
+// Arguments of one leapfrog step over the whole grid of one problem.  A step
+// advances the shots [shot0, shot0 + S) of the problem together (S is the
+// kernel's shot count); their wavefields lie shot_stride elements apart.
 struct StepArgs {
-    const void* ucur;    // level n (backward: j)
+    const void* ucur;    // level n (backward: j), first shot of the group
     void* unew;          // level n-1 on entry, n+1 on return (backward: j+1 -> j-1)
     const void* c;       // wave speed, or dt^2 c^2 itself when coef_direct
-    void* acc;           // sensitivity accumulator (used when acc_sign != 0)
+    void* acc;           // sensitivity accumulator shared by the shots (acc_sign != 0)
+    int64_t shot_stride; // elements between the wavefields of consecutive shots
     int32_t n0, n1, n2;  // extents; 2D grids run with n1 = 1
     double w[8];         // a_j / dx^2, j = 1..r
     double dt2;          // dt^2
     int32_t coef_direct; // 1: c already holds dt^2 c^2
-    int32_t acc_sign;    // 0: no accumulation, +1: acc += d^2, -1: acc -= d^2
+    int32_t acc_sign;    // 0: no accumulation, +1: acc += sum_s d_s^2, -1: acc -= ...
+    int32_t active;      // 0: the problem has no step here (multi-problem launches)
     // events
     const int32_t* blk_off;  // [nblk + 1] ranges into ev
     const Event* ev;
@@ -47,25 +53,37 @@ struct StepArgs {
 
 // Tile shape of one kernel variant.
 struct Variant {
-    int32_t tz;      // tile width along the contiguous axis (threads along z)
+    int32_t tz;      // tile width in cells along the contiguous axis
     int32_t ty;      // tile height along axis 1 (3D only)
     int32_t threads; // threads per block
+    int32_t vz;      // consecutive cells per lane (the contiguous extent must be a multiple)
+    int32_t max_shots; // largest shot group the variant is built for (1, 2 or 4)
 };
 
 int variant_count(int ndim);
 Variant variant_shape(int ndim, int variant);  // variant in 1..count
 
-// Launches one step; returns a hipError_t.
-hipError_t launch_step(int ndim, int r, int dtype, int acc_dtype, int variant, int nblk,
-                       const StepArgs& a, hipStream_t s);
+// One step of one problem for a group of `shots` shots (1, 2 or 4).
+hipError_t launch_step(int ndim, int r, int dtype, int acc_dtype, int variant, int shots,
+                       int nblk, const StepArgs& a, hipStream_t s);
+
+// One step of several problems in one launch: table[p] holds problem p's
+// arguments, block_start[p] its first block (block_start[nprob] = total).
+hipError_t launch_step_multi(int ndim, int r, int dtype, int acc_dtype, int variant,
+                             const StepArgs* d_table, const int32_t* d_block_start, int nprob,
+                             int total_blocks, hipStream_t s);
 
 // Misc kernels.  All return hipError_t of the launch.
 hipError_t launch_speed_stats(int dtype, const void* c, int64_t n, double* d_out3, double* d_part,
                               hipStream_t s);
 hipError_t launch_sum_squares(int dtype, const void* x, const void* y, void* diff_out, int64_t n,
                               double* d_part, double* d_out, hipStream_t s);
+// Terminal hand-over for the shots [shot0, shot0 + nshots) of a problem: per distinct
+// receiver cell, receivers sorted by (cell, shot); u_last / u_prev point at the
+// group's first shot, shots shot_stride elements apart.
 hipError_t launch_terminal(int dtype, int acc_dtype, int nuniq, const int64_t* ucell,
-                           const int32_t* uoff, const int32_t* uidx, const void* c, double dt2,
+                           const int32_t* uoff, const int32_t* uidx, const int32_t* ushot,
+                           int shot0, int nshots, int64_t shot_stride, const void* c, double dt2,
                            const void* u_last, void* u_prev, void* acc, const void* resid_row,
                            double rec_scale, hipStream_t s);
 hipError_t launch_finalize(int dtype, int acc_dtype, int64_t n, const void* acc, const void* c,

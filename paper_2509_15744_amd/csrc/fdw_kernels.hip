@@ -137,33 +137,49 @@ hipError_t launch_speed_stats(int dtype, const void* c, int64_t n, double* d_out
 // terminal hand-over and finalisation
 // ---------------------------------------------------------------------------
 
-// Superposed end level at the receivers: v^{nt-1} = u^{nt-1} + coef * k fdag^{nt}, and the
-// kernel of the last interval, (u^nt - u^{nt-1})^2 - (v^nt - v^{nt-1})^2 (zero elsewhere, so
-// the sweeps skip that interval away from the receivers).  One thread per distinct cell.
+// Superposed end level at the receivers, per shot of the group: v^{nt-1} = u^{nt-1}
+// + coef * k fdag^{nt} (the sum over that shot's receivers in the cell), and the kernel
+// of the last interval, (u^nt - u^{nt-1})^2 - (v^nt - v^{nt-1})^2 summed over the shots
+// (zero away from the receivers, so the sweeps skip that interval there).  One thread
+// per distinct cell; its receivers come sorted by (shot, number).
 template <typename T, typename AT>
 __global__ void terminal_kernel(int nuniq, const int64_t* __restrict__ ucell,
                                 const int32_t* __restrict__ uoff, const int32_t* __restrict__ uidx,
-                                const T* __restrict__ c, T dt2, const T* __restrict__ u_last,
-                                T* __restrict__ u_prev, AT* __restrict__ acc,
-                                const T* __restrict__ resid_row, T rec_scale)
+                                const int32_t* __restrict__ ushot, int shot0, int nshots,
+                                int64_t shot_stride, const T* __restrict__ c, T dt2,
+                                const T* __restrict__ u_last, T* __restrict__ u_prev,
+                                AT* __restrict__ acc, const T* __restrict__ resid_row, T rec_scale)
 {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= nuniq) return;
     const int64_t cell = ucell[u];
-    T s = (T)0;
-    for (int q = uoff[u]; q < uoff[u + 1]; ++q) s += rec_scale * resid_row[uidx[q]];
     const T cv = c[cell];
     const T coef = dt2 * cv * cv;
-    const T y_old = u_prev[cell];
-    const T y_new = y_old + coef * s;
-    const T d_old = u_last[cell] - y_old;
-    const T d_new = u_last[cell] - y_new;
-    acc[cell] += (AT)d_old * (AT)d_old - (AT)d_new * (AT)d_new;
-    u_prev[cell] = y_new;
+    AT delta = (AT)0;
+    int q = uoff[u];
+    const int q_end = uoff[u + 1];
+    while (q < q_end) {
+        const int sh = ushot[q];
+        T s = (T)0;
+        int q2 = q;
+        for (; q2 < q_end && ushot[q2] == sh; ++q2) s += rec_scale * resid_row[uidx[q2]];
+        if (sh >= shot0 && sh < shot0 + nshots) {
+            const int64_t o = (int64_t)(sh - shot0) * shot_stride + cell;
+            const T y_old = u_prev[o];
+            const T y_new = y_old + coef * s;
+            const T d_old = u_last[o] - y_old;
+            const T d_new = u_last[o] - y_new;
+            delta += (AT)d_old * (AT)d_old - (AT)d_new * (AT)d_new;
+            u_prev[o] = y_new;
+        }
+        q = q2;
+    }
+    acc[cell] += delta;
 }
 
 hipError_t launch_terminal(int dtype, int acc_dtype, int nuniq, const int64_t* ucell,
-                           const int32_t* uoff, const int32_t* uidx, const void* c, double dt2,
+                           const int32_t* uoff, const int32_t* uidx, const int32_t* ushot,
+                           int shot0, int nshots, int64_t shot_stride, const void* c, double dt2,
                            const void* u_last, void* u_prev, void* acc, const void* resid_row,
                            double rec_scale, hipStream_t s)
 {
@@ -171,16 +187,19 @@ hipError_t launch_terminal(int dtype, int acc_dtype, int nuniq, const int64_t* u
     const int bs = 256, gs = (nuniq + bs - 1) / bs;
     if (dtype == 1)
         hipLaunchKernelGGL((terminal_kernel<double, double>), dim3(gs), dim3(bs), 0, s, nuniq, ucell,
-                           uoff, uidx, (const double*)c, dt2, (const double*)u_last,
-                           (double*)u_prev, (double*)acc, (const double*)resid_row, rec_scale);
+                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const double*)c, dt2,
+                           (const double*)u_last, (double*)u_prev, (double*)acc,
+                           (const double*)resid_row, rec_scale);
     else if (acc_dtype == 1)
         hipLaunchKernelGGL((terminal_kernel<float, double>), dim3(gs), dim3(bs), 0, s, nuniq, ucell,
-                           uoff, uidx, (const float*)c, (float)dt2, (const float*)u_last,
-                           (float*)u_prev, (double*)acc, (const float*)resid_row, (float)rec_scale);
+                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const float*)c, (float)dt2,
+                           (const float*)u_last, (float*)u_prev, (double*)acc,
+                           (const float*)resid_row, (float)rec_scale);
     else
         hipLaunchKernelGGL((terminal_kernel<float, float>), dim3(gs), dim3(bs), 0, s, nuniq, ucell,
-                           uoff, uidx, (const float*)c, (float)dt2, (const float*)u_last,
-                           (float*)u_prev, (float*)acc, (const float*)resid_row, (float)rec_scale);
+                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const float*)c, (float)dt2,
+                           (const float*)u_last, (float*)u_prev, (float*)acc,
+                           (const float*)resid_row, (float)rec_scale);
     return hipGetLastError();
 }
 

@@ -7,10 +7,15 @@
 // K(v,v) (line 14).  One launch per time step; 2D and 3D share the code.
 //
 // Layout of the work:
-//  * a block owns a tile of the planes normal to axis 0 (3D: TY x TZ cells of
-//    axes 1 and 2; 2D: TZ cells of axis 1) and marches along axis 0 through a
+//  * a block owns a tile of the planes normal to axis 0 (3D: TY x WZ cells of
+//    axes 1 and 2; 2D: WZ cells of axis 1) and marches along axis 0 through a
 //    chunk of planes;
-//  * each thread keeps the 2r+1 values of its column along axis 0 in registers
+//  * a lane owns VZ consecutive cells of the contiguous axis (WZ = 64 VZ per
+//    wave row), so every global access of a wave is one coalesced row segment
+//    of 256 VZ bytes (f32) issued as dword, dwordx2 or dwordx4 loads;
+//  * a lane advances S shots of the same medium at once: c and the shared
+//    accumulator are read once per cell for all S wavefields;
+//  * each lane keeps the 2r+1 values of its column along axis 0 in registers
 //    (a rotating queue), so axis-0 neighbours cost no extra reads;
 //  * the current plane is staged in LDS with an r-wide halo for the in-plane
 //    neighbours (cross-shaped stencil: no corner halo), double-buffered so one
@@ -18,9 +23,7 @@
 //  * software pipelining: every load of plane x+1 (queue entry x+1+r, halo,
 //    u^{n-1}, c, accumulator) is issued before plane x is computed, so a whole
 //    plane of work covers the memory latency;
-//  * the contiguous axis maps to the 64 lanes of a wave: every access of a wave
-//    is one coalesced row segment; plane bases are wave-uniform 64-bit pointers
-//    and in-plane offsets 32-bit;
+//  * plane bases are wave-uniform 64-bit pointers, in-plane offsets 32-bit;
 //  * u^{n+1} overwrites u^{n-1} in place and the speed c is read instead of a
 //    stored dt^2 c^2 array, so a step streams four arrays; those streams are read
 //    and written non-temporally, which leaves the cache to the u^n halos;
@@ -36,7 +39,7 @@
 namespace fdw {
 
 // Ghost index: half-sample mirror about the wall faces, then clamped into the
-// array (the clamp only matters for tile-overhang threads, which store nothing).
+// array (the clamp only matters for tile-overhang lanes, which store nothing).
 __device__ __forceinline__ int ghost(int i, int n)
 {
     i = i < 0 ? -1 - i : i;
@@ -44,45 +47,95 @@ __device__ __forceinline__ int ghost(int i, int n)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+template <typename T, int V>
+struct Vec { typedef T __attribute__((ext_vector_type(V))) type; };
 template <typename T>
-__device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
-template <typename T>
-__device__ __forceinline__ void st_stream(T v, T* p) { __builtin_nontemporal_store(v, p); }
+struct Vec<T, 1> { typedef T type; };
 
-template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY>
-__global__ __launch_bounds__(TZ*(TY / RY)) void step_kernel(StepArgs a)
+template <typename T, int V>
+__device__ __forceinline__ T el(const typename Vec<T, V>::type& v, int i)
 {
-    constexpr int TYT = TY / RY;            // thread rows; a thread owns RY tile rows
-    constexpr int NT = TZ * TYT;
-    constexpr int RYH = (NDIM == 3) ? R : 0;
-    constexpr int LZ = TZ + 2 * R;
-    constexpr int LSZ = (TY + 2 * RYH) * LZ;
-    constexpr int HY = (NDIM == 3) ? 2 * R * TZ : 0;   // halo rows above and below
-    constexpr int HALO = HY + 2 * R * TY;              // plus halo columns left and right
-    constexpr int NH = (HALO + NT - 1) / NT;           // halo cells per thread
-    __shared__ T lds[2][LSZ];
+    if constexpr (V == 1) return v;
+    else return v[i];
+}
+template <typename T, int V>
+__device__ __forceinline__ void set_el(typename Vec<T, V>::type& v, int i, T x)
+{
+    if constexpr (V == 1) v = x;
+    else v[i] = x;
+}
 
-    // XCD-aware logical block id: hardware block i runs on XCD i % 8.
-    const int nb = a.nblk;
-    const int per = (nb + 7) >> 3;
-    const int hb = blockIdx.x;
-    const int b = (hb & 7) * per + (hb >> 3);
-    if (b >= nb) return;
+template <typename T, int V>
+__device__ __forceinline__ typename Vec<T, V>::type reversed(const typename Vec<T, V>::type& v)
+{
+    if constexpr (V == 1) return v;
+    else if constexpr (V == 2) return __builtin_shufflevector(v, v, 1, 0);
+    else return __builtin_shufflevector(v, v, 3, 2, 1, 0);
+}
+
+// V consecutive cells of one row starting at z (z and the row length n2 are multiples
+// of V), without a branch around the load.  A lane past the wall (z >= n2) reads the
+// aligned vector that holds its mirrored ghost cells and, when MIRROR, reverses it:
+// cell z + i maps to 2 n2 - 1 - z - i.  Without MIRROR such lanes get in-bounds values
+// they never use.
+template <typename T, int V, bool STREAM, bool MIRROR>
+__device__ __forceinline__ typename Vec<T, V>::type load_row(const T* row, int z, int n2)
+{
+    typedef typename Vec<T, V>::type vec;
+    const bool past = z >= n2;
+    const int zs = max(past ? 2 * n2 - z - V : z, 0);
+    vec v;
+    if constexpr (STREAM) v = __builtin_nontemporal_load((const vec*)(row + zs));
+    else v = *(const vec*)(row + zs);
+    if constexpr (MIRROR && V > 1) v = past ? reversed<T, V>(v) : v;
+    return v;
+}
+
+// Compile-time shape of one kernel variant.
+template <int R, typename T, int NDIM, int TZ, int TY, int RY, int VZ, int S>
+struct Shape {
+    static constexpr int TYT = TY / RY;            // thread rows; a thread owns RY tile rows
+    static constexpr int NT = TZ * TYT;            // threads per block
+    static constexpr int WZ = TZ * VZ;             // tile width in cells
+    static constexpr int RYH = (NDIM == 3) ? R : 0;
+    static constexpr int PADL = VZ * ((R + VZ - 1) / VZ);   // left pad keeps rows VZ-aligned
+    static constexpr int LZ = PADL + WZ + PADL;
+    static constexpr int LSZ = (TY + 2 * RYH) * LZ;          // one plane of one shot
+    static constexpr int HYV = (NDIM == 3) ? 2 * R * TZ : 0; // halo row vectors above and below
+    static constexpr int HZ = 2 * R * TY;                    // halo cells left and right
+    static constexpr int NHY = (HYV + NT - 1) / NT;
+    static constexpr int NHZ = (HZ + NT - 1) / NT;
+    static constexpr int NHY1 = NHY > 0 ? NHY : 1;
+    static constexpr int LDS = 2 * S * LSZ;                  // double buffer, all shots
+};
+
+// One block's share of one step: logical block b of problem `a`.
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int S>
+__device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __restrict__ lds)
+{
+    typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, S> SH;
+    typedef typename Vec<T, VZ>::type vec;
+    typedef typename Vec<AT, VZ>::type avec;
+    constexpr int TYT = SH::TYT, NT = SH::NT, WZ = SH::WZ, RYH = SH::RYH, PADL = SH::PADL;
+    constexpr int LZ = SH::LZ, LSZ = SH::LSZ, HYV = SH::HYV, HZ = SH::HZ;
+    constexpr int NHY = SH::NHY, NHZ = SH::NHZ, NHY1 = SH::NHY1;
+
     const int tzb = b % a.ntz;
     const int rest = b / a.ntz;
     const int tyb = rest % a.nty;
     const int chb = rest / a.nty;
 
     const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
-    const int z0 = tzb * TZ, y0 = tyb * TY;
+    const int z0 = tzb * WZ, y0 = tyb * TY;
     const int x0 = chb * a.chunk_len;
     const int x1 = min(x0 + a.chunk_len, n0);
     const int tid = threadIdx.x;
     const int lz = tid % TZ;
     const int lyt = tid / TZ;
-    const int z = z0 + lz;
-    const int zg = ghost(z, n2);
+    const int z = z0 + lz * VZ;              // first cell of this lane
+    const bool zlive = z < n2;
     const int64_t ps = (int64_t)n1 * n2;
+    const int64_t sst = a.shot_stride;
 
     const T* __restrict__ ucur = (const T*)a.ucur;
     T* __restrict__ unew = (T*)a.unew;
@@ -94,60 +147,76 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_kernel(StepArgs a)
     for (int j = 0; j < R; ++j) w[j] = (T)a.w[j];
     const T dt2 = (T)a.dt2;
 
-    // own cells: in-plane offset (ghosted for overhang threads, which never store)
-    int off[RY], lofs[RY], lane[RY];
+    // own cells: row offset within a plane (ghosted for overhang rows, which never store)
+    int roff[RY], lofs[RY], lane0[RY];
     bool live[RY];
 #pragma unroll
     for (int k = 0; k < RY; ++k) {
         const int ly = lyt + k * TYT;
         const int y = y0 + ly;
-        off[k] = ghost(y, n1) * n2 + zg;
-        live[k] = (z < n2) && (y < n1);
-        lofs[k] = (ly + RYH) * LZ + lz + R;
-        lane[k] = ly * TZ + lz;
+        roff[k] = ghost(y, n1) * n2;
+        live[k] = zlive && (y < n1);
+        lofs[k] = (ly + RYH) * LZ + PADL + lz * VZ;
+        lane0[k] = ly * WZ + lz * VZ;
     }
-    // halo cells of this thread: LDS slot and in-plane source offset
-    int hl[NH], hg[NH];
+    // halo rows (3D): LDS slot of the vector and its row offset in the plane
+    int hyl[NHY1], hyr[NHY1], hyz[NHY1];
 #pragma unroll
-    for (int i = 0; i < NH; ++i) {
+    for (int i = 0; i < NHY; ++i) {
         const int h = tid + i * NT;
-        int sy = 0, sz = 0;
-        if (h < HY) {
-            const int row = h / TZ;
-            sz = R + h % TZ;
-            sy = row < R ? row : row + TY;
-        } else {
-            const int hh = h - HY;
-            sy = RYH + hh / (2 * R);
-            const int col = hh % (2 * R);
-            sz = col < R ? col : col + TZ;
-        }
-        hl[i] = h < HALO ? sy * LZ + sz : -1;
-        const int gy = (NDIM == 3) ? ghost(y0 + sy - R, n1) : 0;
-        hg[i] = gy * n2 + ghost(z0 + sz - R, n2);
+        const int row = h / TZ;
+        const int sy = row < R ? row : row + TY;
+        const int cz = (h % TZ) * VZ;
+        hyl[i] = h < HYV ? sy * LZ + PADL + cz : -1;
+        hyr[i] = ghost(y0 + sy - R, n1) * n2;
+        hyz[i] = z0 + cz;
+    }
+    // halo columns: LDS slot and in-plane offset of single cells
+    int hzl[NHZ], hzg[NHZ];
+#pragma unroll
+    for (int i = 0; i < NHZ; ++i) {
+        const int h = tid + i * NT;
+        const int row = h / (2 * R);
+        const int col = h % (2 * R);
+        const int sz = col < R ? PADL - R + col : PADL + WZ + (col - R);
+        hzl[i] = h < HZ ? (RYH + row) * LZ + sz : -1;
+        const int gy = ghost(y0 + (h < HZ ? row : 0), n1);
+        hzg[i] = gy * n2 + ghost(z0 + sz - PADL, n2);
     }
 
-    // register queue along axis 0: q[k][R + d] = u^n(x + d), d in [-R, R]
-    T q[RY][2 * R + 1];
+    // register queue along axis 0: q[s][k][R + d] = u^n(x + d) of shot s, d in [-R, R]
+    vec q[S][RY][2 * R + 1];
 #pragma unroll
-    for (int k = 0; k < RY; ++k)
+    for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int d = 0; d < 2 * R + 1; ++d)
-            q[k][d] = ucur[(int64_t)ghost(x0 - R + d, n0) * ps + off[k]];
+        for (int k = 0; k < RY; ++k)
+#pragma unroll
+            for (int d = 0; d < 2 * R + 1; ++d)
+                q[s][k][d] = load_row<T, VZ, false, true>(
+                    ucur + s * sst + (int64_t)ghost(x0 - R + d, n0) * ps + roff[k], z, n2);
 
     // plane-x operands, loaded one plane ahead
-    T cu[RY], cv[RY], ch[NH];
-    AT ca[RY];
+    vec cu[S][RY], cv[RY], chy[S][NHY1];
+    avec ca[RY];
+    T chz[S][NHZ];
     {
         const int64_t xo = (int64_t)x0 * ps;
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
-            cu[k] = ld_stream(unew + xo + off[k]);
-            cv[k] = ld_stream(cc + xo + off[k]);
-            ca[k] = use_acc ? ld_stream(acc + xo + off[k]) : (AT)0;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                cu[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xo + roff[k], z, n2);
+            cv[k] = load_row<T, VZ, true, false>(cc + xo + roff[k], z, n2);
+            if (use_acc) ca[k] = load_row<AT, VZ, true, false>(acc + xo + roff[k], z, n2);
         }
 #pragma unroll
-        for (int i = 0; i < NH; ++i) ch[i] = hl[i] >= 0 ? ucur[xo + hg[i]] : (T)0;
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int i = 0; i < NHY; ++i)
+                if (hyl[i] >= 0) chy[s][i] = load_row<T, VZ, false, true>(ucur + s * sst + xo + hyr[i], hyz[i], n2);
+#pragma unroll
+            for (int i = 0; i < NHZ; ++i) chz[s][i] = hzl[i] >= 0 ? ucur[s * sst + xo + hzg[i]] : (T)0;
+        }
     }
 
     int e = a.blk_off[b];
@@ -156,30 +225,46 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_kernel(StepArgs a)
     for (int x = x0; x < x1; ++x) {
         const int64_t xo = (int64_t)x * ps;
         // issue the loads of plane x + 1
-        T nq[RY], nu[RY], nv[RY], nh[NH];
-        AT na[RY];
+        vec nq[S][RY], nu[S][RY], nv[RY], nhy[S][NHY1];
+        avec na[RY];
+        T nhz[S][NHZ];
         const bool more = x + 1 < x1;
         if (more) {
             const int64_t xn = xo + ps;
             const int64_t xq = (int64_t)ghost(x + 1 + R, n0) * ps;
 #pragma unroll
             for (int k = 0; k < RY; ++k) {
-                nq[k] = ucur[xq + off[k]];
-                nu[k] = ld_stream(unew + xn + off[k]);
-                nv[k] = ld_stream(cc + xn + off[k]);
-                na[k] = use_acc ? ld_stream(acc + xn + off[k]) : (AT)0;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    nq[s][k] = load_row<T, VZ, false, true>(ucur + s * sst + xq + roff[k], z, n2);
+                    nu[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xn + roff[k], z, n2);
+                }
+                nv[k] = load_row<T, VZ, true, false>(cc + xn + roff[k], z, n2);
+                if (use_acc) na[k] = load_row<AT, VZ, true, false>(acc + xn + roff[k], z, n2);
             }
 #pragma unroll
-            for (int i = 0; i < NH; ++i) nh[i] = hl[i] >= 0 ? ucur[xn + hg[i]] : (T)0;
+            for (int s = 0; s < S; ++s) {
+#pragma unroll
+                for (int i = 0; i < NHY; ++i)
+                    if (hyl[i] >= 0) nhy[s][i] = load_row<T, VZ, false, true>(ucur + s * sst + xn + hyr[i], hyz[i], n2);
+#pragma unroll
+                for (int i = 0; i < NHZ; ++i) nhz[s][i] = hzl[i] >= 0 ? ucur[s * sst + xn + hzg[i]] : (T)0;
+            }
         }
 
-        // stage plane x
-        T* L = lds[x & 1];
+        // stage plane x of every shot
 #pragma unroll
-        for (int k = 0; k < RY; ++k) L[lofs[k]] = q[k][R];
+        for (int s = 0; s < S; ++s) {
+            T* L = lds + ((x & 1) * S + s) * LSZ;
 #pragma unroll
-        for (int i = 0; i < NH; ++i)
-            if (hl[i] >= 0) L[hl[i]] = ch[i];
+            for (int k = 0; k < RY; ++k) *(vec*)(L + lofs[k]) = q[s][k][R];
+#pragma unroll
+            for (int i = 0; i < NHY; ++i)
+                if (hyl[i] >= 0) *(vec*)(L + hyl[i]) = chy[s][i];
+#pragma unroll
+            for (int i = 0; i < NHZ; ++i)
+                if (hzl[i] >= 0) L[hzl[i]] = chz[s][i];
+        }
         __syncthreads();
 
         // events of this plane: [ea, e)
@@ -189,51 +274,68 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_kernel(StepArgs a)
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             if (!live[k]) continue;
-            const T u0 = q[k][R];
             const int s0 = lofs[k];
-            T lap = (T)0;
+            vec un[S];
+            avec an;
+            const T* L0 = lds + (x & 1) * S * LSZ;
 #pragma unroll
-            for (int j = 1; j <= R; ++j)
-                lap += w[j - 1] * ((q[k][R + j] - u0) + (q[k][R - j] - u0));
-            if (NDIM == 3) {
+            for (int i = 0; i < VZ; ++i) {
+                const T cvi = el<T, VZ>(cv[k], i);
+                const T coef = a.coef_direct ? cvi : dt2 * cvi * cvi;
+                AT dsum = (AT)0;
 #pragma unroll
-                for (int j = 1; j <= R; ++j)
-                    lap += w[j - 1] * ((L[s0 + j * LZ] - u0) + (L[s0 - j * LZ] - u0));
-            }
+                for (int s = 0; s < S; ++s) {
+                    const T* L = L0 + s * LSZ;
+                    const T u0 = el<T, VZ>(q[s][k][R], i);
+                    T lap = (T)0;
 #pragma unroll
-            for (int j = 1; j <= R; ++j)
-                lap += w[j - 1] * ((L[s0 + j] - u0) + (L[s0 - j] - u0));
+                    for (int j = 1; j <= R; ++j)
+                        lap += w[j - 1] * ((el<T, VZ>(q[s][k][R + j], i) - u0) + (el<T, VZ>(q[s][k][R - j], i) - u0));
+                    if (NDIM == 3) {
+#pragma unroll
+                        for (int j = 1; j <= R; ++j)
+                            lap += w[j - 1] * ((L[s0 + i + j * LZ] - u0) + (L[s0 + i - j * LZ] - u0));
+                    }
+#pragma unroll
+                    for (int j = 1; j <= R; ++j)
+                        lap += w[j - 1] * ((L[s0 + i + j] - u0) + (L[s0 + i - j] - u0));
 
-            if (ea != e) {   // block-uniform: a source or receiver lies in this plane of the tile
-                T s = (T)0;
-                for (int v = ea; v < e; ++v) {
-                    const Event ev = a.ev[v];
-                    if (ev.lane != lane[k]) continue;
-                    if (ev.kind == EV_SRC)
-                        s += ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
-                    else if (a.inject_rec)
-                        s += (T)a.rec_scale * ((const T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
-                }
-                lap += s;
-            }
+                    if (ea != e) {   // block-uniform: a source or receiver lies in this plane
+                        T f = (T)0;
+                        for (int v = ea; v < e; ++v) {
+                            const Event ev = a.ev[v];
+                            if (ev.lane != lane0[k] + i || ev_shot(ev.kind) != s) continue;
+                            if (ev_kind(ev.kind) == EV_SRC)
+                                f += ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
+                            else if (a.inject_rec)
+                                f += (T)a.rec_scale * ((const T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
+                        }
+                        lap += f;
+                    }
 
-            const T coef = a.coef_direct ? cv[k] : dt2 * cv[k] * cv[k];
-            const T un = (u0 + u0) - cu[k] + coef * lap;
-            st_stream(un, unew + xo + off[k]);
-            if (use_acc) {
-                const T d = un - u0;
-                const AT dd = (AT)d * (AT)d;
-                st_stream(a.acc_sign > 0 ? ca[k] + dd : ca[k] - dd, acc + xo + off[k]);
-            }
-            if (a.sample && ea != e) {
-                for (int v = ea; v < e; ++v) {
-                    const Event ev = a.ev[v];
-                    if (ev.lane != lane[k] || ev.kind != EV_REC) continue;
-                    const int64_t o = (int64_t)a.row_rec * a.nrec + ev.idx;
-                    if (a.traces) ((T*)a.traces)[o] = un;
-                    if (a.resid) ((T*)a.resid)[o] = un - ((const T*)a.obs)[o];
+                    const T uni = (u0 + u0) - el<T, VZ>(cu[s][k], i) + coef * lap;
+                    set_el<T, VZ>(un[s], i, uni);
+                    const T d = uni - u0;
+                    dsum += (AT)d * (AT)d;
+                    if (a.sample && ea != e) {
+                        for (int v = ea; v < e; ++v) {
+                            const Event ev = a.ev[v];
+                            if (ev.lane != lane0[k] + i || ev.kind != (EV_REC | (s << 1))) continue;
+                            const int64_t o = (int64_t)a.row_rec * a.nrec + ev.idx;
+                            if (a.traces) ((T*)a.traces)[o] = uni;
+                            if (a.resid) ((T*)a.resid)[o] = uni - ((const T*)a.obs)[o];
+                        }
+                    }
+                }
+                if (use_acc) {
+                    const AT ai = el<AT, VZ>(ca[k], i);
+                    set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + dsum : ai - dsum);
                 }
             }
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                __builtin_nontemporal_store(un[s], (vec*)(unew + s * sst + xo + roff[k] + z));
+            if (use_acc) __builtin_nontemporal_store(an, (avec*)(acc + xo + roff[k] + z));
         }
 
         // rotate to plane x + 1
@@ -241,26 +343,78 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_kernel(StepArgs a)
 #pragma unroll
             for (int k = 0; k < RY; ++k) {
 #pragma unroll
-                for (int d = 0; d < 2 * R; ++d) q[k][d] = q[k][d + 1];
-                q[k][2 * R] = nq[k];
-                cu[k] = nu[k];
+                for (int s = 0; s < S; ++s) {
+#pragma unroll
+                    for (int d = 0; d < 2 * R; ++d) q[s][k][d] = q[s][k][d + 1];
+                    q[s][k][2 * R] = nq[s][k];
+                    cu[s][k] = nu[s][k];
+                }
                 cv[k] = nv[k];
-                ca[k] = na[k];
+                if (use_acc) ca[k] = na[k];
             }
 #pragma unroll
-            for (int i = 0; i < NH; ++i) ch[i] = nh[i];
+            for (int s = 0; s < S; ++s) {
+#pragma unroll
+                for (int i = 0; i < NHY; ++i) chy[s][i] = nhy[s][i];
+#pragma unroll
+                for (int i = 0; i < NHZ; ++i) chz[s][i] = nhz[s][i];
+            }
         }
     }
+}
+
+// XCD-aware logical block id: hardware block i runs on XCD i % 8, so consecutive
+// logical blocks (neighbouring tiles) go to the same XCD.
+__device__ __forceinline__ int logical_block(int nblk)
+{
+    const int per = (nblk + 7) >> 3;
+    const int hb = blockIdx.x;
+    return (hb & 7) * per + (hb >> 3);
+}
+
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int S>
+__global__ __launch_bounds__(TZ*(TY / RY)) void step_kernel(StepArgs a)
+{
+    typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, S> SH;
+    __shared__ __attribute__((aligned(16))) T lds[SH::LDS];
+    const int b = logical_block(a.nblk);
+    if (b >= a.nblk) return;
+    step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, S>(a, b, lds);
+}
+
+// Several problems in one launch: the logical block picks its problem from the
+// prefix table block_start (binary search), then runs that problem's tile.
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
+__global__ __launch_bounds__(TZ*(TY / RY)) void step_multi_kernel(const StepArgs* __restrict__ table,
+                                                                  const int32_t* __restrict__ block_start,
+                                                                  int nprob, int total)
+{
+    typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, 1> SH;
+    __shared__ __attribute__((aligned(16))) T lds[SH::LDS];
+    const int g = logical_block(total);
+    if (g >= total) return;
+    int lo = 0, hi = nprob;   // largest p with block_start[p] <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (block_start[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    const StepArgs a = table[lo];
+    if (!a.active) return;
+    step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, 1>(a, g - block_start[lo], lds);
 }
 
 // ---------------------------------------------------------------------------
 // variants and dispatch
 // ---------------------------------------------------------------------------
 
-// 3D: (tz, ty, rows per thread); 2D: tz.  Chunk lengths are chosen by the host.
-struct V3 { int tz, ty, ry; };
-static constexpr V3 k3d[] = {{64, 8, 2}, {64, 16, 4}, {64, 8, 1}, {64, 16, 2}, {64, 4, 1}};
-static constexpr int k2d[] = {64, 128, 256};
+// (lanes along z, tile rows, rows per thread, cells per lane, largest shot group)
+struct VS { int tz, ty, ry, vz, shots; };
+static constexpr VS k3d[] = {
+    {64, 8, 1, 1, 4}, {64, 8, 1, 2, 4}, {64, 8, 1, 4, 1}, {64, 16, 2, 2, 1},
+    {64, 4, 1, 2, 1}, {64, 16, 1, 1, 1}, {64, 8, 2, 1, 1}, {64, 16, 1, 2, 1}};
+static constexpr VS k2d[] = {
+    {64, 1, 1, 1, 4}, {64, 1, 1, 2, 4}, {64, 1, 1, 4, 1}, {128, 1, 1, 2, 1}, {256, 1, 1, 1, 1}};
 
 int variant_count(int ndim)
 {
@@ -269,66 +423,128 @@ int variant_count(int ndim)
 
 Variant variant_shape(int ndim, int variant)
 {
-    Variant v{0, 0, 0};
+    Variant v{0, 0, 0, 0, 0};
     if (variant < 1 || variant > variant_count(ndim)) return v;
-    if (ndim == 3) {
-        v.tz = k3d[variant - 1].tz;
-        v.ty = k3d[variant - 1].ty;
-        v.threads = v.tz * v.ty / k3d[variant - 1].ry;
-    } else {
-        v.tz = k2d[variant - 1];
-        v.ty = 1;
-        v.threads = v.tz;
-    }
+    const VS& s = ndim == 3 ? k3d[variant - 1] : k2d[variant - 1];
+    v.tz = s.tz * s.vz;
+    v.ty = s.ty;
+    v.threads = s.tz * s.ty / s.ry;
+    v.vz = s.vz;
+    v.max_shots = s.shots;
     return v;
 }
 
-template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY>
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int S>
 static hipError_t launch_one(int nblk, const StepArgs& a, hipStream_t s)
 {
     const int grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((step_kernel<R, T, AT, NDIM, TZ, TY, RY>), dim3(grid), dim3(TZ * (TY / RY)),
-                       0, s, a);
+    hipLaunchKernelGGL((step_kernel<R, T, AT, NDIM, TZ, TY, RY, VZ, S>), dim3(grid),
+                       dim3(TZ * (TY / RY)), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int SMAX>
+static hipError_t launch_shots(int shots, int nblk, const StepArgs& a, hipStream_t s)
+{
+    if (shots == 1) return launch_one<R, T, AT, NDIM, TZ, TY, RY, VZ, 1>(nblk, a, s);
+    if constexpr (SMAX >= 2)
+        if (shots == 2) return launch_one<R, T, AT, NDIM, TZ, TY, RY, VZ, 2>(nblk, a, s);
+    if constexpr (SMAX >= 4)
+        if (shots == 4) return launch_one<R, T, AT, NDIM, TZ, TY, RY, VZ, 4>(nblk, a, s);
+    return hipErrorInvalidValue;
+}
+
+template <int R, typename T, typename AT>
+static hipError_t launch_rt(int ndim, int variant, int shots, int nblk, const StepArgs& a, hipStream_t s)
+{
+    if (ndim == 3) {
+        switch (variant) {
+        case 1: return launch_shots<R, T, AT, 3, 64, 8, 1, 1, 4>(shots, nblk, a, s);
+        case 2: return launch_shots<R, T, AT, 3, 64, 8, 1, 2, 4>(shots, nblk, a, s);
+        case 3: return launch_shots<R, T, AT, 3, 64, 8, 1, 4, 1>(shots, nblk, a, s);
+        case 4: return launch_shots<R, T, AT, 3, 64, 16, 2, 2, 1>(shots, nblk, a, s);
+        case 5: return launch_shots<R, T, AT, 3, 64, 4, 1, 2, 1>(shots, nblk, a, s);
+        case 6: return launch_shots<R, T, AT, 3, 64, 16, 1, 1, 1>(shots, nblk, a, s);
+        case 7: return launch_shots<R, T, AT, 3, 64, 8, 2, 1, 1>(shots, nblk, a, s);
+        case 8: return launch_shots<R, T, AT, 3, 64, 16, 1, 2, 1>(shots, nblk, a, s);
+        }
+    } else {
+        switch (variant) {
+        case 1: return launch_shots<R, T, AT, 2, 64, 1, 1, 1, 4>(shots, nblk, a, s);
+        case 2: return launch_shots<R, T, AT, 2, 64, 1, 1, 2, 4>(shots, nblk, a, s);
+        case 3: return launch_shots<R, T, AT, 2, 64, 1, 1, 4, 1>(shots, nblk, a, s);
+        case 4: return launch_shots<R, T, AT, 2, 128, 1, 1, 2, 1>(shots, nblk, a, s);
+        case 5: return launch_shots<R, T, AT, 2, 256, 1, 1, 1, 1>(shots, nblk, a, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
+static hipError_t launch_multi_one(const StepArgs* t, const int32_t* bs, int nprob, int total,
+                                   hipStream_t s)
+{
+    const int grid = ((total + 7) / 8) * 8;
+    hipLaunchKernelGGL((step_multi_kernel<R, T, AT, NDIM, TZ, TY, RY, VZ>), dim3(grid),
+                       dim3(TZ * (TY / RY)), 0, s, t, bs, nprob, total);
     return hipGetLastError();
 }
 
 template <int R, typename T, typename AT>
-static hipError_t launch_rt(int ndim, int variant, int nblk, const StepArgs& a, hipStream_t s)
+static hipError_t launch_multi_rt(int ndim, int variant, const StepArgs* t, const int32_t* bs,
+                                  int nprob, int total, hipStream_t s)
 {
     if (ndim == 3) {
         switch (variant) {
-        case 1: return launch_one<R, T, AT, 3, 64, 8, 2>(nblk, a, s);
-        case 2: return launch_one<R, T, AT, 3, 64, 16, 4>(nblk, a, s);
-        case 3: return launch_one<R, T, AT, 3, 64, 8, 1>(nblk, a, s);
-        case 4: return launch_one<R, T, AT, 3, 64, 16, 2>(nblk, a, s);
-        case 5: return launch_one<R, T, AT, 3, 64, 4, 1>(nblk, a, s);
+        case 1: return launch_multi_one<R, T, AT, 3, 64, 8, 1, 1>(t, bs, nprob, total, s);
+        case 2: return launch_multi_one<R, T, AT, 3, 64, 8, 1, 2>(t, bs, nprob, total, s);
         }
     } else {
         switch (variant) {
-        case 1: return launch_one<R, T, AT, 2, 64, 1, 1>(nblk, a, s);
-        case 2: return launch_one<R, T, AT, 2, 128, 1, 1>(nblk, a, s);
-        case 3: return launch_one<R, T, AT, 2, 256, 1, 1>(nblk, a, s);
+        case 1: return launch_multi_one<R, T, AT, 2, 64, 1, 1, 1>(t, bs, nprob, total, s);
+        case 2: return launch_multi_one<R, T, AT, 2, 64, 1, 1, 2>(t, bs, nprob, total, s);
         }
     }
     return hipErrorInvalidValue;
 }
 
 template <int R>
-static hipError_t launch_r(int ndim, int dtype, int acc_dtype, int variant, int nblk,
+static hipError_t launch_r(int ndim, int dtype, int acc_dtype, int variant, int shots, int nblk,
                            const StepArgs& a, hipStream_t s)
 {
-    if (dtype == 1) return launch_rt<R, double, double>(ndim, variant, nblk, a, s);
-    if (acc_dtype == 1) return launch_rt<R, float, double>(ndim, variant, nblk, a, s);
-    return launch_rt<R, float, float>(ndim, variant, nblk, a, s);
+    if (dtype == 1) return launch_rt<R, double, double>(ndim, variant, shots, nblk, a, s);
+    if (acc_dtype == 1) return launch_rt<R, float, double>(ndim, variant, shots, nblk, a, s);
+    return launch_rt<R, float, float>(ndim, variant, shots, nblk, a, s);
 }
 
-hipError_t launch_step(int ndim, int r, int dtype, int acc_dtype, int variant, int nblk,
+hipError_t launch_step(int ndim, int r, int dtype, int acc_dtype, int variant, int shots, int nblk,
                        const StepArgs& a, hipStream_t s)
 {
     switch (r) {
-    case 1: return launch_r<1>(ndim, dtype, acc_dtype, variant, nblk, a, s);
-    case 2: return launch_r<2>(ndim, dtype, acc_dtype, variant, nblk, a, s);
-    case 4: return launch_r<4>(ndim, dtype, acc_dtype, variant, nblk, a, s);
+    case 1: return launch_r<1>(ndim, dtype, acc_dtype, variant, shots, nblk, a, s);
+    case 2: return launch_r<2>(ndim, dtype, acc_dtype, variant, shots, nblk, a, s);
+    case 4: return launch_r<4>(ndim, dtype, acc_dtype, variant, shots, nblk, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int R>
+static hipError_t launch_multi_r(int ndim, int dtype, int acc_dtype, int variant, const StepArgs* t,
+                                 const int32_t* bs, int nprob, int total, hipStream_t s)
+{
+    if (dtype == 1) return launch_multi_rt<R, double, double>(ndim, variant, t, bs, nprob, total, s);
+    if (acc_dtype == 1) return launch_multi_rt<R, float, double>(ndim, variant, t, bs, nprob, total, s);
+    return launch_multi_rt<R, float, float>(ndim, variant, t, bs, nprob, total, s);
+}
+
+hipError_t launch_step_multi(int ndim, int r, int dtype, int acc_dtype, int variant,
+                             const StepArgs* d_table, const int32_t* d_block_start, int nprob,
+                             int total_blocks, hipStream_t s)
+{
+    switch (r) {
+    case 1: return launch_multi_r<1>(ndim, dtype, acc_dtype, variant, d_table, d_block_start, nprob, total_blocks, s);
+    case 2: return launch_multi_r<2>(ndim, dtype, acc_dtype, variant, d_table, d_block_start, nprob, total_blocks, s);
+    case 4: return launch_multi_r<4>(ndim, dtype, acc_dtype, variant, d_table, d_block_start, nprob, total_blocks, s);
     }
     return hipErrorInvalidValue;
 }

@@ -4,6 +4,12 @@ Argument marshalling only: torch tensors become device pointers, index arrays
 become host int64 arrays, and every call runs on torch's current HIP stream.
 All arithmetic happens in the library's HIP kernels.  Importing this module
 raises if the library has not been built; there is no fallback path.
+
+Keyword options accepted by the solver calls (``**opts``): ``acc_dtype`` ("f64",
+default, or "f32"), ``variant`` (tile variant, 0 = library choice), ``chunk``
+(planes per block, 0 = library choice), ``max_group`` (shots per launch, 0/1/2/4),
+``graph`` (batched calls: capture each sweep in a hipGraph), ``timing`` (an
+``fd_timing`` record to fill).
 """
 from __future__ import annotations
 
@@ -29,15 +35,19 @@ class FdError(RuntimeError):
         self.code = code
 
 
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+
 class fd_grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("shape", ctypes.c_int64 * 3), ("dx", ctypes.c_double),
                 ("order", ctypes.c_int32), ("dtype", ctypes.c_int32)]
 
 
 class fd_acq(ctypes.Structure):
-    _fields_ = [("nsrc", ctypes.c_int32), ("src_cell", ctypes.POINTER(ctypes.c_int64)),
-                ("wavelet", ctypes.c_void_p), ("nrec", ctypes.c_int32),
-                ("rec_cell", ctypes.POINTER(ctypes.c_int64))]
+    _fields_ = [("nsrc", ctypes.c_int32), ("src_cell", _I64P), ("wavelet", ctypes.c_void_p),
+                ("nrec", ctypes.c_int32), ("rec_cell", _I64P), ("nshot", ctypes.c_int32),
+                ("src_shot", _I32P), ("rec_shot", _I32P)]
 
 
 class fd_timing(ctypes.Structure):
@@ -47,12 +57,19 @@ class fd_timing(ctypes.Structure):
 
 class fd_opts(ctypes.Structure):
     _fields_ = [("acc_dtype", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("timing", ctypes.POINTER(fd_timing)), ("chunk", ctypes.c_int32)]
+                ("timing", ctypes.POINTER(fd_timing)), ("chunk", ctypes.c_int32),
+                ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class fd_state(ctypes.Structure):
     _fields_ = [("u_a", ctypes.c_void_p), ("u_b", ctypes.c_void_p), ("acc", ctypes.c_void_p),
                 ("residual", ctypes.c_void_p)]
+
+
+class fd_problem(ctypes.Structure):
+    _fields_ = [("grid", fd_grid), ("c", ctypes.c_void_p), ("acq", fd_acq), ("dt", ctypes.c_double),
+                ("nt", ctypes.c_int32), ("observed", ctypes.c_void_p), ("k", ctypes.c_double),
+                ("grad_c", ctypes.c_void_p), ("traces", ctypes.c_void_p)]
 
 
 def _load():
@@ -68,11 +85,13 @@ def _load():
         "fd_last_error": ([], ctypes.c_char_p),
         "fd_cfl_limit": ([I, I], D),
         "fd_variant_count": ([I], I),
+        "fd_variant_info": ([I, I, _I32P, _I32P, _I32P, _I32P], ctypes.c_int),
         "fd_forward": ([G, P, A, D, I, P, O, P], ctypes.c_int),
         "fd_misfit": ([I, I, I, D, P, P, P, DP, P], ctypes.c_int),
         "fd_adjoint_sensitivity": ([G, P, A, D, I, P, D, P, DP, P, O, P], ctypes.c_int),
         "fd_sens_forward": ([G, P, A, D, I, P, S, P, DP, O, P], ctypes.c_int),
         "fd_sens_backward": ([G, P, A, D, I, D, S, D, P, O, P], ctypes.c_int),
+        "fd_adjoint_sensitivity_batched": ([ctypes.POINTER(fd_problem), I, DP, O, P], ctypes.c_int),
         "fd_propagate": ([G, P, P, P, I, O, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -128,26 +147,37 @@ def make_grid(shape, dx, order, dtype_code) -> fd_grid:
 
 
 class Acquisition:
-    """Host cell arrays + device wavelet, kept alive for the duration of calls."""
+    """Host cell (and shot) arrays + device wavelet, kept alive for the calls."""
 
-    def __init__(self, src_cells, wavelet: torch.Tensor, rec_cells):
+    def __init__(self, src_cells, wavelet: torch.Tensor, rec_cells, src_shot=None, rec_shot=None,
+                 nshot=0):
         self.src = np.ascontiguousarray(np.asarray(src_cells, dtype=np.int64).reshape(-1))
         self.rec = np.ascontiguousarray(np.asarray(rec_cells, dtype=np.int64).reshape(-1))
         self.wavelet = wavelet
+        self.nshot = int(nshot)
         a = fd_acq()
         a.nsrc = len(self.src)
-        a.src_cell = self.src.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        a.src_cell = self.src.ctypes.data_as(_I64P)
         a.wavelet = _dev(wavelet, "wavelet") if len(self.src) else None
         a.nrec = len(self.rec)
-        a.rec_cell = self.rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        a.rec_cell = self.rec.ctypes.data_as(_I64P)
+        a.nshot = self.nshot
+        if self.nshot > 1:
+            self.src_shot = np.ascontiguousarray(np.asarray(src_shot, dtype=np.int32).reshape(-1))
+            self.rec_shot = np.ascontiguousarray(np.asarray(rec_shot, dtype=np.int32).reshape(-1))
+            if len(self.src_shot) != len(self.src) or len(self.rec_shot) != len(self.rec):
+                raise ValueError("one shot tag per source and per receiver")
+            a.src_shot = self.src_shot.ctypes.data_as(_I32P)
+            a.rec_shot = self.rec_shot.ctypes.data_as(_I32P)
         self.c = a
 
+    @property
+    def shots(self):
+        return max(self.nshot, 1)
 
-def make_opts(acc_dtype=None, variant=0, timing: "fd_timing | None" = None, chunk=0) -> fd_opts:
+
+def make_opts(acc_dtype=None, variant=0, timing=None, chunk=0, max_group=0, graph=False) -> fd_opts:
     o = fd_opts()
-    o.chunk = int(chunk)
-    if timing is not None:
-        o.timing = ctypes.pointer(timing)
     if acc_dtype is None or acc_dtype in ("f64", torch.float64, FD_F64):
         o.acc_dtype = FD_F64
     elif acc_dtype in ("f32", torch.float32, FD_F32):
@@ -155,6 +185,11 @@ def make_opts(acc_dtype=None, variant=0, timing: "fd_timing | None" = None, chun
     else:
         raise ValueError(f"acc_dtype {acc_dtype!r}")
     o.variant = int(variant)
+    if timing is not None:
+        o.timing = ctypes.pointer(timing)
+    o.chunk = int(chunk)
+    o.max_group = int(max_group)
+    o.graph = int(bool(graph))
     return o
 
 
@@ -166,14 +201,35 @@ def fd_variant_count(ndim: int) -> int:
     return int(_lib.fd_variant_count(ndim))
 
 
-def fd_forward(c, dx, order, src, wavelet, rec, dt, nt, traces=None, acc_dtype=None, variant=0,
-               timing=None, chunk=0):
-    """Receiver traces [nt, nrec] of the forward solve."""
-    acq = Acquisition(src, wavelet, rec)
+def fd_variant_info(ndim: int, variant: int) -> dict:
+    """Tile shape of a kernel variant: tile_z, tile_y, threads, cells_per_lane."""
+    out = [ctypes.c_int32() for _ in range(4)]
+    _raise(_lib.fd_variant_info(int(ndim), int(variant), *[ctypes.byref(o) for o in out]))
+    return dict(zip(("tile_z", "tile_y", "threads", "cells_per_lane"), (o.value for o in out)))
+
+
+def variants_for(shape) -> list:
+    """Kernel variants that can run on a grid of this shape."""
+    nd = len(shape)
+    return [v for v in range(1, fd_variant_count(nd) + 1)
+            if shape[-1] % fd_variant_info(nd, v)["cells_per_lane"] == 0]
+
+
+def _acq(src, wavelet, rec, shots):
+    if isinstance(src, Acquisition):
+        return src
+    src_shot, rec_shot, nshot = shots if shots is not None else (None, None, 0)
+    return Acquisition(src, wavelet, rec, src_shot, rec_shot, nshot)
+
+
+def fd_forward(c, dx, order, src, wavelet, rec, dt, nt, traces=None, shots=None, **opts):
+    """Receiver traces [nt, nrec] of the forward solve.  ``shots`` = (src_shot, rec_shot,
+    nshot) tags a batch of shots."""
+    acq = _acq(src, wavelet, rec, shots)
     if traces is None:
         traces = torch.empty((nt, len(acq.rec)), dtype=c.dtype, device=c.device)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
-    o = make_opts(acc_dtype, variant, timing, chunk)
+    o = make_opts(**opts)
     _raise(_lib.fd_forward(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt),
                            _dev(traces, "traces"), ctypes.byref(o), _stream()))
     return traces
@@ -190,13 +246,13 @@ def fd_misfit(traces, observed, dt, residual=None) -> float:
 
 
 def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k, grad=None,
-                           traces=None, acc_dtype=None, variant=0, timing=None, chunk=0):
+                           traces=None, shots=None, **opts):
     """(grad_c, J) of the memory-efficient method at factor ``k``."""
-    acq = Acquisition(src, wavelet, rec)
+    acq = _acq(src, wavelet, rec, shots)
     if grad is None:
         grad = torch.empty_like(c)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
-    o = make_opts(acc_dtype, variant, timing, chunk)
+    o = make_opts(**opts)
     J = ctypes.c_double()
     _raise(_lib.fd_adjoint_sensitivity(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt),
                                        int(nt), _dev(observed, "observed"), float(k),
@@ -208,11 +264,12 @@ def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k,
 class SweepState:
     """Caller-owned device state between fd_sens_forward and fd_sens_backward."""
 
-    def __init__(self, c: torch.Tensor, nt: int, nrec: int, acc_dtype=None):
+    def __init__(self, c: torch.Tensor, nt: int, nrec: int, acc_dtype=None, nshot: int = 1):
         acc_t = torch.float32 if (make_opts(acc_dtype).acc_dtype == FD_F32
                                   and c.dtype == torch.float32) else torch.float64
-        self.u_a = torch.empty_like(c)
-        self.u_b = torch.empty_like(c)
+        ns = max(int(nshot), 1)
+        self.u_a = torch.empty((ns,) + tuple(c.shape), dtype=c.dtype, device=c.device)
+        self.u_b = torch.empty_like(self.u_a)
         self.acc = torch.empty(c.shape, dtype=acc_t, device=c.device)
         self.residual = torch.empty((nt, nrec), dtype=c.dtype, device=c.device)
 
@@ -226,10 +283,10 @@ class SweepState:
 
 
 def fd_sens_forward(c, dx, order, src, wavelet, rec, dt, nt, observed, state: SweepState,
-                    traces=None, acc_dtype=None, variant=0, timing=None, chunk=0) -> float:
-    acq = Acquisition(src, wavelet, rec)
+                    traces=None, shots=None, **opts) -> float:
+    acq = _acq(src, wavelet, rec, shots)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
-    o = make_opts(acc_dtype, variant, timing, chunk)
+    o = make_opts(**opts)
     st = state.c_struct()
     J = ctypes.c_double()
     _raise(_lib.fd_sens_forward(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt),
@@ -239,12 +296,12 @@ def fd_sens_forward(c, dx, order, src, wavelet, rec, dt, nt, observed, state: Sw
 
 
 def fd_sens_backward(c, dx, order, src, wavelet, rec, dt, nt, k, state: SweepState, grad_scale=1.0,
-                     grad=None, acc_dtype=None, variant=0, timing=None, chunk=0):
-    acq = Acquisition(src, wavelet, rec)
+                     grad=None, shots=None, **opts):
+    acq = _acq(src, wavelet, rec, shots)
     if grad is None:
         grad = torch.empty_like(c)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
-    o = make_opts(acc_dtype, variant, timing, chunk)
+    o = make_opts(**opts)
     st = state.c_struct()
     _raise(_lib.fd_sens_backward(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt),
                                  float(k), ctypes.byref(st), float(grad_scale), _dev(grad, "grad"),
@@ -252,10 +309,41 @@ def fd_sens_backward(c, dx, order, src, wavelet, rec, dt, nt, k, state: SweepSta
     return grad
 
 
-def fd_propagate(coef, u_prev, u_cur, nsteps, dx, order, variant=0, chunk=0):
+class Problem:
+    """One independent problem of a batched call (device tensors stay referenced)."""
+
+    def __init__(self, c, dx, order, src, wavelet, rec, dt, nt, observed, k, grad=None, traces=None):
+        self.c, self.observed = c, observed
+        self.acq = Acquisition(src, wavelet, rec)
+        self.grad = torch.empty_like(c) if grad is None else grad
+        self.traces = traces
+        p = fd_problem()
+        p.grid = make_grid(c.shape, dx, order, _dtype_code(c))
+        p.c = _dev(c, "c")
+        p.acq = self.acq.c
+        p.dt = float(dt)
+        p.nt = int(nt)
+        p.observed = _dev(observed, "observed")
+        p.k = float(k)
+        p.grad_c = _dev(self.grad, "grad")
+        p.traces = _dev(traces, "traces")
+        self.c_struct = p
+
+
+def fd_adjoint_sensitivity_batched(problems, **opts):
+    """Alg. 1 for a list of ``Problem``s in lock-step launches; returns their J values
+    (gradients land in each problem's ``grad``)."""
+    arr = (fd_problem * len(problems))(*[p.c_struct for p in problems])
+    J = (ctypes.c_double * len(problems))()
+    o = make_opts(**opts)
+    _raise(_lib.fd_adjoint_sensitivity_batched(arr, len(problems), J, ctypes.byref(o), _stream()))
+    return list(J)
+
+
+def fd_propagate(coef, u_prev, u_cur, nsteps, dx, order, **opts):
     """In place: (u_prev, u_cur) advance by ``nsteps`` source-free steps."""
     g = make_grid(coef.shape, dx, order, _dtype_code(coef))
-    o = make_opts(None, variant, None, chunk)
+    o = make_opts(**opts)
     _raise(_lib.fd_propagate(ctypes.byref(g), _dev(coef, "coef"), _dev(u_prev, "u_prev"),
                              _dev(u_cur, "u_cur"), int(nsteps), ctypes.byref(o), _stream()))
     return u_prev, u_cur

@@ -38,6 +38,7 @@ class Problem:
     rec: np.ndarray            # int64 [nrec] flat cells
     wavelet: np.ndarray        # float64 [nt, nsrc]
     meta: dict = field(default_factory=dict)
+    observed: np.ndarray | None = None   # [nt, nrec] data given directly (c_ref is then None)
 
     @property
     def ndim(self):
@@ -146,24 +147,68 @@ def layered_2d(n: int = 2048, nt: int = 4000, order: int = 8, dtype: str = "f32"
                    meta={"courant": courant, "f_peak": f_peak, "seed": seed})
 
 
+def ricker_fn(f_peak: float, t0: float | None = None):
+    """The Ricker wavelet as a function of continuous time."""
+    if t0 is None:
+        t0 = 1.5 / f_peak
+
+    def fn(t):
+        a = (math.pi * f_peak * (np.asarray(t) - t0)) ** 2
+        return (1.0 - 2.0 * a) * np.exp(-a)
+    return fn
+
+
+def green3d_traces(shape, src_pos, rec_pos, c0, dt, nt, wavelet_fn, dx=1.0):
+    """Closed-form data of a homogeneous 3D box of speed c0 with reflecting walls at the
+    half-cell faces: sum over wall images of s(t - R/c0) / (4 pi R) for
+    (1/c0^2) u_tt - Lap u = s(t) delta, sampled at t = n dt, n = 1..nt.
+    Positions are cell indices (cell centres); returns [nt, nrec]."""
+    t = np.arange(1, nt + 1) * dt
+    reach = c0 * t[-1] / dx + 1.0
+    per_axis = []
+    for p, n in zip(src_pos, shape):
+        m = int(reach // (2 * n)) + 2
+        per_axis.append(np.array([p + 2 * n * k for k in range(-m, m + 1)]
+                                 + [-1 - p + 2 * n * k for k in range(-m, m + 1)], dtype=np.float64))
+    ix, iy, iz = np.meshgrid(*per_axis, indexing="ij")
+    imgs = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)
+    rec_pos = np.asarray(rec_pos, dtype=np.float64)
+    out = np.zeros((nt, len(rec_pos)))
+    for q, r in enumerate(rec_pos):
+        R = np.sqrt(((imgs - r) ** 2).sum(axis=1)) * dx
+        R = R[R <= reach * dx]
+        tau = t[:, None] - R[None, :] / c0
+        out[:, q] = (wavelet_fn(tau) / (4.0 * math.pi * R[None, :])).sum(axis=1)
+    return out
+
+
 def smooth_3d(n: int = 256, nt: int = 2000, order: int = 8, dtype: str = "f32", seed: int = 4,
-              sigma: float = 6.0, courant: float = 0.4, rec_every: int = 8) -> Problem:
+              sigma: float = 6.0, courant: float = 0.4, rec_every: int = 8,
+              observed: str = "green") -> Problem:
     """Smooth random speed in [1, 3] (white noise, Gaussian sigma, affine map); Ricker
     source at the centre of the top face (f = 1/20); receiver grid on the face
-    x0 = 0 every ``rec_every`` cells; observed data from c = 2."""
+    x0 = 0 every ``rec_every`` cells.  Observed data: the closed-form traces of the
+    homogeneous c = 2 box (``observed="green"``, no solve needed) or the traces of a
+    c = 2 solve (``observed="solve"``, c_ref set)."""
     shape = (n, n, n)
     p = smooth_noise(shape, sigma, seed)
     c = 1.0 + (p - p.min()) * (2.0 / (p.max() - p.min()))
-    c_ref = np.full(shape, 2.0)
     dt = time_step(3.0, 1.0, courant)
     f_peak = 1.0 / 20.0
-    src = flat(shape, [[0, n // 2, n // 2]])
+    src_pos = [0, n // 2, n // 2]
+    src = flat(shape, [src_pos])
     h = rec_every // 2
-    rec = flat(shape, [[0, rec_every * a + h, rec_every * b + h]
-                       for a in range(n // rec_every) for b in range(n // rec_every)])
+    rec_pos = [[0, rec_every * a + h, rec_every * b + h]
+               for a in range(n // rec_every) for b in range(n // rec_every)]
+    rec = flat(shape, rec_pos)
+    obs, c_ref = None, None
+    if observed == "green":
+        obs = green3d_traces(shape, src_pos, rec_pos, 2.0, dt, nt, ricker_fn(f_peak))
+    else:
+        c_ref = np.full(shape, 2.0)
     return Problem("smooth3d", shape, order, dtype, 1.0, dt, nt, c, c_ref, src, rec,
                    ricker(nt, dt, f_peak).reshape(nt, 1),
-                   meta={"courant": courant, "f_peak": f_peak, "seed": seed})
+                   meta={"courant": courant, "f_peak": f_peak, "seed": seed}, observed=obs)
 
 
 def layered_3d(n: int = 1024, nt: int = 3000, order: int = 8, dtype: str = "f32", seed: int = 5,

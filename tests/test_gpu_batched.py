@@ -1,0 +1,166 @@
+"""Batching: several shots on one medium (shot-tagged acquisition, shared accumulator,
+S shots per launch) and independent problems of uneven sizes in lock-step launches
+(optionally captured in a hipGraph), against single-shot runs and the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2509_15744_amd import workloads as wl
+from helpers import rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fdw():
+    assert torch.cuda.is_available(), "the gpu tests need a HIP device"
+    from paper_2509_15744_amd import fdwave
+    return fdwave
+
+
+def _shot_problem(shape, nshot, order, nt, dtype, seed):
+    """One medium, nshot shots: each shot has 1-2 sources and 3-5 receivers of its own."""
+    rng = np.random.default_rng(seed)
+    c = 1.0 + rng.random(shape)
+    dt = 0.4 * oracle.cfl_limit(len(shape), order) / c.max()
+    n = int(np.prod(shape))
+    src, src_shot, rec, rec_shot = [], [], [], []
+    for s in range(nshot):
+        for _ in range(1 + s % 2):
+            src.append(rng.integers(n)); src_shot.append(s)
+        for _ in range(3 + s % 3):
+            rec.append(rng.integers(n)); rec_shot.append(s)
+    rec.append(rec[0]); rec_shot.append(rec_shot[0])           # a duplicate receiver
+    rec.append(src[-1]); rec_shot.append(src_shot[-1])         # a receiver on a source
+    src, rec = np.array(src, np.int64), np.array(rec, np.int64)
+    src_shot, rec_shot = np.array(src_shot, np.int32), np.array(rec_shot, np.int32)
+    wavelet = rng.standard_normal((nt, len(src)))
+    obs = 0.01 * rng.standard_normal((nt, len(rec)))
+    return dict(shape=shape, order=order, nt=nt, dtype=dtype, c=c, dt=dt, src=src, rec=rec,
+                src_shot=src_shot, rec_shot=rec_shot, wavelet=wavelet, obs=obs, nshot=nshot)
+
+
+def _oracle_sum(P, k):
+    """Sum over shots of the oracle's single-shot Alg. 1 (gradients and J add up)."""
+    g = np.zeros(P["shape"])
+    J = 0.0
+    tr = np.zeros((P["nt"], len(P["rec"])))
+    for s in range(P["nshot"]):
+        si = np.where(P["src_shot"] == s)[0]
+        ri = np.where(P["rec_shot"] == s)[0]
+        gs, Js, trs = oracle.superposition_gradient(P["c"], 1.0, P["order"], P["dt"], P["nt"],
+                                                    P["src"][si], P["wavelet"][:, si], P["rec"][ri],
+                                                    P["obs"][:, ri], k)
+        g += gs
+        J += Js
+        tr[:, ri] = trs
+    return g, J, tr
+
+
+@pytest.mark.parametrize("shape,nshot,order,max_group", [
+    ((14, 11, 70), 4, 8, 0),
+    ((14, 11, 70), 7, 8, 0),      # groups 4 + 2 + 1
+    ((14, 11, 70), 3, 4, 2),      # groups 2 + 1
+    ((40, 66), 5, 8, 0),
+    ((40, 66), 6, 2, 1),          # one shot per launch
+])
+def test_shots_match_oracle_sum(fdw, shape, nshot, order, max_group):
+    """f64: the shot batch equals the sum of per-shot oracle runs (J, traces, gradient)."""
+    P = _shot_problem(shape, nshot, order, 33, "f64", seed=nshot + len(shape))
+    k = 0.05
+    g_o, J_o, tr_o = _oracle_sum(P, k)
+    f64 = torch.float64
+    tr = torch.empty((P["nt"], len(P["rec"])), dtype=f64, device="cuda")
+    shots = (P["src_shot"], P["rec_shot"], nshot)
+    for variant in [v for v in fdw.variants_for(shape) if v <= 2]:
+        say("shots", shape, nshot, order, "variant", variant, "max_group", max_group)
+        g, J = fdw.fd_adjoint_sensitivity(to_dev(P["c"], f64), 1.0, order, P["src"],
+                                          to_dev(P["wavelet"], f64), P["rec"], P["dt"], P["nt"],
+                                          to_dev(P["obs"], f64), k, traces=tr, shots=shots,
+                                          variant=variant, max_group=max_group)
+        assert rel(tr.cpu().numpy(), tr_o) < 1e-12
+        assert abs(J - J_o) < 1e-12 * J_o
+        assert rel(g.cpu().numpy(), g_o) < 1e-9
+
+
+def test_shots_f32_and_split(fdw):
+    """f32 shot batch within 1e-4 of the oracle; the split forward/backward pair with
+    caller-owned [nshot][ncell] state gives the fused call's result bitwise."""
+    P = _shot_problem((21, 16, 64), 4, 8, 60, "f32", seed=3)
+    k = 0.05
+    g_o, J_o, _ = _oracle_sum(P, k)
+    f32 = torch.float32
+    c, w, obs = to_dev(P["c"], f32), to_dev(P["wavelet"], f32), to_dev(P["obs"], f32)
+    shots = (P["src_shot"], P["rec_shot"], 4)
+    g, J = fdw.fd_adjoint_sensitivity(c, 1.0, 8, P["src"], w, P["rec"], P["dt"], P["nt"], obs, k,
+                                      shots=shots)
+    assert rel(g.cpu().numpy(), g_o) < 1e-4
+    st = fdw.SweepState(c, P["nt"], len(P["rec"]), nshot=4)
+    J2 = fdw.fd_sens_forward(c, 1.0, 8, P["src"], w, P["rec"], P["dt"], P["nt"], obs, st, shots=shots)
+    g2 = fdw.fd_sens_backward(c, 1.0, 8, P["src"], w, P["rec"], P["dt"], P["nt"], k, st, shots=shots)
+    assert J2 == J and torch.equal(g2, g)
+
+
+def test_shot_tags_are_validated(fdw):
+    P = _shot_problem((10, 10, 16), 2, 4, 5, "f32", seed=1)
+    bad = P["rec_shot"].copy()
+    bad[0] = 2
+    f32 = torch.float32
+    with pytest.raises(fdw.FdError) as e:
+        fdw.fd_forward(to_dev(P["c"], f32), 1.0, 4, P["src"], to_dev(P["wavelet"], f32), P["rec"],
+                       P["dt"], 5, shots=(P["src_shot"], bad, 2))
+    assert e.value.code == fdw.FD_E_ARG and "shot out of range" in str(e.value)
+
+
+def _uneven_problems(ndim, nprob, dtype, seed):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for p in range(nprob):
+        if ndim == 2:
+            shape = (int(rng.integers(20, 90)), int(rng.integers(20, 150)))
+        else:
+            shape = (int(rng.integers(8, 20)), int(rng.integers(8, 20)), int(rng.integers(8, 80)))
+        q = wl.small_random(shape, order=8, nt=int(rng.integers(15, 40)), dtype=dtype,
+                            seed=100 * seed + p, nsrc=2, nrec=5)
+        q.meta["k"] = float(0.02 * (1 + p))
+        probs.append(q)
+    return probs
+
+
+@pytest.mark.parametrize("ndim,graph", [(2, False), (2, True), (3, False), (3, True)])
+def test_batched_problems_match_single_calls(fdw, ndim, graph):
+    """Uneven-size problems (different shapes, dt, nt, k, acquisitions) in one launch per
+    step: each result equals its own single-problem call bitwise and the oracle to
+    rounding (f64)."""
+    probs = _uneven_problems(ndim, 6, "f64", seed=ndim)
+    f64 = torch.float64
+    items, singles, refs = [], [], []
+    for q in probs:
+        obs = oracle.forward(q.c_ref, 1.0, 8, q.dt, q.nt, q.src, q.wavelet, q.rec)[0]
+        c, w, o = to_dev(q.c, f64), to_dev(q.wavelet, f64), to_dev(obs, f64)
+        items.append(fdw.Problem(c, 1.0, 8, q.src, w, q.rec, q.dt, q.nt, o, q.meta["k"]))
+        singles.append(fdw.fd_adjoint_sensitivity(c, 1.0, 8, q.src, w, q.rec, q.dt, q.nt, o,
+                                                  q.meta["k"]))
+        refs.append(oracle.superposition_gradient(q.c, 1.0, 8, q.dt, q.nt, q.src, q.wavelet, q.rec,
+                                                  obs, q.meta["k"]))
+    say("batched", ndim, "graph", graph, [q.shape for q in probs])
+    Js = fdw.fd_adjoint_sensitivity_batched(items, graph=graph)
+    for it, (g1, J1), (g_o, J_o, _) in zip(items, singles, refs):
+        assert torch.equal(it.grad, g1) and Js[items.index(it)] == J1
+        assert rel(it.grad.cpu().numpy(), g_o) < 1e-9
+        assert abs(J1 - J_o) < 1e-12 * J_o
+
+
+def test_batched_rejects_mixed_orders(fdw):
+    a = wl.small_random((20, 20), order=8, nt=5, dtype="f32", seed=1)
+    b = wl.small_random((20, 20), order=4, nt=5, dtype="f32", seed=2)
+    f32 = torch.float32
+    items = []
+    for q in (a, b):
+        c, w = to_dev(q.c, f32), to_dev(q.wavelet, f32)
+        obs = torch.zeros((q.nt, len(q.rec)), dtype=f32, device="cuda")
+        items.append(fdw.Problem(c, 1.0, q.order, q.src, w, q.rec, q.dt, q.nt, obs, 0.1))
+    with pytest.raises(fdw.FdError) as e:
+        fdw.fd_adjoint_sensitivity_batched(items)
+    assert "same ndim, order and dtype" in str(e.value)

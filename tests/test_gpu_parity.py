@@ -92,7 +92,7 @@ def test_inclusion_fp64_parity(fdw):
     case = inclusion_case()
     p = case.p
     say("inclusion fp64", p.shape, p.nt, "k", case.k)
-    for variant in range(1, fdw.fd_variant_count(2) + 1):
+    for variant in fdw.variants_for(p.shape):
         grad, J, traces = run_sens(fdw, p, case, variant=variant)
         assert rel(traces, case.traces) < 1e-12
         assert abs(J - case.J) < 1e-12 * case.J
@@ -121,7 +121,7 @@ def test_smooth3d_fp32_parity(fdw):
     for every 3D tile variant."""
     case = smooth3d_case()
     p = case.p
-    for variant in range(1, fdw.fd_variant_count(3) + 1):
+    for variant in fdw.variants_for(p.shape):
         say("smooth3d fp32 variant", variant, p.shape, p.nt)
         grad, J, traces = run_sens(fdw, p, case, variant=variant)
         e_tr, e_g = rel(traces, case.traces), rel(grad, case.g_approx)
@@ -139,6 +139,10 @@ def test_smooth3d_fp32_parity(fdw):
     ((17, 9, 131), 4, 23, 6),
     ((33, 20, 65), 2, 19, 7),
     ((8, 71, 9), 8, 15, 8),
+    ((12, 9, 132), 8, 21, 9),      # multiple of 4, ragged for 128- and 256-wide tiles
+    ((20, 17, 68), 4, 17, 10),
+    ((30, 260), 8, 25, 11),
+    ((7, 6, 8), 8, 9, 12),         # narrower than every vector tile
 ])
 def test_edge_cases_fp64(fdw, shape, order, nt, seed):
     """Random media, duplicate receivers, a receiver on a source cell, cells anywhere
@@ -146,7 +150,7 @@ def test_edge_cases_fp64(fdw, shape, order, nt, seed):
     p = wl.small_random(shape, order=order, nt=nt, dtype="f64", seed=seed, nsrc=3, nrec=9)
     case = OracleCase(p, k=0.05)
     say("edge", shape, order, nt)
-    for variant in range(1, fdw.fd_variant_count(len(shape)) + 1):
+    for variant in fdw.variants_for(shape):
         grad, J, traces = run_sens(fdw, p, case, variant=variant)
         assert rel(traces, case.traces) < 1e-12
         assert abs(J - case.J) <= 1e-12 * max(case.J, 1e-300)
@@ -174,10 +178,11 @@ def test_cells_on_every_wall_and_corner(fdw):
 
 def test_variants_are_bitwise_identical(fdw):
     """The per-cell arithmetic does not depend on the tile shape."""
-    p = wl.small_random((19, 23, 130), order=8, nt=20, dtype="f32", seed=9)
+    p = wl.small_random((19, 23, 132), order=8, nt=20, dtype="f32", seed=9)
     case = OracleCase(p, k=0.05, exact=False)
+    assert len(fdw.variants_for(p.shape)) == fdw.fd_variant_count(3)
     ref = None
-    for variant in range(1, fdw.fd_variant_count(3) + 1):
+    for variant in fdw.variants_for(p.shape):
         say("bitwise variant", variant)
         out = run_sens(fdw, p, case, variant=variant)
         if ref is None:
@@ -185,6 +190,17 @@ def test_variants_are_bitwise_identical(fdw):
         else:
             assert np.array_equal(out[0], ref[0]) and np.array_equal(out[2], ref[2])
             assert out[1] == ref[1]
+
+
+def test_variant_needing_wider_rows_is_rejected(fdw):
+    p = wl.small_random((10, 10, 70), order=4, nt=5, dtype="f32", seed=1)
+    bad = [v for v in range(1, fdw.fd_variant_count(3) + 1)
+           if 70 % fdw.fd_variant_info(3, v)["cells_per_lane"]]
+    assert bad
+    c, w = to_dev(p.c, torch.float32), to_dev(p.wavelet, torch.float32)
+    with pytest.raises(fdw.FdError) as e:
+        fdw.fd_forward(c, 1.0, 4, p.src, w, p.rec, p.dt, 5, variant=bad[0])
+    assert e.value.code == fdw.FD_E_ARG and "multiple of" in str(e.value)
 
 
 def test_chunking_is_bitwise_identical(fdw):

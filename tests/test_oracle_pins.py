@@ -339,6 +339,18 @@ def test_exact_gradient_matches_brute_force_fd(shape, order):
     assert np.abs(fd - g.ravel()).max() < 1e-7 * np.abs(g).max()
 
 
+@pytest.mark.parametrize("seg", [1, 7, 40, 1000])
+def test_checkpointed_adjoint_equals_stored_history(seg):
+    """Uniform checkpointing recomputes the same levels: identical gradient, J, traces
+    and sum (dmu)^2 as the stored-history adjoint, for any segment length."""
+    c, dt, nt, src, w, rec, obs = _tiny((7, 6, 9), 8, 19, nt=40)
+    g, J, s2, tr = oracle.exact_gradient(c, 1.0, 8, dt, nt, src, w, rec, obs)
+    gc, Jc, s2c, trc = oracle.exact_gradient_ckpt(c, 1.0, 8, dt, nt, src, w, rec, obs, seg=seg)
+    assert np.array_equal(tr, trc) and J == Jc
+    assert np.abs(gc - g).max() <= 1e-12 * np.abs(g).max()
+    assert np.abs(s2c - s2).max() <= 1e-12 * np.abs(s2).max()
+
+
 @pytest.mark.parametrize("shape,order", [((9, 11), 4), ((5, 6, 7), 8)])
 def test_superposition_gap_closed_form(shape, order):
     """K(u+k mu, u+k mu) - K(u,u) = 2k K(u,mu) + k^2 K(mu,mu) (paper Eq.
