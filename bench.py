@@ -1,12 +1,19 @@
 """Throughput of the memory-efficient adjoint sensitivity (forward sweep + superposed
 backward sweep) on one MI355X.
 
-One step = one full gradient: fd_sens_forward (nt fused steps: propagate, inject,
-sample, residual, K(u,u)) + fd_sens_backward (terminal hand-over, nt - 1 fused
-superposed steps with K(v,v), finalisation).  Inputs are resident in HBM before the
-timed region; the observed data come from a forward solve in the unperturbed medium.
+One step = one full gradient.  Single-medium workloads run fd_sens_forward (nt fused
+steps: propagate, inject, sample, residual, K(u,u)) + fd_sens_backward (terminal
+hand-over, nt - 1 fused superposed steps with K(v,v), finalisation); shot batches do
+the same for all shots with one shared accumulator; the uneven-problem batch runs
+fd_adjoint_sensitivity_batched.  Inputs are resident in HBM before the timed region;
+observed data come from a forward solve in the unperturbed medium.  The launch shape
+is autotuned in the untimed setup.
 
-    python bench.py [--steps K] [--warmup W] [--workload layered3d|layered2d] ...
+    python bench.py [--steps K] [--warmup W] [--workload NAME] ...
+
+Workloads: layered3d (default; 1024^3, order 8, nt 3000, one shot), layered2d (2048^2,
+order 8, nt 4000), shots3d (4 shots on 1024^3), shots2d (32 shots on 2048^2),
+problems2d (16 independent layered problems, sides 256..2048).
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build measures one GPU.
 """
@@ -30,39 +37,54 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def bytes_per_update(dtype, acc):
-    """Algorithmic HBM bytes of one fused cell update: read u^n, u^{n-1}, c and the
-    accumulator, write u^{n+1} and the accumulator (the last forward step skips the
-    accumulator)."""
-    f = 8 if dtype == "f64" else 4
-    a = 8 if (acc == "f64" or dtype == "f64") else 4
-    return 4 * f + 2 * a, 4 * f
+def step_bytes(group, acc):
+    """Algorithmic HBM bytes per cell of one fused step launch advancing `group` shots:
+    read u^n, u^{n-1} per shot, c and the accumulator once; write u^{n+1} per shot and
+    the accumulator (the last forward step skips the accumulator)."""
+    a = 8 if acc == "f64" else 4
+    return 12 * group + 4 + 2 * a, 12 * group + 4
 
 
-def make_problem(args, torch, wl):
-    if args.workload == "layered3d":
+def make_single(args, torch, wl):
+    if args.workload in ("layered3d", "shots3d"):
         n = args.n or 1024
         nt = args.nt or 3000
-        p = wl.layered_3d(n=n, nt=nt, device="cuda")
+        shots = None
+        if args.workload == "shots3d":
+            q = n // 4
+            shots = [(a, b) for a in (q, 3 * q) for b in (q, 3 * q)]
+        p = wl.layered_3d(n=n, nt=nt, device="cuda", shots=shots)
         c = p.c.float().contiguous()
         c_ref = p.c_ref.float().contiguous()
-        desc = f"layered3d {n}^3 f32 order-8 nt={nt}, 1 Ricker source, {len(p.rec)} receivers"
-    elif args.workload == "layered2d":
+        desc = f"{args.workload} {n}^3 f32 order-8 nt={nt}, {len(p.src)} shot(s), {len(p.rec)} receivers each"
+    else:
         n = args.n or 2048
         nt = args.nt or 4000
-        p = wl.layered_2d(n=n, nt=nt)
+        cols = None
+        if args.workload == "shots2d":
+            cols = [64 * s + 32 for s in range(32)]
+        p = wl.layered_2d(n=n, nt=nt, src_cols=cols)
         c = torch.as_tensor(p.c, dtype=torch.float32, device="cuda")
         c_ref = torch.as_tensor(p.c_ref, dtype=torch.float32, device="cuda")
-        desc = f"layered2d {n}^2 f32 order-8 nt={nt}, 1 Ricker source, {len(p.rec)} receivers"
-    else:
-        raise SystemExit(f"unknown workload {args.workload}")
+        desc = f"{args.workload} {n}^2 f32 order-8 nt={nt}, {len(p.src)} shot(s), {len(p.rec)} receivers each"
     return p, c, c_ref, desc
 
 
-def cpu_baseline(p, c_dev, args, wl, torch):
+def shot_tags(p, np):
+    """Every source is its own shot; every shot records with the whole receiver line."""
+    ns = len(p.src)
+    if ns == 1:
+        return p.src, p.rec, None, p.wavelet
+    rec = np.tile(p.rec, ns)
+    rec_shot = np.repeat(np.arange(ns, dtype=np.int32), len(p.rec))
+    src_shot = np.arange(ns, dtype=np.int32)
+    return p.src, rec, (src_shot, rec_shot, ns), p.wavelet
+
+
+def cpu_baseline(p, c_dev, wl):
     """The FP64 oracle on a bounded sample of the same workload: a crop of the same
-    medium around the source with the workload's receivers that fall inside it,
-    for a few time steps (forward + superposed backward sweep)."""
+    medium around the first source with the receivers that fall inside it, for a few
+    time steps (forward + superposed backward sweep)."""
     import numpy as np
     import oracle
     shape = p.shape
@@ -91,7 +113,110 @@ def cpu_baseline(p, c_dev, args, wl, torch):
     return {"value": upd / el / 1e9, "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"FP64 oracle, crop {'x'.join(map(str, crop))} of the same medium around the "
-                      f"source, {len(rec)} receivers, nt={nt_s} ({upd:.3g} cell-updates in {el:.1f} s)"}
+                      f"first source, {len(rec)} receivers, nt={nt_s}, one shot "
+                      f"({upd:.3g} cell-updates in {el:.1f} s)"}
+
+
+def run_single(args, np, torch, fdw, wl):
+    p, c, c_ref, desc = make_single(args, torch, wl)
+    src, rec, shots, wav = shot_tags(p, np)
+    nshot = shots[2] if shots else 1
+    log("workload:", desc, f"dt={p.dt:.5g}")
+    w = torch.as_tensor(wav, dtype=torch.float32, device="cuda")
+    best, best_ms = fdw.fd_autotune(p.shape, p.dx, p.order, torch.float32, nshot=nshot, steps=3,
+                                    acc_dtype=args.acc)
+    if args.variant:
+        best = {"variant": args.variant, "chunk": 0, "max_group": 0}
+    log("launch shape:", best, f"{best_ms:.3f} ms/step in the tuner")
+    obs = fdw.fd_forward(c_ref, p.dx, p.order, src, w, rec, p.dt, p.nt, shots=shots)
+    del c_ref
+    torch.cuda.synchronize()
+    st = fdw.SweepState(c, p.nt, len(rec), acc_dtype=args.acc, nshot=nshot)
+    grad = torch.empty_like(c)
+    f_norm = float(np.linalg.norm(wav)) / p.dx ** len(p.shape)
+    holder, timings = {}, []
+    acq = fdw.Acquisition(src, w, rec, *(shots if shots else (None, None, 0)))
+    opts = dict(acc_dtype=args.acc, variant=best["variant"], chunk=best["chunk"],
+                max_group=best["max_group"])
+
+    def one_step(record):
+        tf, tb = fdw.fd_timing(), fdw.fd_timing()
+        J = fdw.fd_sens_forward(c, p.dx, p.order, acq, None, None, p.dt, p.nt, obs, st, timing=tf, **opts)
+        if "k" not in holder:
+            fdag_norm = math.sqrt(2.0 * J / p.dt) / p.dt
+            holder["k"] = args.beta * f_norm / fdag_norm if fdag_norm > 0 else 1.0
+            holder["J"] = J
+        fdw.fd_sens_backward(c, p.dx, p.order, acq, None, None, p.dt, p.nt, holder["k"], st, grad=grad,
+                             timing=tb, **opts)
+        if record:
+            timings.append((tf.fwd_ms, tf.fwd_launches, tb.bwd_ms, tb.bwd_launches))
+
+    elapsed = timed(args, torch, one_step)
+    ncell = int(np.prod(p.shape))
+    upd = ncell * (2 * p.nt - 1) * nshot
+    group = best["max_group"] or 1
+    b_k, b_nok = step_bytes(group, args.acc)
+    ngroups = math.ceil(nshot / group)
+    launches = sum(t[1] + t[3] for t in timings)
+    kern_ms = sum(t[0] + t[2] for t in timings)
+    bytes_all = ncell * ngroups * (b_k * (p.nt - 1) + b_nok + b_k * (p.nt - 1)) * args.steps
+    cfg = {"workload": desc, "grid": list(p.shape), "nt": p.nt, "order": p.order, "shots": nshot,
+           "receivers": len(rec), "accumulator": args.acc, "k": holder["k"], "J": holder["J"],
+           "launch_shape": best, "cell_updates_per_step": upd}
+    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, b_k / group), p, c
+
+
+def run_problems(args, np, torch, fdw, wl):
+    """16 independent layered problems with sides drawn uniformly from 256..2048 (seeded),
+    each with its own medium, dt, source at the top centre and receivers every 4 cells."""
+    rng = np.random.default_rng(33)
+    sides = sorted(int(s) for s in rng.integers(256, 2049, size=16))
+    nt = args.nt or 4000
+    items, ncell_all = [], 0
+    probs = []
+    for i, n in enumerate(sides):
+        p = wl.layered_2d(n=n, nt=nt, seed=100 + i)
+        c = torch.as_tensor(p.c, dtype=torch.float32, device="cuda")
+        c_ref = torch.as_tensor(p.c_ref, dtype=torch.float32, device="cuda")
+        w = torch.as_tensor(p.wavelet, dtype=torch.float32, device="cuda")
+        obs = fdw.fd_forward(c_ref, p.dx, p.order, p.src, w, p.rec, p.dt, nt)
+        J = fdw.fd_misfit(fdw.fd_forward(c, p.dx, p.order, p.src, w, p.rec, p.dt, nt), obs, p.dt)
+        k = args.beta * float(np.linalg.norm(p.wavelet)) / (math.sqrt(2 * J / p.dt) / p.dt)
+        items.append(fdw.Problem(c, p.dx, p.order, p.src, w, p.rec, p.dt, nt, obs, k))
+        probs.append(p)
+        ncell_all += n * n
+    desc = f"problems2d: 16 layered problems, sides {sides[0]}..{sides[-1]}, f32 order-8 nt={nt}"
+    log("workload:", desc)
+    timings = []
+
+    def one_step(record):
+        t = fdw.fd_timing()
+        fdw.fd_adjoint_sensitivity_batched(items, graph=args.graph, timing=t, variant=1, acc_dtype=args.acc)
+        if record:
+            timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
+
+    elapsed = timed(args, torch, one_step)
+    upd = ncell_all * (2 * nt - 1)
+    b_k, b_nok = step_bytes(1, args.acc)
+    launches = sum(t[1] + t[3] for t in timings)
+    kern_ms = sum(t[0] + t[2] for t in timings)
+    bytes_all = ncell_all * (b_k * (nt - 1) + b_nok + b_k * (nt - 1)) * args.steps
+    cfg = {"workload": desc, "sides": sides, "nt": nt, "order": 8, "problems": 16,
+           "accumulator": args.acc, "graph": bool(args.graph), "cell_updates_per_step": upd}
+    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, b_k), probs[0], items[0].c
+
+
+def timed(args, torch, one_step):
+    for i in range(args.warmup):
+        one_step(False)
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step(True)
+        log(f"timed step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
 
 
 def main():
@@ -99,13 +224,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="layered3d", choices=["layered3d", "layered2d"])
+    ap.add_argument("--workload", default="layered3d",
+                    choices=["layered3d", "layered2d", "shots3d", "shots2d", "problems2d"])
     ap.add_argument("--n", type=int, default=0, help="grid side (default: 1024 in 3D, 2048 in 2D)")
     ap.add_argument("--nt", type=int, default=0, help="time steps (default: 3000 in 3D, 4000 in 2D)")
     ap.add_argument("--acc", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0, help="force a tile variant (default: autotuned)")
+    ap.add_argument("--graph", type=int, default=1, help="problems2d: replay sweeps as hipGraphs")
     ap.add_argument("--beta", type=float, default=0.005,
-                    help="k = beta ||f|| / ||f_dagger||, fixed from the first step")
+                    help="k = beta ||f|| / ||fdag||, fixed from the first step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -121,55 +248,10 @@ def main():
 
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    p, c, c_ref, desc = make_problem(args, torch, wl)
-    log("workload:", desc, f"dt={p.dt:.5g}")
-    w = torch.as_tensor(p.wavelet, dtype=torch.float32, device="cuda")
-    obs = fdw.fd_forward(c_ref, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, variant=args.variant)
-    del c_ref
-    torch.cuda.synchronize()
-    st = fdw.SweepState(c, p.nt, len(p.rec), acc_dtype=args.acc)
-    grad = torch.empty_like(c)
-    log(f"setup {time.perf_counter() - t_setup:.1f} s; state "
-        f"{(st.u_a.numel() * 8 + st.acc.numel() * st.acc.element_size()) / 2**30:.1f} GiB")
-    f_norm = float(np.linalg.norm(p.wavelet)) / p.dx ** len(p.shape)
-    k_holder = {}
-    timings = []
-
-    def one_step(record):
-        tf, tb = fdw.fd_timing(), fdw.fd_timing()
-        J = fdw.fd_sens_forward(c, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, obs, st,
-                                acc_dtype=args.acc, variant=args.variant, timing=tf)
-        if "k" not in k_holder:
-            fdag_norm = math.sqrt(2.0 * J / p.dt) / p.dt
-            k_holder["k"] = args.beta * f_norm / fdag_norm if fdag_norm > 0 else 1.0
-            k_holder["J"] = J
-        fdw.fd_sens_backward(c, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, k_holder["k"], st,
-                             grad=grad, acc_dtype=args.acc, variant=args.variant, timing=tb)
-        if record:
-            timings.append((tf.fwd_ms, tf.fwd_launches, tb.bwd_ms, tb.bwd_launches))
-        return J
-
-    for i in range(args.warmup):
-        one_step(False)
-        log(f"warmup step {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        one_step(True)
-        log(f"timed step {i + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    ncell = int(np.prod(p.shape))
-    upd_per_step = ncell * (2 * p.nt - 1)
-    value = upd_per_step * args.steps / elapsed / 1e9
-    b_k, b_nok = bytes_per_update("f32", args.acc)
-    # dominant kernel: the fused step; average algorithmic bytes per launch over a step
-    bytes_step = ncell * (b_k * (p.nt - 1) + b_nok + b_k * (p.nt - 1))
-    launches = sum(t[1] + t[3] for t in timings)
-    kern_ms = sum(t[0] + t[2] for t in timings)
-    avg_ms = kern_ms / launches
-    bytes_launch = bytes_step * args.steps / launches
+    runner = run_problems if args.workload == "problems2d" else run_single
+    upd, elapsed, cfg, (bytes_launch, avg_ms, bpu), p0, c0 = runner(args, np, torch, fdw, wl)
+    log(f"total {time.perf_counter() - t_setup:.1f} s")
+    value = upd * args.steps / elapsed / 1e9
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     out = {
         "metric": "Gcell-updates/s fwd+adjoint sweep",
@@ -184,19 +266,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": desc,
-            "grid": list(p.shape),
-            "nt": p.nt,
-            "order": p.order,
-            "shots": len(p.src),
-            "receivers": len(p.rec),
-            "accumulator": args.acc,
-            "k": k_holder["k"],
-            "J": k_holder["J"],
-            "variant": args.variant,
-            "cell_updates_per_step": upd_per_step,
-        },
+        "config": cfg,
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
@@ -204,15 +274,15 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "kernel": "fdw::step_kernel",
+            "kernel": "fdw::step_kernel" if args.workload != "problems2d" else "fdw::step_multi_kernel",
             "avg_launch_ms": round(avg_ms, 4),
             "bytes_per_launch": bytes_launch,
-            "bytes_per_cell_update": b_k,
+            "bytes_per_shot_cell_update": bpu,
         },
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(p, c, args, wl, torch)
+        out["cpu_baseline"] = cpu_baseline(p0, c0, wl)
     print(json.dumps(out), flush=True)
 
 

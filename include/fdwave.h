@@ -154,6 +154,19 @@ int32_t fd_variant_count(int32_t ndim);
 int fd_variant_info(int32_t ndim, int32_t variant, int32_t* tile_z, int32_t* tile_y,
                     int32_t* threads, int32_t* cells_per_lane);
 
+/* Autotuner: times `steps` fused steps (with accumulation) for every tile variant that
+ * fits the grid, several axis-0 chunk lengths and, for nshot > 1, the shot-group sizes,
+ * on scratch fields of this grid allocated and freed by the call; writes the fastest
+ * (time per shot-cell update) into *best (variant, chunk, max_group; other fields copied
+ * from opts) and remembers it for this process under the key (GPU architecture, HIP
+ * runtime version, ndim, order, dtype, accumulator dtype, shape, shot count).  Calls
+ * whose fd_opts.variant is 0 use a remembered entry of their key (their chunk and
+ * max_group too, unless set).  If the environment variable FDWAVE_TUNE_CACHE names a
+ * file, entries are appended to it as JSON lines and read back on first use.
+ * best_ms (may be NULL) receives the best time per step.  Synchronises `stream`. */
+int fd_autotune(const fd_grid* grid, int32_t nshot, const fd_opts* opts, int32_t steps,
+                fd_opts* best, double* best_ms, void* stream);
+
 /* Forward solve (Alg. 1 forward loop without cost or kernel): traces DEVICE [nt][nrec]
  * receive u^1..u^nt at the receivers.  c DEVICE [ncell] is the wave speed. */
 int fd_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int32_t nt,

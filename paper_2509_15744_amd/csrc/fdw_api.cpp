@@ -9,7 +9,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -72,6 +75,7 @@ struct Geo {
     int chunk = 0;       // requested planes per block (0: library choice)
     int max_group = 0;   // requested shots per launch (0: the variant's largest)
     int graph = 0;
+    bool auto_variant = true;   // the caller left the variant to the library
     int n0, n1, n2;      // internal extents (2D: n1 = 1)
     int64_t ncell;
     double dx, inv_vol;
@@ -105,6 +109,7 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
             if (o->variant < 1 || o->variant > fdw::variant_count(g->ndim))
                 return fail(FD_E_ARG, "variant out of range");
             G.variant = o->variant;
+            G.auto_variant = false;
         }
         G.timing = o->timing;
         if (o->chunk < 0) return fail(FD_E_ARG, "chunk is negative");
@@ -247,8 +252,11 @@ struct Plan {
     int32_t* d_ushot = nullptr;
 };
 
-int make_plan(const Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch& sc, Plan* P)
+void apply_tuned(Geo& G, int nshot);
+
+int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch& sc, Plan* P)
 {
+    if (G.auto_variant) apply_tuned(G, acq ? nshots(acq) : 1);
     fdw::Variant v = fdw::variant_shape(G.ndim, G.variant);
     if (v.tz == 0) return fail(FD_E_ARG, "invalid variant");
     if (G.n2 % v.vz != 0)
@@ -617,6 +625,212 @@ int sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double 
 }
 
 // ---------------------------------------------------------------------------
+// autotuner: remembered launch shapes per (arch, runtime, problem class)
+// ---------------------------------------------------------------------------
+
+struct Tuned {
+    int variant = 1, chunk = 0, group = 1;
+    double ms = 0.0;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Tuned> g_tuned;
+bool g_tune_loaded = false;
+
+std::string device_tag()
+{
+    int dev = 0, rt = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    (void)hipRuntimeGetVersion(&rt);
+    return arch + "|hip" + std::to_string(rt);
+}
+
+std::string tune_key(const Geo& G, int nshot)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|%dd|o%d|%s|acc%s|%dx%dx%d|s%d", device_tag().c_str(), G.ndim,
+             2 * G.r, G.dtype == FD_F64 ? "f64" : "f32", G.acc_dtype == FD_F64 ? "f64" : "f32",
+             G.n0, G.n1, G.n2, nshot);
+    return buf;
+}
+
+const char* tune_file() { return std::getenv("FDWAVE_TUNE_CACHE"); }
+
+// Reads "key" and the integers after "variant", "chunk", "max_group" and "ms" from one
+// JSON line written by tune_save (no general JSON parser is needed for that format).
+bool parse_line(const std::string& ln, std::string* key, Tuned* t)
+{
+    auto str_after = [&](const char* name, std::string* out) {
+        const std::string pat = std::string("\"") + name + "\": \"";
+        size_t p = ln.find(pat);
+        if (p == std::string::npos) return false;
+        p += pat.size();
+        size_t q = ln.find('"', p);
+        if (q == std::string::npos) return false;
+        *out = ln.substr(p, q - p);
+        return true;
+    };
+    auto num_after = [&](const char* name, double* out) {
+        const std::string pat = std::string("\"") + name + "\": ";
+        size_t p = ln.find(pat);
+        if (p == std::string::npos) return false;
+        *out = std::atof(ln.c_str() + p + pat.size());
+        return true;
+    };
+    double v, c, g, ms;
+    if (!str_after("key", key) || !num_after("variant", &v) || !num_after("chunk", &c) ||
+        !num_after("max_group", &g) || !num_after("ms", &ms))
+        return false;
+    t->variant = (int)v;
+    t->chunk = (int)c;
+    t->group = (int)g;
+    t->ms = ms;
+    return true;
+}
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = tune_file();
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string key;
+        Tuned t;
+        if (parse_line(line, &key, &t)) g_tuned[key] = t;   // later lines win
+    }
+    std::fclose(f);
+}
+
+void tune_save_locked(const std::string& key, const Tuned& t)
+{
+    g_tuned[key] = t;
+    const char* path = tune_file();
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"variant\": %d, \"chunk\": %d, \"max_group\": %d, \"ms\": %.6f}\n",
+                 key.c_str(), t.variant, t.chunk, t.group, t.ms);
+    std::fclose(f);
+}
+
+void apply_tuned(Geo& G, int nshot)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tuned.find(tune_key(G, nshot));
+    if (it == g_tuned.end()) return;
+    const fdw::Variant v = fdw::variant_shape(G.ndim, it->second.variant);
+    if (v.tz == 0 || G.n2 % v.vz != 0) return;
+    G.variant = it->second.variant;
+    if (G.chunk == 0) G.chunk = it->second.chunk;
+    if (G.max_group == 0) G.max_group = it->second.group;
+}
+
+int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_opts* best,
+             double* best_ms, hipStream_t s)
+{
+    Geo G;
+    int rc = check_grid(grid, opts, &G);
+    if (rc) return rc;
+    if (!best) return fail(FD_E_ARG, "best is null");
+    if (steps < 1) return fail(FD_E_ARG, "steps must be >= 1");
+    nshot = std::max(nshot, 1);
+    // candidate shapes: variants that fit, shot groups, chunk lengths
+    std::vector<int> groups = {1};
+    if (nshot >= 2) groups.push_back(2);
+    if (nshot >= 4) groups.push_back(4);
+    int gmax = 1;
+    for (int g : groups) gmax = std::max(gmax, g);
+    struct Scoped {
+        std::vector<void*> p;
+        ~Scoped() { for (void* q : p) (void)hipFree(q); }
+    } mem;
+    const size_t es = dsize(G.dtype);
+    void *c = nullptr, *ua = nullptr, *ub = nullptr, *acc = nullptr;
+    HIPCHK(hipMalloc(&c, G.ncell * es)); mem.p.push_back(c);
+    HIPCHK(hipMalloc(&ua, G.ncell * es * gmax)); mem.p.push_back(ua);
+    HIPCHK(hipMalloc(&ub, G.ncell * es * gmax)); mem.p.push_back(ub);
+    HIPCHK(hipMalloc(&acc, G.ncell * dsize(G.acc_dtype))); mem.p.push_back(acc);
+    HIPCHK(hipMemsetAsync(c, 0, G.ncell * es, s));
+    HIPCHK(hipMemsetAsync(ua, 0, G.ncell * es * gmax, s));
+    HIPCHK(hipMemsetAsync(ub, 0, G.ncell * es * gmax, s));
+    HIPCHK(hipMemsetAsync(acc, 0, G.ncell * dsize(G.acc_dtype), s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evs{e0, e1};
+    Tuned bestv;
+    double best_per_shot = 1e300;
+    for (int variant = 1; variant <= fdw::variant_count(G.ndim); ++variant) {
+        const fdw::Variant v = fdw::variant_shape(G.ndim, variant);
+        if (G.n2 % v.vz != 0) continue;
+        std::vector<int> chunks = {0, G.n0, G.n0 / 2, G.n0 / 4, G.n0 / 8, 256, 128, 64};
+        std::sort(chunks.begin(), chunks.end());
+        chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
+        for (int group : groups) {
+            if (group > v.max_shots) continue;
+            for (int chunk : chunks) {
+                if (chunk != 0 && (chunk < 2 * G.r || chunk > G.n0)) continue;
+                Geo T = G;
+                T.variant = variant;
+                T.auto_variant = false;
+                T.chunk = chunk;
+                T.max_group = group;
+                T.timing = nullptr;
+                Scratch sc(s);
+                Plan P;
+                if ((rc = make_plan(T, nullptr, false, s, sc, &P))) return rc;
+                Group gr = P.groups[0];
+                gr.size = group;
+                fdw::StepArgs a = base_args(T, P, c, 0.1);
+                a.acc = acc;
+                a.acc_sign = 1;
+                void *prev = ua, *cur = ub;
+                for (int n = 0; n < steps + 1; ++n) {
+                    if (n == 1) HIPCHK(hipEventRecord(e0, s));
+                    a.ucur = cur;
+                    a.unew = prev;
+                    if ((rc = step(T, P, gr, a, s))) return rc;
+                    std::swap(prev, cur);
+                }
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                const double per_step = ms / steps;
+                if (per_step / group < best_per_shot) {
+                    best_per_shot = per_step / group;
+                    bestv.variant = variant;
+                    bestv.chunk = chunk == 0 ? P.chunk : chunk;
+                    bestv.group = group;
+                    bestv.ms = per_step;
+                }
+            }
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        tune_save_locked(tune_key(G, nshot), bestv);
+    }
+    if (opts) *best = *opts;
+    else std::memset(best, 0, sizeof(*best));
+    best->variant = bestv.variant;
+    best->chunk = bestv.chunk;
+    best->max_group = bestv.group;
+    if (best_ms) *best_ms = bestv.ms;
+    return FD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // batches of independent problems
 // ---------------------------------------------------------------------------
 
@@ -633,6 +847,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         const fd_problem& q = probs[p];
         const std::string who = "problem " + std::to_string(p) + ": ";
         if ((rc = check_grid(&q.grid, opts, &G[p]))) return fail(rc, who + g_err);
+        G[p].auto_variant = false;   // one launch serves every problem: one shape for all
         if (p > 0 && (G[p].ndim != G[0].ndim || G[p].r != G[0].r || G[p].dtype != G[0].dtype))
             return fail(FD_E_ARG, who + "all problems need the same ndim, order and dtype");
         if ((rc = check_time(q.dt, q.nt))) return fail(rc, who + g_err);
@@ -928,6 +1143,13 @@ int fd_adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq
     if ((rc = sens_forward(grid, c, acq, dt, nt, observed, &st, traces_or_null, J_host, opts, s, true)))
         return rc;
     return sens_backward(grid, c, acq, dt, nt, k, &st, 1.0, grad_c, opts, s, true);
+}
+
+int fd_autotune(const fd_grid* grid, int32_t nshot, const fd_opts* opts, int32_t steps,
+                fd_opts* best, double* best_ms, void* stream)
+{
+    g_err.clear();
+    return autotune(grid, nshot, opts, steps, best, best_ms, (hipStream_t)stream);
 }
 
 int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, double* J_host,

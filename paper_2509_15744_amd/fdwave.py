@@ -93,6 +93,7 @@ def _load():
         "fd_sens_backward": ([G, P, A, D, I, D, S, D, P, O, P], ctypes.c_int),
         "fd_adjoint_sensitivity_batched": ([ctypes.POINTER(fd_problem), I, DP, O, P], ctypes.c_int),
         "fd_propagate": ([G, P, P, P, I, O, P], ctypes.c_int),
+        "fd_autotune": ([G, I, O, I, O, DP, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -338,6 +339,18 @@ def fd_adjoint_sensitivity_batched(problems, **opts):
     o = make_opts(**opts)
     _raise(_lib.fd_adjoint_sensitivity_batched(arr, len(problems), J, ctypes.byref(o), _stream()))
     return list(J)
+
+
+def fd_autotune(shape, dx, order, dtype=torch.float32, nshot=1, steps=3, **opts):
+    """Time the launch shapes for this grid class; the library remembers the fastest for
+    later calls with variant 0.  Returns ({variant, chunk, max_group}, ms per step)."""
+    g = make_grid(shape, dx, order, FD_F64 if dtype == torch.float64 else FD_F32)
+    o = make_opts(**opts)
+    best = fd_opts()
+    ms = ctypes.c_double()
+    _raise(_lib.fd_autotune(ctypes.byref(g), int(nshot), ctypes.byref(o), int(steps),
+                            ctypes.byref(best), ctypes.byref(ms), _stream()))
+    return {"variant": best.variant, "chunk": best.chunk, "max_group": best.max_group}, ms.value
 
 
 def fd_propagate(coef, u_prev, u_cur, nsteps, dx, order, **opts):

@@ -152,6 +152,29 @@ def test_batched_problems_match_single_calls(fdw, ndim, graph):
         assert abs(J1 - J_o) < 1e-12 * J_o
 
 
+def test_autotune_picks_a_valid_shape_and_persists(fdw, tmp_path, monkeypatch):
+    """The tuner returns a variant that fits the grid, writes a JSON line to the cache
+    file, and later calls with variant 0 (which take the tuned shape) still agree with
+    the oracle."""
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("FDWAVE_TUNE_CACHE", str(cache))
+    shape = (40, 24, 132)
+    best, ms = fdw.fd_autotune(shape, 1.0, 8, torch.float32, nshot=4, steps=2)
+    say("autotune", best, ms)
+    info = fdw.fd_variant_info(3, best["variant"])
+    assert shape[-1] % info["cells_per_lane"] == 0
+    assert best["max_group"] in (1, 2, 4) and best["chunk"] >= 1 and ms > 0
+    lines = cache.read_text().strip().splitlines()
+    assert lines and '"variant": %d' % best["variant"] in lines[-1]
+    P = _shot_problem(shape, 4, 8, 20, "f32", seed=5)
+    g_o, J_o, _ = _oracle_sum(P, 0.05)
+    f32 = torch.float32
+    g, J = fdw.fd_adjoint_sensitivity(to_dev(P["c"], f32), 1.0, 8, P["src"], to_dev(P["wavelet"], f32),
+                                      P["rec"], P["dt"], P["nt"], to_dev(P["obs"], f32), 0.05,
+                                      shots=(P["src_shot"], P["rec_shot"], 4))
+    assert rel(g.cpu().numpy(), g_o) < 1e-4
+
+
 def test_batched_rejects_mixed_orders(fdw):
     a = wl.small_random((20, 20), order=8, nt=5, dtype="f32", seed=1)
     b = wl.small_random((20, 20), order=4, nt=5, dtype="f32", seed=2)
