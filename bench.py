@@ -126,7 +126,7 @@ def run_single(args, np, torch, fdw, wl):
     best, best_ms = fdw.fd_autotune(p.shape, p.dx, p.order, torch.float32, nshot=nshot, steps=3,
                                     acc_dtype=args.acc)
     if args.variant:
-        best = {"variant": args.variant, "chunk": 0, "max_group": 0}
+        best = {"variant": args.variant, "chunk": args.chunk, "max_group": 0}
     log("launch shape:", best, f"{best_ms:.3f} ms/step in the tuner")
     obs = fdw.fd_forward(c_ref, p.dx, p.order, src, w, rec, p.dt, p.nt, shots=shots)
     del c_ref
@@ -191,7 +191,8 @@ def run_problems(args, np, torch, fdw, wl):
 
     def one_step(record):
         t = fdw.fd_timing()
-        fdw.fd_adjoint_sensitivity_batched(items, graph=args.graph, timing=t, variant=1, acc_dtype=args.acc)
+        fdw.fd_adjoint_sensitivity_batched(items, graph=args.graph, persistent=args.persistent, timing=t,
+                                           variant=1, acc_dtype=args.acc)
         if record:
             timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
 
@@ -202,8 +203,29 @@ def run_problems(args, np, torch, fdw, wl):
     kern_ms = sum(t[0] + t[2] for t in timings)
     bytes_all = ncell_all * (b_k * (nt - 1) + b_nok + b_k * (nt - 1)) * args.steps
     cfg = {"workload": desc, "sides": sides, "nt": nt, "order": 8, "problems": 16,
-           "accumulator": args.acc, "graph": bool(args.graph), "cell_updates_per_step": upd}
+           "accumulator": args.acc, "graph": bool(args.graph), "persistent": bool(args.persistent),
+           "cell_updates_per_step": upd}
     return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, b_k), probs[0], items[0].c
+
+
+def measured_traffic(args):
+    """HBM bytes per accumulating step launch from the committed rocprofv3 counter record
+    of the default workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), or
+    None when this run is another workload or the kernel source changed since."""
+    import hashlib
+    if args.workload != "layered3d" or args.n not in (0, 1024) or args.acc != "f64":
+        return None
+    rec = os.path.join(ROOT, "profiles", "step_kernel_layered3d_1024_traffic.md")
+    src = os.path.join(ROOT, "paper_2509_15744_amd", "csrc", "fdw_step.hip")
+    try:
+        fields = dict(ln.split(": ", 1) for ln in open(rec).read().splitlines()
+                      if ln.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if fields.get("source_sha256", "").strip() != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def timed(args, torch, one_step):
@@ -230,7 +252,9 @@ def main():
     ap.add_argument("--nt", type=int, default=0, help="time steps (default: 3000 in 3D, 4000 in 2D)")
     ap.add_argument("--acc", default="f64", choices=["f64", "f32"])
     ap.add_argument("--variant", type=int, default=0, help="force a tile variant (default: autotuned)")
+    ap.add_argument("--chunk", type=int, default=0, help="with --variant: planes per block (0: library)")
     ap.add_argument("--graph", type=int, default=1, help="problems2d: replay sweeps as hipGraphs")
+    ap.add_argument("--persistent", type=int, default=0, help="problems2d: one cooperative launch per sweep")
     ap.add_argument("--beta", type=float, default=0.005,
                     help="k = beta ||f|| / ||fdag||, fixed from the first step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -273,7 +297,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args),
             "kernel": "fdw::step_kernel" if args.workload != "problems2d" else "fdw::step_multi_kernel",
             "avg_launch_ms": round(avg_ms, 4),
             "bytes_per_launch": bytes_launch,

@@ -112,6 +112,11 @@ typedef struct fd_opts {
     int32_t chunk;      /* planes of axis 0 marched per block; 0 lets the library choose */
     int32_t max_group;  /* shots advanced per launch: 1, 2 or 4 (0: the largest the variant has) */
     int32_t graph;      /* batched calls: 1 replays each sweep as one captured hipGraph */
+    int32_t persistent; /* batched calls: 1 runs each sweep as one cooperative launch whose
+                           resident blocks walk all steps with a grid barrier per step */
+    int32_t barrier_timeout_us; /* persistent launches: longest wait at one grid barrier
+                           before the launch gives up and the call returns FD_E_DEVICE
+                           (0: 2 s) */
 } fd_opts;
 
 /* Caller-owned device state that carries one gradient from its forward sweep
@@ -202,9 +207,12 @@ int fd_sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, doub
 
 /* Alg. 1 for `nprob` independent problems of uneven sizes in lock-step: every time
  * step of all problems is one launch over the union of their tiles (problems that
- * have no step there skip it), the backward sweeps are aligned at their ends, and
- * with opts->graph each sweep is captured once into a hipGraph and replayed as one
- * launch.  J_host [nprob] receives each problem's J.  Needs opts variant 0, 1 or 2. */
+ * have no step there skip it), the backward sweeps are aligned at their ends.  With
+ * opts->graph each sweep is captured once into a hipGraph and replayed as one
+ * launch; with opts->persistent each sweep is one cooperative launch whose resident
+ * blocks walk all its steps with a grid barrier per step (captured in a graph too
+ * when opts->graph is set and the runtime can capture it, else launched directly).
+ * J_host [nprob] receives each problem's J.  Needs opts variant 0, 1 or 2. */
 int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, double* J_host,
                                    const fd_opts* opts, void* stream);
 

@@ -75,6 +75,8 @@ struct Geo {
     int chunk = 0;       // requested planes per block (0: library choice)
     int max_group = 0;   // requested shots per launch (0: the variant's largest)
     int graph = 0;
+    int persistent = 0;
+    int barrier_timeout_us = 0;
     bool auto_variant = true;   // the caller left the variant to the library
     int n0, n1, n2;      // internal extents (2D: n1 = 1)
     int64_t ncell;
@@ -118,6 +120,9 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
             return fail(FD_E_ARG, "max_group must be 0, 1, 2 or 4");
         G.max_group = o->max_group;
         G.graph = o->graph;
+        G.persistent = o->persistent;
+        if (o->barrier_timeout_us < 0) return fail(FD_E_ARG, "barrier_timeout_us is negative");
+        G.barrier_timeout_us = o->barrier_timeout_us;
     }
     if (G.dtype == FD_F64) G.acc_dtype = FD_F64;
     G.n0 = (int)n[0];
@@ -962,7 +967,37 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         HIPCHK(hipStreamCreate(&own.s));
         ws = own.s;
     }
+    // persistent launches: barrier words (arrivals, generation, error flag), zeroed
+    // here, outside any capture, and the bounded wait in device wall-clock ticks
+    unsigned* d_bar = nullptr;
+    long long timeout_ticks = 0;
+    if (G0.persistent) {
+        HIPCHK(sc.get((void**)&d_bar, 4 * sizeof(unsigned)));
+        HIPCHK(hipMemsetAsync(d_bar, 0, 4 * sizeof(unsigned), s));
+        HIPCHK(hipStreamSynchronize(s));
+        int dev = 0, khz = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        const long long us = G0.barrier_timeout_us > 0 ? G0.barrier_timeout_us : 2000000;
+        timeout_ticks = std::max(1LL, us * (long long)khz / 1000);
+    }
+    auto barrier_ok = [&]() -> int {
+        unsigned h[4] = {0, 0, 0, 0};
+        HIPCHK(hipMemcpyAsync(h, d_bar, sizeof(h), hipMemcpyDeviceToHost, ws));
+        HIPCHK(hipStreamSynchronize(ws));
+        if (h[2] != 0)
+            return fail(FD_E_DEVICE, "persistent launch: a grid barrier wait timed out (not all blocks "
+                                     "could be resident); the results are invalid");
+        return FD_OK;
+    };
     auto sweep = [&](int first, int count) -> int {
+        if (G0.persistent) {
+            int grid = 0;
+            HIPCHK(fdw::launch_step_persistent(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant,
+                                               d_tab + (size_t)first * nprob, d_bstart, nprob, total,
+                                               count, d_bar, timeout_ticks, ws, &grid));
+            return FD_OK;
+        }
         for (int i = 0; i < count; ++i)
             HIPCHK(fdw::launch_step_multi(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant,
                                           d_tab + (size_t)(first + i) * nprob, d_bstart, nprob, total, ws));
@@ -981,6 +1016,19 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
             HIPCHK(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
             int rc2 = sweep(first, count);
             hipError_t e = hipStreamEndCapture(ws, &graph);
+            if ((rc2 || e != hipSuccess) && G0.persistent) {
+                // this runtime cannot capture a cooperative launch: the persistent sweep is
+                // a single launch anyway, so run it directly
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                g_err.clear();
+                tm.start();
+                if ((rc = sweep(first, count))) return rc;
+                tm.stop();
+                if ((rc = barrier_ok())) return rc;
+                if (ms) *ms = tm.ms();
+                return FD_OK;
+            }
             if (rc2) { if (graph) (void)hipGraphDestroy(graph); return rc2; }
             HIPCHK(e);
             e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -994,6 +1042,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
             HIPCHK(e);
             HIPCHK(e2);
         }
+        if (G0.persistent && (rc = barrier_ok())) return rc;
         if (ms) *ms = tm.ms();
         return FD_OK;
     };

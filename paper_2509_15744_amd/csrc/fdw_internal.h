@@ -73,6 +73,16 @@ hipError_t launch_step_multi(int ndim, int r, int dtype, int acc_dtype, int vari
                              const StepArgs* d_table, const int32_t* d_block_start, int nprob,
                              int total_blocks, hipStream_t s);
 
+// `nsteps` consecutive steps (table rows of nprob entries each) of several problems in
+// one cooperative launch with a bounded grid barrier between steps.  d_barrier: three
+// zeroed unsigned words (arrivals, generation, error flag); a barrier wait longer than
+// timeout_ticks (device wall clock) sets the error flag and ends the launch early.
+// *grid_used receives the number of blocks launched.
+hipError_t launch_step_persistent(int ndim, int r, int dtype, int acc_dtype, int variant,
+                                  const StepArgs* d_table, const int32_t* d_block_start, int nprob,
+                                  int total_blocks, int nsteps, unsigned* d_barrier,
+                                  long long timeout_ticks, hipStream_t s, int* grid_used);
+
 // Misc kernels.  All return hipError_t of the launch.
 hipError_t launch_speed_stats(int dtype, const void* c, int64_t n, double* d_out3, double* d_part,
                               hipStream_t s);

@@ -58,7 +58,8 @@ class fd_timing(ctypes.Structure):
 class fd_opts(ctypes.Structure):
     _fields_ = [("acc_dtype", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("timing", ctypes.POINTER(fd_timing)), ("chunk", ctypes.c_int32),
-                ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32)]
 
 
 class fd_state(ctypes.Structure):
@@ -177,8 +178,11 @@ class Acquisition:
         return max(self.nshot, 1)
 
 
-def make_opts(acc_dtype=None, variant=0, timing=None, chunk=0, max_group=0, graph=False) -> fd_opts:
+def make_opts(acc_dtype=None, variant=0, timing=None, chunk=0, max_group=0, graph=False,
+              persistent=False, barrier_timeout_us=0) -> fd_opts:
     o = fd_opts()
+    o.persistent = int(bool(persistent))
+    o.barrier_timeout_us = int(barrier_timeout_us)
     if acc_dtype is None or acc_dtype in ("f64", torch.float64, FD_F64):
         o.acc_dtype = FD_F64
     elif acc_dtype in ("f32", torch.float32, FD_F32):

@@ -128,11 +128,13 @@ def _uneven_problems(ndim, nprob, dtype, seed):
     return probs
 
 
-@pytest.mark.parametrize("ndim,graph", [(2, False), (2, True), (3, False), (3, True)])
-def test_batched_problems_match_single_calls(fdw, ndim, graph):
+@pytest.mark.parametrize("ndim,graph,persistent", [
+    (2, False, False), (2, True, False), (3, False, False), (3, True, False),
+    (2, False, True), (3, False, True), (3, True, True)])
+def test_batched_problems_match_single_calls(fdw, ndim, graph, persistent):
     """Uneven-size problems (different shapes, dt, nt, k, acquisitions) in one launch per
-    step: each result equals its own single-problem call bitwise and the oracle to
-    rounding (f64)."""
+    step, or one persistent launch per sweep: each result equals its own single-problem
+    call bitwise and the oracle to rounding (f64)."""
     probs = _uneven_problems(ndim, 6, "f64", seed=ndim)
     f64 = torch.float64
     items, singles, refs = [], [], []
@@ -144,8 +146,8 @@ def test_batched_problems_match_single_calls(fdw, ndim, graph):
                                                   q.meta["k"]))
         refs.append(oracle.superposition_gradient(q.c, 1.0, 8, q.dt, q.nt, q.src, q.wavelet, q.rec,
                                                   obs, q.meta["k"]))
-    say("batched", ndim, "graph", graph, [q.shape for q in probs])
-    Js = fdw.fd_adjoint_sensitivity_batched(items, graph=graph)
+    say("batched", ndim, "graph", graph, "persistent", persistent, [q.shape for q in probs])
+    Js = fdw.fd_adjoint_sensitivity_batched(items, graph=graph, persistent=persistent)
     for it, (g1, J1), (g_o, J_o, _) in zip(items, singles, refs):
         assert torch.equal(it.grad, g1) and Js[items.index(it)] == J1
         assert rel(it.grad.cpu().numpy(), g_o) < 1e-9
@@ -173,6 +175,28 @@ def test_autotune_picks_a_valid_shape_and_persists(fdw, tmp_path, monkeypatch):
                                       P["rec"], P["dt"], P["nt"], to_dev(P["obs"], f32), 0.05,
                                       shots=(P["src_shot"], P["rec_shot"], 4))
     assert rel(g.cpu().numpy(), g_o) < 1e-4
+
+
+def test_persistent_barrier_timeout_is_reported(fdw):
+    """A barrier wait limit of 1 microsecond (forced from the host) expires while other
+    blocks still work on their tiles: every block leaves the launch and the call
+    returns FD_E_DEVICE instead of waiting."""
+    f32 = torch.float32
+    items = []
+    for i, shape in enumerate([(300, 260), (280, 300), (310, 290)]):
+        q = wl.small_random(shape, order=8, nt=6, dtype="f32", seed=40 + i)
+        c, w = to_dev(q.c, f32), to_dev(q.wavelet, f32)
+        obs = torch.zeros((q.nt, len(q.rec)), dtype=f32, device="cuda")
+        items.append(fdw.Problem(c, 1.0, 8, q.src, w, q.rec, q.dt, q.nt, obs, 0.1))
+    say("persistent barrier timeout")
+    with pytest.raises(fdw.FdError) as e:
+        fdw.fd_adjoint_sensitivity_batched(items, persistent=True, barrier_timeout_us=1, chunk=300)
+    assert e.value.code == fdw.FD_E_DEVICE and "timed out" in str(e.value)
+    # the same batch with the default limit completes and matches the per-step launches
+    Js = fdw.fd_adjoint_sensitivity_batched(items, persistent=True, chunk=300)
+    grads = [it.grad.clone() for it in items]
+    Js2 = fdw.fd_adjoint_sensitivity_batched(items, persistent=False, chunk=300)
+    assert Js == Js2 and all(torch.equal(g, it.grad) for g, it in zip(grads, items))
 
 
 def test_batched_rejects_mixed_orders(fdw):
