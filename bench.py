@@ -13,7 +13,14 @@ is autotuned in the untimed setup.
 
 Workloads: layered3d (default; 1024^3, order 8, nt 3000, one shot), layered2d (2048^2,
 order 8, nt 4000), shots3d (4 shots on 1024^3), shots2d (32 shots on 2048^2),
-problems2d (16 independent layered problems, sides 256..2048).
+problems2d (16 independent layered problems, sides 256..2048).  ``--method exact`` times
+the exact re-simulation gradient (fd_adjoint_exact) instead of the superposition.
+
+After the timed region (single-medium workloads, superposition): the gap of the
+gradient to the exact discrete gradient at full size (fd_adjoint_exact on the device),
+and on the 256^3 differentiation workload (order 8, nt 2000) the relative errors of
+the device gradients against the FP64 oracle references stored in tests/golden and
+against central finite differences of the f64 misfit on sampled cells.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build measures one GPU.
 """
@@ -117,6 +124,90 @@ def cpu_baseline(p, c_dev, wl):
                       f"({upd:.3g} cell-updates in {el:.1f} s)"}
 
 
+def rel_dev(a, b):
+    """||a - b|| / ||b|| of two device tensors, accumulated in f64 slab by slab."""
+    num = den = 0.0
+    for i in range(0, a.shape[0], 32):
+        da, db = a[i:i + 32].double(), b[i:i + 32].double()
+        num += float(((da - db) ** 2).sum())
+        den += float((db ** 2).sum())
+    return math.sqrt(num / den) if den > 0 else float("nan")
+
+
+def accuracy_full(args, torch, fdw, p, c, acq, obs, grad, ncell):
+    """Gap of the superposition gradient `grad` to the exact discrete gradient of the
+    same run, both on the device (the exact one by re-simulation)."""
+    g_ex = torch.empty_like(c)
+    t = fdw.fd_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fdw.fd_adjoint_exact(c, p.dx, p.order, acq, None, None, p.dt, p.nt, obs, grad=g_ex, timing=t,
+                         acc_dtype=args.acc)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gap = rel_dev(grad, g_ex)
+    del g_ex
+    return {"gap_vs_exact_resim": gap,
+            "exact_resim_s": round(el, 3),
+            "exact_resim_gcell_updates_per_s": round(ncell * (2 * p.nt - 1) / el / 1e9, 3),
+            "exact_resim_fwd_ms": round(t.fwd_ms, 2), "exact_resim_bwd_ms": round(t.bwd_ms, 2)}
+
+
+def accuracy_256(np, torch, fdw, wl, acc, fd_cells=8):
+    """Device gradients of the 256^3 differentiation workload (smooth speed in [1, 3],
+    order 8, nt 2000, f32) against the oracle's FP64 references in tests/golden (sampled
+    on every 8th cell per axis): Alg. 1 at the same k, the exact discrete adjoint; and the
+    exact gradient against central differences of the f64 misfit (eps 1e-6) on a few
+    sampled cells where |g| >= 1e-3 max |g|."""
+    path = os.path.join(ROOT, "tests", "golden", "smooth3d_256_nt2000.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    k = float(ref["k"])
+    stride = int(ref["stride"])
+    s = (slice(None, None, stride),) * 3
+    p = wl.smooth_3d(n=256, nt=2000)
+
+    def dev(x, dt):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=dt).cuda()
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    f32, f64 = torch.float32, torch.float64
+    c, w, o = dev(p.c, f32), dev(p.wavelet, f32), dev(p.observed, f32)
+    g_ap, J = fdw.fd_adjoint_sensitivity(c, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, o, k,
+                                         acc_dtype=acc)
+    g_ex, _ = fdw.fd_adjoint_exact(c, p.dx, p.order, p.src, w, p.rec, p.dt, p.nt, o, acc_dtype=acc)
+    ap = g_ap[s].double().cpu().numpy()
+    ex = g_ex[s].double().cpu().numpy()
+    ref_ex = ref["exact_sample"]
+    out = {"workload": "smooth3d 256^3 f32 order-8 nt=2000 (speed in [1, 3]), oracle sample stride 8",
+           "k": k,
+           "superposition_vs_oracle_same_k": rel(ap, ref["approx_sample"]),
+           "exact_resim_vs_oracle_exact": rel(ex, ref_ex),
+           "gap_gpu": rel(ap, ref_ex), "gap_oracle": rel(ref["approx_sample"], ref_ex),
+           "J_rel_err": abs(J - float(ref["J"])) / float(ref["J"])}
+    cand = np.argwhere(np.abs(ref_ex) >= 1e-3 * np.abs(ref_ex).max())
+    pick = cand[np.random.default_rng(64).choice(len(cand), size=min(fd_cells, len(cand)), replace=False)]
+    c64, w64, o64 = dev(p.c, f64), dev(p.wavelet, f64), dev(p.observed, f64)
+    errs = []
+    for cell in pick:
+        idx = tuple(int(v) * stride for v in cell)
+        jj = []
+        for sgn in (1.0, -1.0):
+            cp = c64.clone()
+            cp[idx] += sgn * 1e-6
+            tr = fdw.fd_forward(cp, p.dx, p.order, p.src, w64, p.rec, p.dt, p.nt)
+            jj.append(fdw.fd_misfit(tr, o64, p.dt))
+        fd = (jj[0] - jj[1]) / 2e-6
+        errs.append(abs(ex[tuple(cell)] - fd) / abs(fd))
+    out["exact_resim_vs_fd_median"] = float(np.median(errs))
+    out["exact_resim_vs_fd_max"] = float(np.max(errs))
+    out["fd_cells"] = len(errs)
+    return out
+
+
 def run_single(args, np, torch, fdw, wl):
     p, c, c_ref, desc = make_single(args, torch, wl)
     src, rec, shots, wav = shot_tags(p, np)
@@ -139,6 +230,15 @@ def run_single(args, np, torch, fdw, wl):
     opts = dict(acc_dtype=args.acc, variant=best["variant"], chunk=best["chunk"],
                 max_group=best["max_group"])
 
+    def exact_step(record):
+        t = fdw.fd_timing()
+        _, J = fdw.fd_adjoint_exact(c, p.dx, p.order, acq, None, None, p.dt, p.nt, obs, grad=grad,
+                                    timing=t, acc_dtype=args.acc)
+        holder.setdefault("k", None)
+        holder.setdefault("J", J)
+        if record:
+            timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
+
     def one_step(record):
         tf, tb = fdw.fd_timing(), fdw.fd_timing()
         J = fdw.fd_sens_forward(c, p.dx, p.order, acq, None, None, p.dt, p.nt, obs, st, timing=tf, **opts)
@@ -151,19 +251,33 @@ def run_single(args, np, torch, fdw, wl):
         if record:
             timings.append((tf.fwd_ms, tf.fwd_launches, tb.bwd_ms, tb.bwd_launches))
 
-    elapsed = timed(args, torch, one_step)
+    exact = args.method == "exact"
+    elapsed = timed(args, torch, exact_step if exact else one_step)
     ncell = int(np.prod(p.shape))
     upd = ncell * (2 * p.nt - 1) * nshot
-    group = best["max_group"] or 1
-    b_k, b_nok = step_bytes(group, args.acc)
-    ngroups = math.ceil(nshot / group)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    bytes_all = ncell * ngroups * (b_k * (p.nt - 1) + b_nok + b_k * (p.nt - 1)) * args.steps
+    if exact:
+        # forward: one field per launch without accumulator; backward: u and mu together
+        # with the cross accumulator, one launch per shot and step
+        b_fwd, b_bwd = step_bytes(1, args.acc)[1], step_bytes(2, args.acc)[0]
+        bytes_all = ncell * nshot * (b_fwd * p.nt + b_bwd * (p.nt - 1)) * args.steps
+        bpu = (b_fwd + b_bwd) / 2
+    else:
+        group = best["max_group"] or 1
+        b_k, b_nok = step_bytes(group, args.acc)
+        ngroups = math.ceil(nshot / group)
+        bytes_all = ncell * ngroups * (b_k * (p.nt - 1) + b_nok + b_k * (p.nt - 1)) * args.steps
+        bpu = b_k / group
     cfg = {"workload": desc, "grid": list(p.shape), "nt": p.nt, "order": p.order, "shots": nshot,
-           "receivers": len(rec), "accumulator": args.acc, "k": holder["k"], "J": holder["J"],
-           "launch_shape": best, "cell_updates_per_step": upd}
-    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, b_k / group), p, c
+           "receivers": len(rec), "accumulator": args.acc, "method": args.method, "k": holder["k"],
+           "J": holder["J"], "launch_shape": best, "cell_updates_per_step": upd}
+    acc_info = None
+    if not exact and not args.no_accuracy:
+        log("accuracy: exact re-simulation gradient at full size ...")
+        acc_info = {"full_size": accuracy_full(args, torch, fdw, p, c, acq, obs, grad, ncell * nshot)}
+        log("accuracy:", acc_info["full_size"])
+    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, bpu), p, c, acc_info
 
 
 def run_problems(args, np, torch, fdw, wl):
@@ -205,22 +319,34 @@ def run_problems(args, np, torch, fdw, wl):
     cfg = {"workload": desc, "sides": sides, "nt": nt, "order": 8, "problems": 16,
            "accumulator": args.acc, "graph": bool(args.graph), "persistent": bool(args.persistent),
            "cell_updates_per_step": upd}
-    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, b_k), probs[0], items[0].c
+    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, b_k), probs[0], items[0].c, None
+
+
+STEP_KERNEL_SOURCES = ("fdw_internal.h", "fdw_step_body.h", "fdw_step.hip")
+
+
+def step_kernel_sha():
+    """sha256 over the sources of the single-problem step kernel, in this order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_15744_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(args):
     """HBM bytes per accumulating step launch from the committed rocprofv3 counter record
     of the default workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), or
     None when this run is another workload or the kernel source changed since."""
-    import hashlib
-    if args.workload != "layered3d" or args.n not in (0, 1024) or args.acc != "f64":
+    if (args.workload != "layered3d" or args.n not in (0, 1024) or args.acc != "f64"
+            or args.method != "superposition"):
         return None
     rec = os.path.join(ROOT, "profiles", "step_kernel_layered3d_1024_traffic.md")
-    src = os.path.join(ROOT, "paper_2509_15744_amd", "csrc", "fdw_step.hip")
     try:
         fields = dict(ln.split(": ", 1) for ln in open(rec).read().splitlines()
                       if ln.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = step_kernel_sha()
     except (OSError, ValueError):
         return None
     if fields.get("source_sha256", "").strip() != sha:
@@ -257,6 +383,9 @@ def main():
     ap.add_argument("--persistent", type=int, default=0, help="problems2d: one cooperative launch per sweep")
     ap.add_argument("--beta", type=float, default=0.005,
                     help="k = beta ||f|| / ||fdag||, fixed from the first step")
+    ap.add_argument("--method", default="superposition", choices=["superposition", "exact"],
+                    help="single-medium workloads: the gradient that is timed")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -273,7 +402,13 @@ def main():
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
     runner = run_problems if args.workload == "problems2d" else run_single
-    upd, elapsed, cfg, (bytes_launch, avg_ms, bpu), p0, c0 = runner(args, np, torch, fdw, wl)
+    upd, elapsed, cfg, (bytes_launch, avg_ms, bpu), p0, c0, accuracy = runner(args, np, torch, fdw, wl)
+    if accuracy is not None:
+        log("accuracy: 256^3 gradients against the oracle references ...")
+        a256 = accuracy_256(np, torch, fdw, wl, args.acc)
+        if a256 is not None:
+            accuracy["oracle_256"] = a256
+            log("accuracy:", a256)
     log(f"total {time.perf_counter() - t_setup:.1f} s")
     value = upd * args.steps / elapsed / 1e9
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
@@ -304,6 +439,8 @@ def main():
             "bytes_per_shot_cell_update": bpu,
         },
     }
+    if accuracy is not None:
+        out["accuracy"] = accuracy
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p0, c0, wl)

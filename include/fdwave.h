@@ -101,7 +101,7 @@ typedef struct fd_acq {
 typedef struct fd_timing {
     double fwd_ms;          /* device time from the first to the last forward step launch */
     int32_t fwd_launches;   /* forward step launches in that interval */
-    double bwd_ms;          /* the same for the superposed backward sweep */
+    double bwd_ms;          /* the same for the backward sweep (superposed or re-simulation) */
     int32_t bwd_launches;
 } fd_timing;
 
@@ -153,11 +153,13 @@ double fd_cfl_limit(int32_t ndim, int32_t order);
 int32_t fd_variant_count(int32_t ndim);
 
 /* Shape of tile variant `variant` (1..count) for `ndim`: tile width along the contiguous
- * axis and height along axis 1 in cells, threads per block, and cells per lane along the
+ * axis and height along axis 1 in cells, threads per block, cells per lane along the
  * contiguous axis (a variant runs only on grids whose contiguous extent is a multiple of
- * it).  Any output pointer may be NULL.  Returns FD_OK or FD_E_ARG. */
+ * it), and the most wavefields one launch advances together (shots of a group, or the
+ * two fields of the exact re-simulation).  Any output pointer may be NULL.  Returns
+ * FD_OK or FD_E_ARG. */
 int fd_variant_info(int32_t ndim, int32_t variant, int32_t* tile_z, int32_t* tile_y,
-                    int32_t* threads, int32_t* cells_per_lane);
+                    int32_t* threads, int32_t* cells_per_lane, int32_t* max_fields);
 
 /* Autotuner: times `steps` fused steps (with accumulation) for every tile variant that
  * fits the grid, several axis-0 chunk lengths and, for nshot > 1, the shot-group sizes,
@@ -190,6 +192,22 @@ int fd_adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq
                            int32_t nt, const void* observed, double k, void* grad_c,
                            double* J_host, void* traces_or_null, const fd_opts* opts,
                            void* stream);
+
+/* Exact discrete gradient by re-simulation (the alternative to the superposition that the
+ * paper's introduction cites; no stored history, no factor k): a forward sweep with cost
+ * and adjoint force but no kernel accumulation, then one backward sweep that steps u
+ * back from (u^nt, u^{nt-1}) with the same scheme together with the adjoint field mu
+ * (mu^nt = 0, mu^{nt-1} = dt^2 c^2 fdag^nt at the receivers, fdag^n = -(u^n(x_r) -
+ * observed^n_r)/dt) and accumulates sum_n (u^{n+1} - u^n)(mu^{n+1} - mu^n) per cell;
+ * grad_c DEVICE [ncell] = 2 acc / c^3 = dJ/dc of the discrete J, exact up to rounding
+ * (the re-simulated u carries the rounding of the backward recursion).  Arguments as for
+ * fd_adjoint_sensitivity without k; every shot is one two-field launch per step, so
+ * fd_opts.variant must carry two fields (variants 1 and 2; 0 picks one) and
+ * fd_opts.max_group is ignored.  Scratch: four wavefields per shot, the accumulator and
+ * the residuals, allocated stream-ordered and freed by the call.  Synchronises `stream`. */
+int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int32_t nt,
+                     const void* observed, void* grad_c, double* J_host, void* traces_or_null,
+                     const fd_opts* opts, void* stream);
 
 /* First half of fd_adjoint_sensitivity: the forward sweep with cost, adjoint force and
  * K(u,u) accumulation; leaves u^{nt-1}, u^nt, the accumulator and the residuals in

@@ -257,13 +257,18 @@ struct Plan {
     int32_t* d_ushot = nullptr;
 };
 
-void apply_tuned(Geo& G, int nshot);
+bool apply_tuned(Geo& G, int nshot);
 
-int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch& sc, Plan* P)
+// `pairs`: one group per shot carrying two fields, the shot's wavefield in slot 0 (its
+// sources inject there) and its adjoint field in slot 1 (its receivers inject there).
+int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch& sc, Plan* P,
+              bool pairs = false)
 {
     if (G.auto_variant) apply_tuned(G, acq ? nshots(acq) : 1);
     fdw::Variant v = fdw::variant_shape(G.ndim, G.variant);
     if (v.tz == 0) return fail(FD_E_ARG, "invalid variant");
+    if (pairs && v.max_shots < 2)
+        return fail(FD_E_ARG, "variant " + std::to_string(G.variant) + " cannot carry two fields per launch");
     if (G.n2 % v.vz != 0)
         return fail(FD_E_ARG, "variant " + std::to_string(G.variant) +
                                   " needs the contiguous extent to be a multiple of " + std::to_string(v.vz));
@@ -298,9 +303,9 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
         while (sz > gmax || g0 + sz > ns) sz >>= 1;
         Group gr;
         gr.g0 = g0;
-        gr.size = sz;
+        gr.size = pairs ? 2 : sz;
         P->groups.push_back(gr);
-        g0 += sz;
+        g0 += pairs ? 1 : sz;
     }
 
     const int nsrc = acq ? acq->nsrc : 0;
@@ -311,7 +316,13 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
         struct Item { int64_t key; fdw::Event e; };
         std::vector<Item> items;
         auto add = [&](int64_t cell, int kind, int idx, int shot) {
-            if (shot < gr.g0 || shot >= gr.g0 + gr.size) return;
+            int slot = shot - gr.g0;
+            if (pairs) {
+                if (shot != gr.g0) return;
+                slot = kind == fdw::EV_REC ? 1 : 0;
+            } else if (shot < gr.g0 || shot >= gr.g0 + gr.size) {
+                return;
+            }
             const int64_t plane = (int64_t)G.n1 * G.n2;
             const int x = (int)(cell / plane);
             const int64_t rem = cell - (int64_t)x * plane;
@@ -322,7 +333,7 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
             fdw::Event e;
             e.plane = x;
             e.lane = (y - ty * v.ty) * v.tz + (z - tz * v.tz);
-            e.kind = kind | ((shot - gr.g0) << 1);
+            e.kind = kind | (slot << 1);
             e.idx = idx;
             items.push_back({b, e});
         };
@@ -411,6 +422,24 @@ int step(const Geo& G, const Plan& P, const Group& gr, fdw::StepArgs a, hipStrea
     return FD_OK;
 }
 
+// Kernel terms of launch l in a run of `count` consecutive accumulating launches of one
+// sweep (the interval each completes follows the previous launch's): launch l can add
+// its own interval and the one before, so launches 1, 3, 5, ... add pairs and, for odd
+// counts, the last one adds its own alone.  The accumulator is then read and written
+// by every other launch only.  Returns 0 (none), 1 (own interval) or 3 (both).
+int acc_terms(int l, int count)
+{
+    if (l < 0 || l >= count) return 0;
+    if (l & 1) return 3;
+    return l == count - 1 ? 1 : 0;
+}
+
+void set_acc(fdw::StepArgs& a, int terms, int sign)
+{
+    a.acc_sign = terms ? sign : 0;
+    a.acc_prev = terms == 3;
+}
+
 int check_time(double dt, int nt)
 {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FD_E_ARG, "dt must be positive and finite");
@@ -487,7 +516,8 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
         for (int n = 0; n < nt; ++n) {
             a.ucur = cur;
             a.unew = prev;
-            a.acc_sign = (acc && n < nt - 1) ? 1 : 0;   // the last interval is settled at hand-over
+            // intervals 0..nt-2; the last one is settled at hand-over
+            set_acc(a, acc ? acc_terms(n, nt - 1) : 0, 1);
             a.row_src = n;
             a.row_rec = n;
             int rc = step(G, P, gr, a, s);
@@ -520,7 +550,6 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
     const size_t es = dsize(G.dtype);
     fdw::StepArgs a = base_args(G, P, c, dt);
     a.acc = acc;
-    a.acc_sign = -1;
     a.wavelet = acq->wavelet;
     a.nsrc = acq->nsrc;
     a.inject_rec = 1;
@@ -543,6 +572,7 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
             a.unew = vn;
             a.row_src = j;
             a.row_rec = j - 1;
+            set_acc(a, acc_terms(nt - 1 - j, nt - 1), -1);   // intervals nt-2..0
             int rc = step(G, P, gr, a, s);
             if (rc) return rc;
             std::swap(vj, vn);
@@ -626,6 +656,117 @@ int sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double 
     if ((rc = backward_sweep(G, P, c, acq, dt, nt, k, st->u_a, st->u_b, st->acc, st->residual, s)))
         return rc;
     HIPCHK(fdw::launch_finalize(G.dtype, G.acc_dtype, G.ncell, st->acc, c, grad_scale / k, grad, s));
+    return FD_OK;
+}
+
+// Launch shape of the re-simulation backward sweep: a variant that carries two fields
+// per launch (the remembered choice for two shots, else for one shot, when it can).
+int pair_variant(Geo& G)
+{
+    if (G.auto_variant) {
+        if (!apply_tuned(G, 2)) apply_tuned(G, 1);
+        G.auto_variant = false;
+        if (fdw::variant_shape(G.ndim, G.variant).max_shots < 2) {
+            G.variant = (G.n2 % 2 == 0) ? 2 : 1;
+            G.chunk = 0;
+        }
+    }
+    if (fdw::variant_shape(G.ndim, G.variant).max_shots < 2)
+        return fail(FD_E_ARG, "variant " + std::to_string(G.variant) + " cannot carry two fields per launch");
+    G.max_group = 0;
+    return FD_OK;
+}
+
+// Exact discrete gradient without stored history (re-simulation): after a forward sweep
+// without kernel accumulation, u is stepped backward from (u^nt, u^{nt-1}) by the same
+// scheme (time-reversible) together with the adjoint field mu, whose sweep starts from
+// mu^nt = 0, mu^{nt-1} = coef fdag^nt (the exact discrete adjoint that the superposition
+// of Sec. 4 approximates, with the kernel of Eq. kernel2 in its discrete form), and the
+// launch accumulates the cross kernel sum_n (u^{n+1} - u^n)(mu^{n+1} - mu^n); then
+// grad_c = 2 acc / c^3.  Shot s keeps u at slot s and mu at slot nshot + s of the two
+// field buffers.
+int exact_gradient(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int nt,
+                   const void* observed, void* grad, double* J_host, void* traces,
+                   const fd_opts* opts, hipStream_t s)
+{
+    Scratch sc(s);
+    Geo G;
+    int rc = prepare(grid, c, acq, dt, nt, opts, s, sc, &G, true);
+    if (rc) return rc;
+    const size_t es = dsize(G.dtype);
+    const size_t tb = (size_t)nt * acq->nrec * es;
+    if ((rc = check_dev(observed, tb, "observed"))) return rc;
+    if (traces && (rc = check_dev(traces, tb, "traces"))) return rc;
+    if ((rc = check_dev(grad, G.ncell * es, "grad_c"))) return rc;
+    const int ns = nshots(acq);
+    const size_t half = G.ncell * es * ns;
+    void *ua = nullptr, *ub = nullptr, *acc = nullptr, *resid = nullptr;
+    HIPCHK(sc.get(&ua, 2 * half));
+    HIPCHK(sc.get(&ub, 2 * half));
+    HIPCHK(sc.get(&acc, G.ncell * dsize(G.acc_dtype)));
+    HIPCHK(sc.get(&resid, std::max<size_t>(tb, es)));
+
+    Geo Gf = G;
+    Plan Pf;
+    if ((rc = make_plan(Gf, acq, false, s, sc, &Pf))) return rc;
+    if ((rc = forward_sweep(Gf, Pf, c, acq, dt, nt, observed, ua, ub, nullptr, resid, traces, s)))
+        return rc;
+    if (J_host) {
+        double ss = 0.0;
+        if ((rc = misfit_sum(G.dtype, resid, nullptr, nullptr, (int64_t)nt * acq->nrec, s, sc, &ss)))
+            return rc;
+        *J_host = 0.5 * dt * ss;
+        if (!std::isfinite(*J_host)) return fail(FD_E_NONFINITE, "misfit is not finite");
+    }
+
+    Geo Gb = G;
+    if ((rc = pair_variant(Gb))) return rc;
+    Plan Pb;
+    if ((rc = make_plan(Gb, acq, true, s, sc, &Pb, true))) return rc;
+    void* up = nullptr;   // u^{nt-1}
+    void* ul = nullptr;   // u^nt
+    final_levels(ua, ub, nt, &up, &ul);
+    HIPCHK(hipMemsetAsync((char*)up + half, 0, half, s));
+    HIPCHK(hipMemsetAsync((char*)ul + half, 0, half, s));
+    HIPCHK(hipMemsetAsync(acc, 0, G.ncell * dsize(G.acc_dtype), s));
+    const double rec_scale = -1.0 / dt;   // fdag^n = -residual^n / dt
+    if (acq->nrec > 0)
+        HIPCHK(fdw::launch_terminal_exact(G.dtype, G.acc_dtype, Pb.nuniq, Pb.d_ucell, Pb.d_uoff, Pb.d_uidx,
+                                          Pb.d_ushot, 0, ns, G.ncell, (int64_t)G.ncell * ns, c, dt * dt,
+                                          ul, up, acc, (const char*)resid + (size_t)(nt - 1) * acq->nrec * es,
+                                          rec_scale, s));
+    fdw::StepArgs a = base_args(Gb, Pb, c, dt);
+    a.shot_stride = (int64_t)G.ncell * ns;   // slot 1 (mu) of shot s sits nshot fields after its u
+    a.acc = acc;
+    a.acc_cross = 1;
+    a.wavelet = acq->wavelet;
+    a.nsrc = acq->nsrc;
+    a.inject_rec = 1;
+    a.resid = resid;
+    a.nrec = acq->nrec;
+    a.rec_scale = rec_scale;
+    SweepTimer tm(G.timing != nullptr && nt > 1, s);
+    tm.start();
+    for (const Group& gr : Pb.groups) {
+        char* xj = (char*)up + (size_t)gr.g0 * G.ncell * es;   // level j
+        char* xn = (char*)ul + (size_t)gr.g0 * G.ncell * es;   // level j+1, overwritten by j-1
+        for (int j = nt - 1; j >= 1; --j) {
+            a.ucur = xj;
+            a.unew = xn;
+            a.row_src = j;
+            a.row_rec = j - 1;
+            set_acc(a, acc_terms(nt - 1 - j, nt - 1), 1);   // intervals nt-2..0
+            if ((rc = step(Gb, Pb, gr, a, s))) return rc;
+            std::swap(xj, xn);
+        }
+    }
+    tm.stop();
+    if (G.timing) {
+        G.timing->bwd_ms = tm.ms();
+        G.timing->bwd_launches = (nt - 1) * (int)Pb.groups.size();
+    }
+    HIPCHK(fdw::launch_finalize(G.dtype, G.acc_dtype, G.ncell, acc, c, -2.0, grad, s));
+    HIPCHK(hipStreamSynchronize(s));
     return FD_OK;
 }
 
@@ -725,17 +866,19 @@ void tune_save_locked(const std::string& key, const Tuned& t)
     std::fclose(f);
 }
 
-void apply_tuned(Geo& G, int nshot)
+// Applies the remembered launch shape of (G, nshot), if any; returns whether there was one.
+bool apply_tuned(Geo& G, int nshot)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
     auto it = g_tuned.find(tune_key(G, nshot));
-    if (it == g_tuned.end()) return;
+    if (it == g_tuned.end()) return false;
     const fdw::Variant v = fdw::variant_shape(G.ndim, it->second.variant);
-    if (v.tz == 0 || G.n2 % v.vz != 0) return;
+    if (v.tz == 0 || G.n2 % v.vz != 0) return false;
     G.variant = it->second.variant;
     if (G.chunk == 0) G.chunk = it->second.chunk;
     if (G.max_group == 0) G.max_group = it->second.group;
+    return true;
 }
 
 int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_opts* best,
@@ -907,7 +1050,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
             a.ev = P[p].groups[0].d_ev;
             a.active = n < q.nt;
             a.acc = st[p].acc;
-            a.acc_sign = n < q.nt - 1 ? 1 : 0;
+            set_acc(a, acc_terms(n, q.nt - 1), 1);
             a.wavelet = q.acq.wavelet;
             a.nsrc = q.acq.nsrc;
             a.sample = 1;
@@ -931,7 +1074,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
             a.ev = P[p].groups[0].d_ev;
             a.active = j >= 1;
             a.acc = st[p].acc;
-            a.acc_sign = -1;
+            set_acc(a, acc_terms(i, q.nt - 1), -1);
             a.wavelet = q.acq.wavelet;
             a.nsrc = q.acq.nsrc;
             a.inject_rec = 1;
@@ -1097,7 +1240,7 @@ int32_t fd_variant_count(int32_t ndim)
 }
 
 int fd_variant_info(int32_t ndim, int32_t variant, int32_t* tile_z, int32_t* tile_y,
-                    int32_t* threads, int32_t* cells_per_lane)
+                    int32_t* threads, int32_t* cells_per_lane, int32_t* max_fields)
 {
     g_err.clear();
     if (ndim != 2 && ndim != 3) return fail(FD_E_ARG, "ndim must be 2 or 3");
@@ -1107,6 +1250,7 @@ int fd_variant_info(int32_t ndim, int32_t variant, int32_t* tile_z, int32_t* til
     if (tile_y) *tile_y = v.ty;
     if (threads) *threads = v.threads;
     if (cells_per_lane) *cells_per_lane = v.vz;
+    if (max_fields) *max_fields = v.max_shots;
     return FD_OK;
 }
 
@@ -1192,6 +1336,16 @@ int fd_adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq
     if ((rc = sens_forward(grid, c, acq, dt, nt, observed, &st, traces_or_null, J_host, opts, s, true)))
         return rc;
     return sens_backward(grid, c, acq, dt, nt, k, &st, 1.0, grad_c, opts, s, true);
+}
+
+int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int32_t nt,
+                     const void* observed, void* grad_c, double* J_host, void* traces_or_null,
+                     const fd_opts* opts, void* stream)
+{
+    g_err.clear();
+    if (!acq) return fail(FD_E_ARG, "acq is null");
+    return exact_gradient(grid, c, acq, dt, nt, observed, grad_c, J_host, traces_or_null, opts,
+                          (hipStream_t)stream);
 }
 
 int fd_autotune(const fd_grid* grid, int32_t nshot, const fd_opts* opts, int32_t steps,

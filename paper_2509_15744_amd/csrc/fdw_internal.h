@@ -31,6 +31,8 @@ struct StepArgs {
     double dt2;          // dt^2
     int32_t coef_direct; // 1: c already holds dt^2 c^2
     int32_t acc_sign;    // 0: no accumulation, +1: acc += sum_s d_s^2, -1: acc -= ...
+    int32_t acc_cross;   // 1: the sum is over slot pairs, d_0 d_1 (+ d_2 d_3), not squares
+    int32_t acc_prev;    // 1: also add the interval before, d = ucur - unew (on entry)
     int32_t active;      // 0: the problem has no step here (multi-problem launches)
     // events
     const int32_t* blk_off;  // [nblk + 1] ranges into ev
@@ -96,6 +98,16 @@ hipError_t launch_terminal(int dtype, int acc_dtype, int nuniq, const int64_t* u
                            int shot0, int nshots, int64_t shot_stride, const void* c, double dt2,
                            const void* u_last, void* u_prev, void* acc, const void* resid_row,
                            double rec_scale, hipStream_t s);
+// Terminal hand-over of the re-simulation sweep for the shots [shot0, shot0 + nshots):
+// mu^{nt-1} = coef * fdag^{nt} at the receiver cells of each shot (mu^{nt} = 0) and the
+// kernel of the last interval, -(u^nt - u^{nt-1}) mu^{nt-1}.  u_last / u_prev point at
+// the first shot's u; shot s's u sits s * shot_stride further and its mu a further
+// mu_offset elements on.
+hipError_t launch_terminal_exact(int dtype, int acc_dtype, int nuniq, const int64_t* ucell,
+                                 const int32_t* uoff, const int32_t* uidx, const int32_t* ushot,
+                                 int shot0, int nshots, int64_t shot_stride, int64_t mu_offset,
+                                 const void* c, double dt2, const void* u_last, void* u_prev,
+                                 void* acc, const void* resid_row, double rec_scale, hipStream_t s);
 hipError_t launch_finalize(int dtype, int acc_dtype, int64_t n, const void* acc, const void* c,
                            double scale, void* grad, hipStream_t s);
 

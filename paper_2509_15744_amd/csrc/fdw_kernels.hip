@@ -203,6 +203,69 @@ hipError_t launch_terminal(int dtype, int acc_dtype, int nuniq, const int64_t* u
     return hipGetLastError();
 }
 
+// End of the forward sweep for the exact re-simulation sweep, per shot of the group:
+// the adjoint field starts from mu^nt = 0 and mu^{nt-1} = coef * fdag^{nt} (the sum over
+// that shot's receivers in the cell), so the last interval contributes
+// (u^nt - u^{nt-1}) (mu^nt - mu^{nt-1}) = -(u^nt - u^{nt-1}) mu^{nt-1} to the cross kernel.
+// The mu arrays are zero on entry; one thread per distinct receiver cell.
+template <typename T, typename AT>
+__global__ void terminal_exact_kernel(int nuniq, const int64_t* __restrict__ ucell,
+                                      const int32_t* __restrict__ uoff, const int32_t* __restrict__ uidx,
+                                      const int32_t* __restrict__ ushot, int shot0, int nshots,
+                                      int64_t shot_stride, int64_t mu_offset, const T* __restrict__ c,
+                                      T dt2, const T* __restrict__ u_last, T* __restrict__ u_prev,
+                                      AT* __restrict__ acc, const T* __restrict__ resid_row, T rec_scale)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nuniq) return;
+    const int64_t cell = ucell[u];
+    const T cv = c[cell];
+    const T coef = dt2 * cv * cv;
+    AT delta = (AT)0;
+    int q = uoff[u];
+    const int q_end = uoff[u + 1];
+    while (q < q_end) {
+        const int sh = ushot[q];
+        T s = (T)0;
+        int q2 = q;
+        for (; q2 < q_end && ushot[q2] == sh; ++q2) s += rec_scale * resid_row[uidx[q2]];
+        if (sh >= shot0 && sh < shot0 + nshots) {
+            const int64_t o = (int64_t)(sh - shot0) * shot_stride + cell;
+            const T mu = coef * s;
+            u_prev[o + mu_offset] = mu;
+            delta -= (AT)(u_last[o] - u_prev[o]) * (AT)mu;
+        }
+        q = q2;
+    }
+    acc[cell] += delta;
+}
+
+hipError_t launch_terminal_exact(int dtype, int acc_dtype, int nuniq, const int64_t* ucell,
+                                 const int32_t* uoff, const int32_t* uidx, const int32_t* ushot,
+                                 int shot0, int nshots, int64_t shot_stride, int64_t mu_offset,
+                                 const void* c, double dt2, const void* u_last, void* u_prev,
+                                 void* acc, const void* resid_row, double rec_scale, hipStream_t s)
+{
+    if (nuniq <= 0) return hipSuccess;
+    const int bs = 256, gs = (nuniq + bs - 1) / bs;
+    if (dtype == 1)
+        hipLaunchKernelGGL((terminal_exact_kernel<double, double>), dim3(gs), dim3(bs), 0, s, nuniq,
+                           ucell, uoff, uidx, ushot, shot0, nshots, shot_stride, mu_offset,
+                           (const double*)c, dt2, (const double*)u_last, (double*)u_prev,
+                           (double*)acc, (const double*)resid_row, rec_scale);
+    else if (acc_dtype == 1)
+        hipLaunchKernelGGL((terminal_exact_kernel<float, double>), dim3(gs), dim3(bs), 0, s, nuniq,
+                           ucell, uoff, uidx, ushot, shot0, nshots, shot_stride, mu_offset,
+                           (const float*)c, (float)dt2, (const float*)u_last, (float*)u_prev,
+                           (double*)acc, (const float*)resid_row, (float)rec_scale);
+    else
+        hipLaunchKernelGGL((terminal_exact_kernel<float, float>), dim3(gs), dim3(bs), 0, s, nuniq,
+                           ucell, uoff, uidx, ushot, shot0, nshots, shot_stride, mu_offset,
+                           (const float*)c, (float)dt2, (const float*)u_last, (float*)u_prev,
+                           (float*)acc, (const float*)resid_row, (float)rec_scale);
+    return hipGetLastError();
+}
+
 // grad_c = -scale * acc / c^3, with acc = K(u,u) - K(v,v) in the sign convention
 // acc = sum (u^{n+1}-u^n)^2 - sum (v^{n+1}-v^n)^2 and scale = grad_scale / k.
 template <typename T, typename AT>

@@ -1,0 +1,391 @@
+// The fused leapfrog step of fdwave for gfx950 (CDNA4, wave64): the per-tile body
+// shared by the single-problem, multi-problem and persistent kernels.
+//
+// One step of the scheme (paper Sec. 3.1, Eq. FDstencil2 with rho^-1 = 1,
+// kappa = c^2, order-2r Laplacian) over the whole grid, fused with the work that
+// Alg. 1 does per time step: source injection, receiver sampling, the residual /
+// adjoint force and the kernel increments, K(u,u) in the forward loop and K(v,v)
+// in the superposed backward loop (or, for the exact re-simulation sweep, the
+// cross term of u and the adjoint field).  One launch per time step; 2D and 3D
+// share the code.
+//
+// Layout of the work:
+//  * a block owns a tile of the planes normal to axis 0 (3D: TY x WZ cells of
+//    axes 1 and 2; 2D: WZ cells of axis 1) and marches along axis 0 through a
+//    chunk of planes;
+//  * a lane owns VZ consecutive cells of the contiguous axis (WZ = 64 VZ per
+//    wave row), so every global access of a wave is one coalesced row segment
+//    of 256 VZ bytes (f32) issued as dword, dwordx2 or dwordx4 loads;
+//  * a lane advances S shots of the same medium at once: c and the shared
+//    accumulator are read once per cell for all S wavefields;
+//  * each lane keeps the 2r+1 values of its column along axis 0 in registers
+//    (a rotating queue), so axis-0 neighbours cost no extra reads;
+//  * the current plane is staged in LDS with an r-wide halo for the in-plane
+//    neighbours (cross-shaped stencil: no corner halo), double-buffered so one
+//    barrier per plane suffices;
+//  * software pipelining: every load of plane x+1 (queue entry x+1+r, halo,
+//    u^{n-1}, c, accumulator) is issued before plane x is computed, so a whole
+//    plane of work covers the memory latency;
+//  * plane bases are wave-uniform 64-bit pointers, in-plane offsets 32-bit;
+//  * u^{n+1} overwrites u^{n-1} in place and the speed c is read instead of a
+//    stored dt^2 c^2 array, so a step streams four arrays; those streams are read
+//    and written non-temporally, which leaves the cache to the u^n halos;
+//  * block ids are remapped so that consecutive tiles run on the same XCD
+//    (dispatch is round-robin over the 8 XCDs) and share halo rows in its L2.
+//
+// Difference form of the Laplacian, sum_j w_j [(u_{+j} - u_0) + (u_{-j} - u_0)]:
+// L applied to a constant is exactly zero in f32 even though the rounded weights
+// do not sum to zero, which removes the phase drift of the a_0 form.
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fdw_internal.h"
+
+namespace fdw {
+
+
+// Ghost index: half-sample mirror about the wall faces, then clamped into the
+// array (the clamp only matters for tile-overhang lanes, which store nothing).
+__device__ __forceinline__ int ghost(int i, int n)
+{
+    i = i < 0 ? -1 - i : i;
+    i = i >= n ? 2 * n - 1 - i : i;
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <typename T, int V>
+struct Vec { typedef T __attribute__((ext_vector_type(V))) type; };
+template <typename T>
+struct Vec<T, 1> { typedef T type; };
+
+template <typename T, int V>
+__device__ __forceinline__ T el(const typename Vec<T, V>::type& v, int i)
+{
+    if constexpr (V == 1) return v;
+    else return v[i];
+}
+template <typename T, int V>
+__device__ __forceinline__ void set_el(typename Vec<T, V>::type& v, int i, T x)
+{
+    if constexpr (V == 1) v = x;
+    else v[i] = x;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ typename Vec<T, V>::type reversed(const typename Vec<T, V>::type& v)
+{
+    if constexpr (V == 1) return v;
+    else if constexpr (V == 2) return __builtin_shufflevector(v, v, 1, 0);
+    else return __builtin_shufflevector(v, v, 3, 2, 1, 0);
+}
+
+// V consecutive cells of one row starting at z (z and the row length n2 are multiples
+// of V), without a branch around the load.  A lane past the wall (z >= n2) reads the
+// aligned vector that holds its mirrored ghost cells and, when MIRROR, reverses it:
+// cell z + i maps to 2 n2 - 1 - z - i.  Without MIRROR such lanes get in-bounds values
+// they never use.
+template <typename T, int V, bool STREAM, bool MIRROR>
+__device__ __forceinline__ typename Vec<T, V>::type load_row(const T* row, int z, int n2)
+{
+    typedef typename Vec<T, V>::type vec;
+    const bool past = z >= n2;
+    const int zs = max(past ? 2 * n2 - z - V : z, 0);
+    vec v;
+    if constexpr (STREAM) v = __builtin_nontemporal_load((const vec*)(row + zs));
+    else v = *(const vec*)(row + zs);
+    if constexpr (MIRROR && V > 1) v = past ? reversed<T, V>(v) : v;
+    return v;
+}
+
+// Compile-time shape of one kernel variant.
+template <int R, typename T, int NDIM, int TZ, int TY, int RY, int VZ, int S>
+struct Shape {
+    static constexpr int TYT = TY / RY;            // thread rows; a thread owns RY tile rows
+    static constexpr int NT = TZ * TYT;            // threads per block
+    static constexpr int WZ = TZ * VZ;             // tile width in cells
+    static constexpr int RYH = (NDIM == 3) ? R : 0;
+    static constexpr int PADL = VZ * ((R + VZ - 1) / VZ);   // left pad keeps rows VZ-aligned
+    static constexpr int LZ = PADL + WZ + PADL;
+    static constexpr int LSZ = (TY + 2 * RYH) * LZ;          // one plane of one shot
+    static constexpr int HYV = (NDIM == 3) ? 2 * R * TZ : 0; // halo row vectors above and below
+    static constexpr int HZ = 2 * R * TY;                    // halo cells left and right
+    static constexpr int NHY = (HYV + NT - 1) / NT;
+    static constexpr int NHZ = (HZ + NT - 1) / NT;
+    static constexpr int NHY1 = NHY > 0 ? NHY : 1;
+    static constexpr int LDS = 2 * S * LSZ;                  // double buffer, all shots
+};
+
+// One block's share of one step: logical block b of problem `a`.
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int S>
+__device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __restrict__ lds)
+{
+    typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, S> SH;
+    typedef typename Vec<T, VZ>::type vec;
+    typedef typename Vec<AT, VZ>::type avec;
+    constexpr int TYT = SH::TYT, NT = SH::NT, WZ = SH::WZ, RYH = SH::RYH, PADL = SH::PADL;
+    constexpr int LZ = SH::LZ, LSZ = SH::LSZ, HYV = SH::HYV, HZ = SH::HZ;
+    constexpr int NHY = SH::NHY, NHZ = SH::NHZ, NHY1 = SH::NHY1;
+
+    const int tzb = b % a.ntz;
+    const int rest = b / a.ntz;
+    const int tyb = rest % a.nty;
+    const int chb = rest / a.nty;
+
+    const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
+    const int z0 = tzb * WZ, y0 = tyb * TY;
+    const int x0 = chb * a.chunk_len;
+    const int x1 = min(x0 + a.chunk_len, n0);
+    const int tid = threadIdx.x;
+    const int lz = tid % TZ;
+    const int lyt = tid / TZ;
+    const int z = z0 + lz * VZ;              // first cell of this lane
+    const bool zlive = z < n2;
+    const int64_t ps = (int64_t)n1 * n2;
+    const int64_t sst = a.shot_stride;
+
+    const T* __restrict__ ucur = (const T*)a.ucur;
+    T* __restrict__ unew = (T*)a.unew;
+    const T* __restrict__ cc = (const T*)a.c;
+    AT* __restrict__ acc = (AT*)a.acc;
+    const bool use_acc = a.acc_sign != 0;
+    T w[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) w[j] = (T)a.w[j];
+    const T dt2 = (T)a.dt2;
+
+    // own cells: row offset within a plane (ghosted for overhang rows, which never store)
+    int roff[RY], lofs[RY], lane0[RY];
+    bool live[RY];
+#pragma unroll
+    for (int k = 0; k < RY; ++k) {
+        const int ly = lyt + k * TYT;
+        const int y = y0 + ly;
+        roff[k] = ghost(y, n1) * n2;
+        live[k] = zlive && (y < n1);
+        lofs[k] = (ly + RYH) * LZ + PADL + lz * VZ;
+        lane0[k] = ly * WZ + lz * VZ;
+    }
+    // halo rows (3D): LDS slot of the vector and its row offset in the plane
+    int hyl[NHY1], hyr[NHY1], hyz[NHY1];
+#pragma unroll
+    for (int i = 0; i < NHY; ++i) {
+        const int h = tid + i * NT;
+        const int row = h / TZ;
+        const int sy = row < R ? row : row + TY;
+        const int cz = (h % TZ) * VZ;
+        hyl[i] = h < HYV ? sy * LZ + PADL + cz : -1;
+        hyr[i] = ghost(y0 + sy - R, n1) * n2;
+        hyz[i] = z0 + cz;
+    }
+    // halo columns: LDS slot and in-plane offset of single cells
+    int hzl[NHZ], hzg[NHZ];
+#pragma unroll
+    for (int i = 0; i < NHZ; ++i) {
+        const int h = tid + i * NT;
+        const int row = h / (2 * R);
+        const int col = h % (2 * R);
+        const int sz = col < R ? PADL - R + col : PADL + WZ + (col - R);
+        hzl[i] = h < HZ ? (RYH + row) * LZ + sz : -1;
+        const int gy = ghost(y0 + (h < HZ ? row : 0), n1);
+        hzg[i] = gy * n2 + ghost(z0 + sz - PADL, n2);
+    }
+
+    // register queue along axis 0: q[s][k][R + d] = u^n(x + d) of shot s, d in [-R, R]
+    vec q[S][RY][2 * R + 1];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k = 0; k < RY; ++k)
+#pragma unroll
+            for (int d = 0; d < 2 * R + 1; ++d)
+                q[s][k][d] = load_row<T, VZ, false, true>(
+                    ucur + s * sst + (int64_t)ghost(x0 - R + d, n0) * ps + roff[k], z, n2);
+
+    // plane-x operands, loaded one plane ahead
+    vec cu[S][RY], cv[RY], chy[S][NHY1];
+    avec ca[RY];
+    T chz[S][NHZ];
+    {
+        const int64_t xo = (int64_t)x0 * ps;
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                cu[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xo + roff[k], z, n2);
+            cv[k] = load_row<T, VZ, true, false>(cc + xo + roff[k], z, n2);
+            if (use_acc) ca[k] = load_row<AT, VZ, true, false>(acc + xo + roff[k], z, n2);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int i = 0; i < NHY; ++i)
+                if (hyl[i] >= 0) chy[s][i] = load_row<T, VZ, false, true>(ucur + s * sst + xo + hyr[i], hyz[i], n2);
+#pragma unroll
+            for (int i = 0; i < NHZ; ++i) chz[s][i] = hzl[i] >= 0 ? ucur[s * sst + xo + hzg[i]] : (T)0;
+        }
+    }
+
+    int e = a.blk_off[b];
+    const int e_end = a.blk_off[b + 1];
+
+    for (int x = x0; x < x1; ++x) {
+        const int64_t xo = (int64_t)x * ps;
+        // issue the loads of plane x + 1
+        vec nq[S][RY], nu[S][RY], nv[RY], nhy[S][NHY1];
+        avec na[RY];
+        T nhz[S][NHZ];
+        const bool more = x + 1 < x1;
+        if (more) {
+            const int64_t xn = xo + ps;
+            const int64_t xq = (int64_t)ghost(x + 1 + R, n0) * ps;
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    nq[s][k] = load_row<T, VZ, false, true>(ucur + s * sst + xq + roff[k], z, n2);
+                    nu[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xn + roff[k], z, n2);
+                }
+                nv[k] = load_row<T, VZ, true, false>(cc + xn + roff[k], z, n2);
+                if (use_acc) na[k] = load_row<AT, VZ, true, false>(acc + xn + roff[k], z, n2);
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+#pragma unroll
+                for (int i = 0; i < NHY; ++i)
+                    if (hyl[i] >= 0) nhy[s][i] = load_row<T, VZ, false, true>(ucur + s * sst + xn + hyr[i], hyz[i], n2);
+#pragma unroll
+                for (int i = 0; i < NHZ; ++i) nhz[s][i] = hzl[i] >= 0 ? ucur[s * sst + xn + hzg[i]] : (T)0;
+            }
+        }
+
+        // stage plane x of every shot
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            T* L = lds + ((x & 1) * S + s) * LSZ;
+#pragma unroll
+            for (int k = 0; k < RY; ++k) *(vec*)(L + lofs[k]) = q[s][k][R];
+#pragma unroll
+            for (int i = 0; i < NHY; ++i)
+                if (hyl[i] >= 0) *(vec*)(L + hyl[i]) = chy[s][i];
+#pragma unroll
+            for (int i = 0; i < NHZ; ++i)
+                if (hzl[i] >= 0) L[hzl[i]] = chz[s][i];
+        }
+        __syncthreads();
+
+        // events of this plane: [ea, e)
+        const int ea = e;
+        while (e < e_end && a.ev[e].plane == x) ++e;
+
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            if (!live[k]) continue;
+            const int s0 = lofs[k];
+            vec un[S];
+            avec an;
+            const T* L0 = lds + (x & 1) * S * LSZ;
+#pragma unroll
+            for (int i = 0; i < VZ; ++i) {
+                const T cvi = el<T, VZ>(cv[k], i);
+                const T coef = a.coef_direct ? cvi : dt2 * cvi * cvi;
+                AT dsum = (AT)0, dpair = (AT)0, dpair_p = (AT)0;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const T* L = L0 + s * LSZ;
+                    const T u0 = el<T, VZ>(q[s][k][R], i);
+                    T lap = (T)0;
+#pragma unroll
+                    for (int j = 1; j <= R; ++j)
+                        lap += w[j - 1] * ((el<T, VZ>(q[s][k][R + j], i) - u0) + (el<T, VZ>(q[s][k][R - j], i) - u0));
+                    if (NDIM == 3) {
+#pragma unroll
+                        for (int j = 1; j <= R; ++j)
+                            lap += w[j - 1] * ((L[s0 + i + j * LZ] - u0) + (L[s0 + i - j * LZ] - u0));
+                    }
+#pragma unroll
+                    for (int j = 1; j <= R; ++j)
+                        lap += w[j - 1] * ((L[s0 + i + j] - u0) + (L[s0 + i - j] - u0));
+
+                    if (ea != e) {   // block-uniform: a source or receiver lies in this plane
+                        T f = (T)0;
+                        for (int v = ea; v < e; ++v) {
+                            const Event ev = a.ev[v];
+                            if (ev.lane != lane0[k] + i || ev_shot(ev.kind) != s) continue;
+                            if (ev_kind(ev.kind) == EV_SRC)
+                                f += ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
+                            else if (a.inject_rec)
+                                f += (T)a.rec_scale * ((const T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
+                        }
+                        lap += f;
+                    }
+
+                    const T uni = (u0 + u0) - el<T, VZ>(cu[s][k], i) + coef * lap;
+                    set_el<T, VZ>(un[s], i, uni);
+                    // kernel terms: the interval this launch completes and, with acc_prev,
+                    // the one before it (its two ends are already in registers)
+                    const AT d = (AT)(uni - u0);
+                    const AT dp = a.acc_prev ? (AT)(u0 - el<T, VZ>(cu[s][k], i)) : (AT)0;
+                    if (a.acc_cross) {   // exact re-simulation: slots (2p, 2p+1) hold (u, mu)
+                        if (s & 1) dsum += dpair * d + dpair_p * dp;
+                        else { dpair = d; dpair_p = dp; }
+                    } else {
+                        dsum += d * d + dp * dp;
+                    }
+                    if (a.sample && ea != e) {
+                        for (int v = ea; v < e; ++v) {
+                            const Event ev = a.ev[v];
+                            if (ev.lane != lane0[k] + i || ev.kind != (EV_REC | (s << 1))) continue;
+                            const int64_t o = (int64_t)a.row_rec * a.nrec + ev.idx;
+                            if (a.traces) ((T*)a.traces)[o] = uni;
+                            if (a.resid) ((T*)a.resid)[o] = uni - ((const T*)a.obs)[o];
+                        }
+                    }
+                }
+                if (use_acc) {
+                    const AT ai = el<AT, VZ>(ca[k], i);
+                    set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + dsum : ai - dsum);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                __builtin_nontemporal_store(un[s], (vec*)(unew + s * sst + xo + roff[k] + z));
+            if (use_acc) __builtin_nontemporal_store(an, (avec*)(acc + xo + roff[k] + z));
+        }
+
+        // rotate to plane x + 1
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+#pragma unroll
+                    for (int d = 0; d < 2 * R; ++d) q[s][k][d] = q[s][k][d + 1];
+                    q[s][k][2 * R] = nq[s][k];
+                    cu[s][k] = nu[s][k];
+                }
+                cv[k] = nv[k];
+                if (use_acc) ca[k] = na[k];
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+#pragma unroll
+                for (int i = 0; i < NHY; ++i) chy[s][i] = nhy[s][i];
+#pragma unroll
+                for (int i = 0; i < NHZ; ++i) chz[s][i] = nhz[s][i];
+            }
+        }
+    }
+}
+
+// XCD-aware logical block id: hardware block i runs on XCD i % 8, so consecutive
+// logical blocks (neighbouring tiles) go to the same XCD.
+__device__ __forceinline__ int logical_block(int nblk)
+{
+    const int per = (nblk + 7) >> 3;
+    const int hb = blockIdx.x;
+    return (hb & 7) * per + (hb >> 3);
+}
+
+}  // namespace fdw

@@ -86,10 +86,11 @@ def _load():
         "fd_last_error": ([], ctypes.c_char_p),
         "fd_cfl_limit": ([I, I], D),
         "fd_variant_count": ([I], I),
-        "fd_variant_info": ([I, I, _I32P, _I32P, _I32P, _I32P], ctypes.c_int),
+        "fd_variant_info": ([I, I, _I32P, _I32P, _I32P, _I32P, _I32P], ctypes.c_int),
         "fd_forward": ([G, P, A, D, I, P, O, P], ctypes.c_int),
         "fd_misfit": ([I, I, I, D, P, P, P, DP, P], ctypes.c_int),
         "fd_adjoint_sensitivity": ([G, P, A, D, I, P, D, P, DP, P, O, P], ctypes.c_int),
+        "fd_adjoint_exact": ([G, P, A, D, I, P, P, DP, P, O, P], ctypes.c_int),
         "fd_sens_forward": ([G, P, A, D, I, P, S, P, DP, O, P], ctypes.c_int),
         "fd_sens_backward": ([G, P, A, D, I, D, S, D, P, O, P], ctypes.c_int),
         "fd_adjoint_sensitivity_batched": ([ctypes.POINTER(fd_problem), I, DP, O, P], ctypes.c_int),
@@ -207,10 +208,11 @@ def fd_variant_count(ndim: int) -> int:
 
 
 def fd_variant_info(ndim: int, variant: int) -> dict:
-    """Tile shape of a kernel variant: tile_z, tile_y, threads, cells_per_lane."""
-    out = [ctypes.c_int32() for _ in range(4)]
+    """Tile shape of a kernel variant: tile_z, tile_y, threads, cells_per_lane, max_fields."""
+    out = [ctypes.c_int32() for _ in range(5)]
     _raise(_lib.fd_variant_info(int(ndim), int(variant), *[ctypes.byref(o) for o in out]))
-    return dict(zip(("tile_z", "tile_y", "threads", "cells_per_lane"), (o.value for o in out)))
+    return dict(zip(("tile_z", "tile_y", "threads", "cells_per_lane", "max_fields"),
+                    (o.value for o in out)))
 
 
 def variants_for(shape) -> list:
@@ -263,6 +265,21 @@ def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k,
                                        int(nt), _dev(observed, "observed"), float(k),
                                        _dev(grad, "grad"), ctypes.byref(J), _dev(traces, "traces"),
                                        ctypes.byref(o), _stream()))
+    return grad, J.value
+
+
+def fd_adjoint_exact(c, dx, order, src, wavelet, rec, dt, nt, observed, grad=None, traces=None,
+                     shots=None, **opts):
+    """(grad_c, J) of the exact discrete adjoint by re-simulation (no factor k)."""
+    acq = _acq(src, wavelet, rec, shots)
+    if grad is None:
+        grad = torch.empty_like(c)
+    g = make_grid(c.shape, dx, order, _dtype_code(c))
+    o = make_opts(**opts)
+    J = ctypes.c_double()
+    _raise(_lib.fd_adjoint_exact(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt),
+                                 _dev(observed, "observed"), _dev(grad, "grad"), ctypes.byref(J),
+                                 _dev(traces, "traces"), ctypes.byref(o), _stream()))
     return grad, J.value
 
 

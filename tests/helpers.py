@@ -55,3 +55,25 @@ class OracleCase:
 @functools.lru_cache(maxsize=16)
 def cached_case(key, builder, k=None, gap=None, exact=True):
     return OracleCase(builder(), k=k, gap=gap, exact=exact)
+
+
+def shot_problem(shape, nshot, order, nt, dtype, seed):
+    """One medium, nshot shots: each shot has 1-2 sources and 3-5 receivers of its own."""
+    rng = np.random.default_rng(seed)
+    c = 1.0 + rng.random(shape)
+    dt = 0.4 * oracle.cfl_limit(len(shape), order) / c.max()
+    n = int(np.prod(shape))
+    src, src_shot, rec, rec_shot = [], [], [], []
+    for s in range(nshot):
+        for _ in range(1 + s % 2):
+            src.append(rng.integers(n)); src_shot.append(s)
+        for _ in range(3 + s % 3):
+            rec.append(rng.integers(n)); rec_shot.append(s)
+    rec.append(rec[0]); rec_shot.append(rec_shot[0])           # a duplicate receiver
+    rec.append(src[-1]); rec_shot.append(src_shot[-1])         # a receiver on a source
+    src, rec = np.array(src, np.int64), np.array(rec, np.int64)
+    src_shot, rec_shot = np.array(src_shot, np.int32), np.array(rec_shot, np.int32)
+    wavelet = rng.standard_normal((nt, len(src)))
+    obs = 0.01 * rng.standard_normal((nt, len(rec)))
+    return dict(shape=shape, order=order, nt=nt, dtype=dtype, c=c, dt=dt, src=src, rec=rec,
+                src_shot=src_shot, rec_shot=rec_shot, wavelet=wavelet, obs=obs, nshot=nshot)

@@ -110,6 +110,28 @@ def test_sensitivity_rejects_bad_k(fdw):
         assert "k must be" in fdw.lib().fd_last_error().decode()
 
 
+def test_exact_validation(fdw):
+    """fd_adjoint_exact rejects missing grid, acquisition and speed before any device work."""
+    g = fdw.make_grid((16, 16), 1.0, 4, fdw.FD_F64)
+    a = fdw.fd_acq()
+    J = ctypes.c_double()
+    f = fdw.lib().fd_adjoint_exact
+    assert f(None, None, ctypes.byref(a), 0.1, 10, None, None, ctypes.byref(J), None, None, None) == fdw.FD_E_ARG
+    assert f(ctypes.byref(g), None, None, 0.1, 10, None, None, ctypes.byref(J), None, None, None) == fdw.FD_E_ARG
+    assert "acq is null" in fdw.lib().fd_last_error().decode()
+    assert f(ctypes.byref(g), None, ctypes.byref(a), 0.1, 10, None, None, ctypes.byref(J), None, None,
+             None) == fdw.FD_E_ARG
+    assert "c is null" in fdw.lib().fd_last_error().decode()
+    assert f(ctypes.byref(g), None, ctypes.byref(a), 0.1, 0, None, None, ctypes.byref(J), None, None,
+             None) == fdw.FD_E_ARG
+
+
+def test_variant_info_reports_fields_per_launch(fdw):
+    for nd in (2, 3):
+        fields = [fdw.fd_variant_info(nd, v)["max_fields"] for v in range(1, fdw.fd_variant_count(nd) + 1)]
+        assert fields[0] == 4 and fields[1] == 4 and set(fields) <= {1, 2, 4}
+
+
 def test_misfit_validation(fdw):
     J = ctypes.c_double()
     assert fdw.lib().fd_misfit(10, 3, 5, 0.1, None, None, None, ctypes.byref(J), None) == fdw.FD_E_ARG

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_2509_15744_amd import workloads as wl
-from helpers import rel, say, to_dev
+from helpers import rel, say, shot_problem, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -17,28 +17,6 @@ def fdw():
     assert torch.cuda.is_available(), "the gpu tests need a HIP device"
     from paper_2509_15744_amd import fdwave
     return fdwave
-
-
-def _shot_problem(shape, nshot, order, nt, dtype, seed):
-    """One medium, nshot shots: each shot has 1-2 sources and 3-5 receivers of its own."""
-    rng = np.random.default_rng(seed)
-    c = 1.0 + rng.random(shape)
-    dt = 0.4 * oracle.cfl_limit(len(shape), order) / c.max()
-    n = int(np.prod(shape))
-    src, src_shot, rec, rec_shot = [], [], [], []
-    for s in range(nshot):
-        for _ in range(1 + s % 2):
-            src.append(rng.integers(n)); src_shot.append(s)
-        for _ in range(3 + s % 3):
-            rec.append(rng.integers(n)); rec_shot.append(s)
-    rec.append(rec[0]); rec_shot.append(rec_shot[0])           # a duplicate receiver
-    rec.append(src[-1]); rec_shot.append(src_shot[-1])         # a receiver on a source
-    src, rec = np.array(src, np.int64), np.array(rec, np.int64)
-    src_shot, rec_shot = np.array(src_shot, np.int32), np.array(rec_shot, np.int32)
-    wavelet = rng.standard_normal((nt, len(src)))
-    obs = 0.01 * rng.standard_normal((nt, len(rec)))
-    return dict(shape=shape, order=order, nt=nt, dtype=dtype, c=c, dt=dt, src=src, rec=rec,
-                src_shot=src_shot, rec_shot=rec_shot, wavelet=wavelet, obs=obs, nshot=nshot)
 
 
 def _oracle_sum(P, k):
@@ -67,7 +45,7 @@ def _oracle_sum(P, k):
 ])
 def test_shots_match_oracle_sum(fdw, shape, nshot, order, max_group):
     """f64: the shot batch equals the sum of per-shot oracle runs (J, traces, gradient)."""
-    P = _shot_problem(shape, nshot, order, 33, "f64", seed=nshot + len(shape))
+    P = shot_problem(shape, nshot, order, 33, "f64", seed=nshot + len(shape))
     k = 0.05
     g_o, J_o, tr_o = _oracle_sum(P, k)
     f64 = torch.float64
@@ -87,7 +65,7 @@ def test_shots_match_oracle_sum(fdw, shape, nshot, order, max_group):
 def test_shots_f32_and_split(fdw):
     """f32 shot batch within 1e-4 of the oracle; the split forward/backward pair with
     caller-owned [nshot][ncell] state gives the fused call's result bitwise."""
-    P = _shot_problem((21, 16, 64), 4, 8, 60, "f32", seed=3)
+    P = shot_problem((21, 16, 64), 4, 8, 60, "f32", seed=3)
     k = 0.05
     g_o, J_o, _ = _oracle_sum(P, k)
     f32 = torch.float32
@@ -103,7 +81,7 @@ def test_shots_f32_and_split(fdw):
 
 
 def test_shot_tags_are_validated(fdw):
-    P = _shot_problem((10, 10, 16), 2, 4, 5, "f32", seed=1)
+    P = shot_problem((10, 10, 16), 2, 4, 5, "f32", seed=1)
     bad = P["rec_shot"].copy()
     bad[0] = 2
     f32 = torch.float32
@@ -168,7 +146,7 @@ def test_autotune_picks_a_valid_shape_and_persists(fdw, tmp_path, monkeypatch):
     assert best["max_group"] in (1, 2, 4) and best["chunk"] >= 1 and ms > 0
     lines = cache.read_text().strip().splitlines()
     assert lines and '"variant": %d' % best["variant"] in lines[-1]
-    P = _shot_problem(shape, 4, 8, 20, "f32", seed=5)
+    P = shot_problem(shape, 4, 8, 20, "f32", seed=5)
     g_o, J_o, _ = _oracle_sum(P, 0.05)
     f32 = torch.float32
     g, J = fdw.fd_adjoint_sensitivity(to_dev(P["c"], f32), 1.0, 8, P["src"], to_dev(P["wavelet"], f32),
