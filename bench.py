@@ -45,11 +45,25 @@ def log(*a):
 
 
 def step_bytes(group, acc):
-    """Algorithmic HBM bytes per cell of one fused step launch advancing `group` shots:
-    read u^n, u^{n-1} per shot, c and the accumulator once; write u^{n+1} per shot and
-    the accumulator (the last forward step skips the accumulator)."""
+    """Algorithmic HBM bytes per cell of one fused step launch advancing `group` fields:
+    read u^n, u^{n-1} per field and c once, write u^{n+1} per field; a launch that adds
+    kernel terms also reads and writes the accumulator once.  Returns (with, without)."""
     a = 8 if acc == "f64" else 4
     return 12 * group + 4 + 2 * a, 12 * group + 4
+
+
+def accumulating_launches(nt):
+    """Launches of one sweep that touch the accumulator: each sweep accumulates nt - 1
+    intervals, two per launch on every other launch (one alone at the end of an odd
+    count), i.e. ceil((nt - 1) / 2) of them."""
+    return nt // 2
+
+
+def gradient_bytes(nt, fwd, bwd):
+    """Algorithmic bytes per cell of the step launches of one gradient: nt forward and
+    nt - 1 backward launches; fwd and bwd are (with, without) accumulator bytes."""
+    na = accumulating_launches(nt)
+    return (na * fwd[0] + (nt - na) * fwd[1]) + (na * bwd[0] + (nt - 1 - na) * bwd[1])
 
 
 def make_single(args, torch, wl):
@@ -209,22 +223,25 @@ def accuracy_256(np, torch, fdw, wl, acc, fd_cells=8):
 
 
 def run_single(args, np, torch, fdw, wl):
+    from paper_2509_15744_amd import calibrate
     p, c, c_ref, desc = make_single(args, torch, wl)
     src, rec, shots, wav = shot_tags(p, np)
     nshot = shots[2] if shots else 1
     log("workload:", desc, f"dt={p.dt:.5g}")
     w = torch.as_tensor(wav, dtype=torch.float32, device="cuda")
-    best, best_ms = fdw.fd_autotune(p.shape, p.dx, p.order, torch.float32, nshot=nshot, steps=3,
-                                    acc_dtype=args.acc)
     if args.variant:
         best = {"variant": args.variant, "chunk": args.chunk, "max_group": 0}
-    log("launch shape:", best, f"{best_ms:.3f} ms/step in the tuner")
+        log("launch shape (given):", best)
+    else:
+        best, best_ms = fdw.fd_autotune(p.shape, p.dx, p.order, torch.float32, nshot=nshot, steps=4,
+                                        acc_dtype=args.acc)
+        log("launch shape:", best, f"{best_ms:.3f} ms/step in the tuner")
     obs = fdw.fd_forward(c_ref, p.dx, p.order, src, w, rec, p.dt, p.nt, shots=shots)
     del c_ref
     torch.cuda.synchronize()
     st = fdw.SweepState(c, p.nt, len(rec), acc_dtype=args.acc, nshot=nshot)
     grad = torch.empty_like(c)
-    f_norm = float(np.linalg.norm(wav)) / p.dx ** len(p.shape)
+    w_norm = float(np.linalg.norm(wav))
     holder, timings = {}, []
     acq = fdw.Acquisition(src, w, rec, *(shots if shots else (None, None, 0)))
     opts = dict(acc_dtype=args.acc, variant=best["variant"], chunk=best["chunk"],
@@ -243,8 +260,7 @@ def run_single(args, np, torch, fdw, wl):
         tf, tb = fdw.fd_timing(), fdw.fd_timing()
         J = fdw.fd_sens_forward(c, p.dx, p.order, acq, None, None, p.dt, p.nt, obs, st, timing=tf, **opts)
         if "k" not in holder:
-            fdag_norm = math.sqrt(2.0 * J / p.dt) / p.dt
-            holder["k"] = args.beta * f_norm / fdag_norm if fdag_norm > 0 else 1.0
+            holder["k"] = calibrate.auto_k(J, p.dt, w_norm, p.dx, len(p.shape), args.beta)
             holder["J"] = J
         fdw.fd_sens_backward(c, p.dx, p.order, acq, None, None, p.dt, p.nt, holder["k"], st, grad=grad,
                              timing=tb, **opts)
@@ -258,17 +274,18 @@ def run_single(args, np, torch, fdw, wl):
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
     if exact:
-        # forward: one field per launch without accumulator; backward: u and mu together
-        # with the cross accumulator, one launch per shot and step
-        b_fwd, b_bwd = step_bytes(1, args.acc)[1], step_bytes(2, args.acc)[0]
-        bytes_all = ncell * nshot * (b_fwd * p.nt + b_bwd * (p.nt - 1)) * args.steps
-        bpu = (b_fwd + b_bwd) / 2
+        # forward: one field per launch, no accumulator; backward: u and mu together with
+        # the cross accumulator, one launch per shot and step
+        nof = step_bytes(1, args.acc)[1]
+        per_cell = gradient_bytes(p.nt, (nof, nof), step_bytes(2, args.acc))
+        bytes_all = ncell * nshot * per_cell * args.steps
+        bpu = per_cell / (2 * p.nt - 1)
     else:
         group = best["max_group"] or 1
-        b_k, b_nok = step_bytes(group, args.acc)
         ngroups = math.ceil(nshot / group)
-        bytes_all = ncell * ngroups * (b_k * (p.nt - 1) + b_nok + b_k * (p.nt - 1)) * args.steps
-        bpu = b_k / group
+        per_cell = gradient_bytes(p.nt, step_bytes(group, args.acc), step_bytes(group, args.acc))
+        bytes_all = ncell * ngroups * per_cell * args.steps
+        bpu = per_cell / (2 * p.nt - 1) / group
     cfg = {"workload": desc, "grid": list(p.shape), "nt": p.nt, "order": p.order, "shots": nshot,
            "receivers": len(rec), "accumulator": args.acc, "method": args.method, "k": holder["k"],
            "J": holder["J"], "launch_shape": best, "cell_updates_per_step": upd}
@@ -283,6 +300,7 @@ def run_single(args, np, torch, fdw, wl):
 def run_problems(args, np, torch, fdw, wl):
     """16 independent layered problems with sides drawn uniformly from 256..2048 (seeded),
     each with its own medium, dt, source at the top centre and receivers every 4 cells."""
+    from paper_2509_15744_amd import calibrate
     rng = np.random.default_rng(33)
     sides = sorted(int(s) for s in rng.integers(256, 2049, size=16))
     nt = args.nt or 4000
@@ -295,7 +313,7 @@ def run_problems(args, np, torch, fdw, wl):
         w = torch.as_tensor(p.wavelet, dtype=torch.float32, device="cuda")
         obs = fdw.fd_forward(c_ref, p.dx, p.order, p.src, w, p.rec, p.dt, nt)
         J = fdw.fd_misfit(fdw.fd_forward(c, p.dx, p.order, p.src, w, p.rec, p.dt, nt), obs, p.dt)
-        k = args.beta * float(np.linalg.norm(p.wavelet)) / (math.sqrt(2 * J / p.dt) / p.dt)
+        k = calibrate.auto_k(J, p.dt, float(np.linalg.norm(p.wavelet)), p.dx, 2, args.beta)
         items.append(fdw.Problem(c, p.dx, p.order, p.src, w, p.rec, p.dt, nt, obs, k))
         probs.append(p)
         ncell_all += n * n
@@ -312,14 +330,16 @@ def run_problems(args, np, torch, fdw, wl):
 
     elapsed = timed(args, torch, one_step)
     upd = ncell_all * (2 * nt - 1)
-    b_k, b_nok = step_bytes(1, args.acc)
+    b = step_bytes(1, args.acc)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    bytes_all = ncell_all * (b_k * (nt - 1) + b_nok + b_k * (nt - 1)) * args.steps
+    per_cell = gradient_bytes(nt, b, b)
+    bytes_all = ncell_all * per_cell * args.steps
     cfg = {"workload": desc, "sides": sides, "nt": nt, "order": 8, "problems": 16,
            "accumulator": args.acc, "graph": bool(args.graph), "persistent": bool(args.persistent),
            "cell_updates_per_step": upd}
-    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, b_k), probs[0], items[0].c, None
+    return (upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, per_cell / (2 * nt - 1)),
+            probs[0], items[0].c, None)
 
 
 STEP_KERNEL_SOURCES = ("fdw_internal.h", "fdw_step_body.h", "fdw_step.hip")

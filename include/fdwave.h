@@ -161,7 +161,8 @@ int32_t fd_variant_count(int32_t ndim);
 int fd_variant_info(int32_t ndim, int32_t variant, int32_t* tile_z, int32_t* tile_y,
                     int32_t* threads, int32_t* cells_per_lane, int32_t* max_fields);
 
-/* Autotuner: times `steps` fused steps (with accumulation) for every tile variant that
+/* Autotuner: times `steps` pairs of fused steps (one without accumulator access, one
+ * adding two kernel terms, the mix the sweeps run) for every tile variant that
  * fits the grid, several axis-0 chunk lengths and, for nshot > 1, the shot-group sizes,
  * on scratch fields of this grid allocated and freed by the call; writes the fastest
  * (time per shot-cell update) into *best (variant, chunk, max_group; other fields copied

@@ -237,10 +237,12 @@ int check_speeds(const std::vector<const Geo*>& geos, const std::vector<const vo
     return FD_OK;
 }
 
-// One shot group of a plan: shots [g0, g0 + size) and their events.
+// One shot group of a plan: shots [g0, g0 + size) and their events: per block a range
+// of plane groups (d_off), each a range of events (d_grp), sorted by plane.
 struct Group {
     int g0 = 0, size = 1;
     int32_t* d_off = nullptr;
+    fdw::EvPlane* d_grp = nullptr;
     fdw::Event* d_ev = nullptr;
 };
 
@@ -311,6 +313,7 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
     const int nsrc = acq ? acq->nsrc : 0;
     const int nrec = acq ? acq->nrec : 0;
     std::vector<std::vector<int32_t>> offs;
+    std::vector<std::vector<fdw::EvPlane>> grps;
     std::vector<std::vector<fdw::Event>> evs;
     for (Group& gr : P->groups) {
         struct Item { int64_t key; fdw::Event e; };
@@ -346,19 +349,34 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
             if (a.e.kind != b.e.kind) return a.e.kind < b.e.kind;
             return a.e.idx < b.e.idx;
         });
+        // plane groups: runs of one block's events in one plane
         std::vector<int32_t> off(P->nblk + 1, 0);
+        std::vector<fdw::EvPlane> grp;
         std::vector<fdw::Event> ev(items.size());
         for (size_t i = 0; i < items.size(); ++i) {
-            off[items[i].key + 1]++;
             ev[i] = items[i].e;
+            if (i == 0 || items[i].key != items[i - 1].key || ev[i].plane != ev[i - 1].plane) {
+                fdw::EvPlane g;
+                g.plane = ev[i].plane;
+                g.begin = (int32_t)i;
+                g.end = (int32_t)i;
+                g.pad = 0;
+                grp.push_back(g);
+                off[items[i].key + 1]++;
+            }
+            grp.back().end = (int32_t)i + 1;
         }
         for (int b = 0; b < P->nblk; ++b) off[b + 1] += off[b];
         HIPCHK(sc.get((void**)&gr.d_off, sizeof(int32_t) * off.size()));
+        HIPCHK(sc.get((void**)&gr.d_grp, sizeof(fdw::EvPlane) * std::max<size_t>(1, grp.size())));
         HIPCHK(sc.get((void**)&gr.d_ev, sizeof(fdw::Event) * std::max<size_t>(1, ev.size())));
         HIPCHK(hipMemcpyAsync(gr.d_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, s));
+        if (!grp.empty())
+            HIPCHK(hipMemcpyAsync(gr.d_grp, grp.data(), sizeof(fdw::EvPlane) * grp.size(), hipMemcpyHostToDevice, s));
         if (!ev.empty())
             HIPCHK(hipMemcpyAsync(gr.d_ev, ev.data(), sizeof(fdw::Event) * ev.size(), hipMemcpyHostToDevice, s));
         offs.push_back(std::move(off));
+        grps.push_back(std::move(grp));
         evs.push_back(std::move(ev));
     }
 
@@ -417,6 +435,7 @@ fdw::StepArgs base_args(const Geo& G, const Plan& P, const void* c, double dt)
 int step(const Geo& G, const Plan& P, const Group& gr, fdw::StepArgs a, hipStream_t s)
 {
     a.blk_off = gr.d_off;
+    a.grp = gr.d_grp;
     a.ev = gr.d_ev;
     HIPCHK(fdw::launch_step(G.ndim, G.r, G.dtype, G.acc_dtype, G.variant, gr.size, P.nblk, a, s));
     return FD_OK;
@@ -939,12 +958,14 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
                 gr.size = group;
                 fdw::StepArgs a = base_args(T, P, c, 0.1);
                 a.acc = acc;
-                a.acc_sign = 1;
+                // the sweeps' mix: launches alternate between no accumulator access and
+                // two kernel terms; `steps` such pairs are timed after one warm-up launch
                 void *prev = ua, *cur = ub;
-                for (int n = 0; n < steps + 1; ++n) {
+                for (int n = 0; n < 2 * steps + 1; ++n) {
                     if (n == 1) HIPCHK(hipEventRecord(e0, s));
                     a.ucur = cur;
                     a.unew = prev;
+                    set_acc(a, (n & 1) ? 3 : 0, 1);
                     if ((rc = step(T, P, gr, a, s))) return rc;
                     std::swap(prev, cur);
                 }
@@ -952,7 +973,7 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                const double per_step = ms / steps;
+                const double per_step = ms / (2 * steps);
                 if (per_step / group < best_per_shot) {
                     best_per_shot = per_step / group;
                     bestv.variant = variant;
@@ -1047,6 +1068,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         for (int n = 0; n < nfw; ++n) {
             fdw::StepArgs a = base_args(G[p], P[p], q.c, q.dt);
             a.blk_off = P[p].groups[0].d_off;
+            a.grp = P[p].groups[0].d_grp;
             a.ev = P[p].groups[0].d_ev;
             a.active = n < q.nt;
             a.acc = st[p].acc;
@@ -1071,6 +1093,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
             const int j = q.nt - 1 - i;
             fdw::StepArgs a = base_args(G[p], P[p], q.c, q.dt);
             a.blk_off = P[p].groups[0].d_off;
+            a.grp = P[p].groups[0].d_grp;
             a.ev = P[p].groups[0].d_ev;
             a.active = j >= 1;
             a.acc = st[p].acc;

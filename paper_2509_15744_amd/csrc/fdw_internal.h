@@ -14,6 +14,16 @@ struct Event {
     int32_t idx;    // source or receiver number
 };
 enum { EV_SRC = 0, EV_REC = 1 };
+
+// The events of one block in one plane: ev[begin, end).  A block's groups are sorted
+// by plane, so the kernel reads one group per plane that has events.
+struct EvPlane {
+    int32_t plane, begin, end, pad;
+};
+
+// Events of one plane of one block that the kernel stages in LDS at once (planes with
+// more take a slower path that reads them from global memory one by one).
+constexpr int kStagedEvents = 128;
 __host__ __device__ inline int ev_kind(int k) { return k & 1; }
 __host__ __device__ inline int ev_shot(int k) { return k >> 1; }
 
@@ -35,7 +45,8 @@ struct StepArgs {
     int32_t acc_prev;    // 1: also add the interval before, d = ucur - unew (on entry)
     int32_t active;      // 0: the problem has no step here (multi-problem launches)
     // events
-    const int32_t* blk_off;  // [nblk + 1] ranges into ev
+    const int32_t* blk_off;  // [nblk + 1] ranges into grp
+    const EvPlane* grp;      // per block, its planes that hold events
     const Event* ev;
     const void* wavelet;     // [nt][nsrc]
     int32_t nsrc;

@@ -6,14 +6,25 @@
 
 namespace fdw {
 
-template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int S>
-__global__ __launch_bounds__(TZ*(TY / RY)) void step_kernel(StepArgs a)
+// Waves per SIMD the compiler is asked to make room for.  A 512-thread block puts two
+// waves on each SIMD, so an instance that fits five waves per SIMD still runs only two
+// blocks per CU; the f32 single-field, two-cells-per-lane instance without accumulator
+// fits three blocks (six waves) without spilling.  Other instances keep the default.
+template <typename T, bool ACC, int S, int VZ, int RY, int NT>
+constexpr int min_waves_per_simd()
+{
+    return (sizeof(T) == 4 && !ACC && S == 1 && VZ == 2 && RY == 1 && NT == 512) ? 6 : 1;
+}
+
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int S, bool ACC>
+__global__ __launch_bounds__(TZ*(TY / RY), (min_waves_per_simd<T, ACC, S, VZ, RY, TZ*(TY / RY)>()))
+void step_kernel(StepArgs a)
 {
     typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, S> SH;
     __shared__ __attribute__((aligned(16))) T lds[SH::LDS];
     const int b = logical_block(a.nblk);
     if (b >= a.nblk) return;
-    step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, S>(a, b, lds);
+    step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, S, ACC>(a, b, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -50,8 +61,12 @@ template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int 
 static hipError_t launch_one(int nblk, const StepArgs& a, hipStream_t s)
 {
     const int grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((step_kernel<R, T, AT, NDIM, TZ, TY, RY, VZ, S>), dim3(grid),
-                       dim3(TZ * (TY / RY)), 0, s, a);
+    if (a.acc_sign != 0)
+        hipLaunchKernelGGL((step_kernel<R, T, AT, NDIM, TZ, TY, RY, VZ, S, true>), dim3(grid),
+                           dim3(TZ * (TY / RY)), 0, s, a);
+    else
+        hipLaunchKernelGGL((step_kernel<R, T, AT, NDIM, TZ, TY, RY, VZ, S, false>), dim3(grid),
+                           dim3(TZ * (TY / RY)), 0, s, a);
     return hipGetLastError();
 }
 

@@ -117,8 +117,11 @@ struct Shape {
     static constexpr int LDS = 2 * S * LSZ;                  // double buffer, all shots
 };
 
-// One block's share of one step: logical block b of problem `a`.
-template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int S>
+// One block's share of one step: logical block b of problem `a`.  ACC = false compiles
+// a launch that never touches the accumulator (no registers held for it, which lets
+// more waves stay resident); with ACC = true a.acc_sign decides at run time.
+template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, int S,
+          bool ACC = true>
 __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __restrict__ lds)
 {
     typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, S> SH;
@@ -149,7 +152,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
     T* __restrict__ unew = (T*)a.unew;
     const T* __restrict__ cc = (const T*)a.c;
     AT* __restrict__ acc = (AT*)a.acc;
-    const bool use_acc = a.acc_sign != 0;
+    const bool use_acc = ACC && a.acc_sign != 0;
     T w[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) w[j] = (T)a.w[j];
@@ -227,8 +230,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
         }
     }
 
-    int e = a.blk_off[b];
-    const int e_end = a.blk_off[b + 1];
+    // events: the next plane group of this block, read one group ahead; the events of
+    // a plane (and their wavelet, adjoint force and observed values) are staged in
+    // LDS, double-buffered like the planes, so lanes scan them without global loads
+    // (staged event: key = lane << 8 | kind, kind = shot slot << 1 | source/receiver)
+    __shared__ int32_t skey[2][kStagedEvents];
+    __shared__ int32_t sidx[2][kStagedEvents];
+    __shared__ T sval[2][kStagedEvents];
+    __shared__ T sobs[2][kStagedEvents];
+    int gi = a.blk_off[b];
+    const int g_end = a.blk_off[b + 1];
+    EvPlane nextg;
+    nextg.plane = -1;
+    if (gi < g_end) nextg = a.grp[gi];
 
     for (int x = x0; x < x1; ++x) {
         const int64_t xo = (int64_t)x * ps;
@@ -273,11 +287,36 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
             for (int i = 0; i < NHZ; ++i)
                 if (hzl[i] >= 0) L[hzl[i]] = chz[s][i];
         }
+        // events of this plane (block-uniform): ev[ea, e)
+        const bool has_ev = nextg.plane == x;
+        int ea = 0, e = 0;
+        bool staged = false;
+        const int eb = x & 1;
+        if (has_ev) {
+            ea = nextg.begin;
+            e = nextg.end;
+            nextg.plane = -1;
+            if (++gi < g_end) nextg = a.grp[gi];
+            staged = e - ea <= kStagedEvents;
+            if (staged) {
+                for (int t = tid; t < e - ea; t += NT) {
+                    const Event ev = a.ev[ea + t];
+                    T v = (T)0, o = (T)0;
+                    if (ev_kind(ev.kind) == EV_SRC) {
+                        v = ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
+                    } else {
+                        const int64_t r = (int64_t)a.row_rec * a.nrec + ev.idx;
+                        if (a.inject_rec) v = (T)a.rec_scale * ((const T*)a.resid)[r];
+                        if (a.sample && a.resid) o = ((const T*)a.obs)[r];
+                    }
+                    skey[eb][t] = (ev.lane << 8) | ev.kind;
+                    sidx[eb][t] = ev.idx;
+                    sval[eb][t] = v;
+                    sobs[eb][t] = o;
+                }
+            }
+        }
         __syncthreads();
-
-        // events of this plane: [ea, e)
-        const int ea = e;
-        while (e < e_end && a.ev[e].plane == x) ++e;
 
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
@@ -308,15 +347,25 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     for (int j = 1; j <= R; ++j)
                         lap += w[j - 1] * ((L[s0 + i + j] - u0) + (L[s0 + i - j] - u0));
 
-                    if (ea != e) {   // block-uniform: a source or receiver lies in this plane
+                    if (has_ev) {   // a source or receiver lies in this plane
                         T f = (T)0;
-                        for (int v = ea; v < e; ++v) {
-                            const Event ev = a.ev[v];
-                            if (ev.lane != lane0[k] + i || ev_shot(ev.kind) != s) continue;
-                            if (ev_kind(ev.kind) == EV_SRC)
-                                f += ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
-                            else if (a.inject_rec)
-                                f += (T)a.rec_scale * ((const T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
+                        if (staged) {
+                            // sources of this cell and slot, and receivers when injecting
+                            const int want = (((lane0[k] + i) << 8) | (s << 1)) >> 1;
+                            for (int t = 0; t < e - ea; ++t) {
+                                const int key = skey[eb][t];
+                                if ((key >> 1) == want && ((key & 1) == EV_SRC || a.inject_rec))
+                                    f += sval[eb][t];
+                            }
+                        } else {
+                            for (int v = ea; v < e; ++v) {
+                                const Event ev = a.ev[v];
+                                if (ev.lane != lane0[k] + i || ev_shot(ev.kind) != s) continue;
+                                if (ev_kind(ev.kind) == EV_SRC)
+                                    f += ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
+                                else if (a.inject_rec)
+                                    f += (T)a.rec_scale * ((const T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
+                            }
                         }
                         lap += f;
                     }
@@ -333,13 +382,23 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     } else {
                         dsum += d * d + dp * dp;
                     }
-                    if (a.sample && ea != e) {
-                        for (int v = ea; v < e; ++v) {
-                            const Event ev = a.ev[v];
-                            if (ev.lane != lane0[k] + i || ev.kind != (EV_REC | (s << 1))) continue;
-                            const int64_t o = (int64_t)a.row_rec * a.nrec + ev.idx;
-                            if (a.traces) ((T*)a.traces)[o] = uni;
-                            if (a.resid) ((T*)a.resid)[o] = uni - ((const T*)a.obs)[o];
+                    if (a.sample && has_ev) {
+                        if (staged) {
+                            const int want = ((lane0[k] + i) << 8) | (s << 1) | EV_REC;
+                            for (int t = 0; t < e - ea; ++t) {
+                                if (skey[eb][t] != want) continue;
+                                const int64_t o = (int64_t)a.row_rec * a.nrec + sidx[eb][t];
+                                if (a.traces) ((T*)a.traces)[o] = uni;
+                                if (a.resid) ((T*)a.resid)[o] = uni - sobs[eb][t];
+                            }
+                        } else {
+                            for (int v = ea; v < e; ++v) {
+                                const Event ev = a.ev[v];
+                                if (ev.lane != lane0[k] + i || ev.kind != (EV_REC | (s << 1))) continue;
+                                const int64_t o = (int64_t)a.row_rec * a.nrec + ev.idx;
+                                if (a.traces) ((T*)a.traces)[o] = uni;
+                                if (a.resid) ((T*)a.resid)[o] = uni - ((const T*)a.obs)[o];
+                            }
                         }
                     }
                 }

@@ -176,6 +176,31 @@ def test_cells_on_every_wall_and_corner(fdw):
     assert rel(grad, case.g_approx) < 1e-9
 
 
+@pytest.mark.parametrize("copies", [1, 3])
+def test_dense_receiver_planes(fdw, copies):
+    """Every cell of the first row is a receiver, `copies` times over, and several
+    sources share it: with 3 copies a block's plane holds more events than the kernel
+    stages in LDS (128), which takes the global-memory path; both paths match the
+    oracle to rounding in every 2D variant."""
+    shape = (26, 300)
+    rng = np.random.default_rng(40 + copies)
+    c = 1.0 + rng.random(shape)
+    nt = 24
+    dt = 0.4 * oracle.cfl_limit(2, 4) / c.max()
+    row = [[0, j] for j in range(shape[1])]
+    rec = wl.flat(shape, row * copies)
+    src = wl.flat(shape, [[0, 7], [0, 7], [0, 150], [3, 299]])
+    p = wl.Problem("dense", shape, 4, "f64", 1.0, dt, nt, c, np.full(shape, 1.5), src, rec,
+                   rng.standard_normal((nt, len(src))))
+    case = OracleCase(p, k=0.05)
+    for variant in fdw.variants_for(shape):
+        say("dense receiver plane, copies", copies, "variant", variant)
+        grad, J, traces = run_sens(fdw, p, case, variant=variant)
+        assert rel(traces, case.traces) < 1e-12
+        assert abs(J - case.J) <= 1e-12 * case.J
+        assert rel(grad, case.g_approx) < 1e-9
+
+
 def test_variants_are_bitwise_identical(fdw):
     """The per-cell arithmetic does not depend on the tile shape."""
     p = wl.small_random((19, 23, 132), order=8, nt=20, dtype="f32", seed=9)
