@@ -6,16 +6,18 @@ only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 meet only through the seeded input generators, which hold none of the
 method's arithmetic.
 
-The arithmetic lives in ``fdoracle.c`` (plain double-precision loops, see its
-header for the discretisation and the time indexing).  This module
+The arithmetic lives in ``fdoracle.c`` (the constant-density high-order scheme)
+and ``vdoracle.c`` (the paper's second-order flux-form scheme with variable mass
+and stiffness coefficients), plain double-precision loops; their headers give the
+discretisation and the time indexing.  This module
 
 * derives the central second-derivative weights with Fornberg's recursion
   (B. Fornberg, Math. Comp. 51 (1988) 699-706), in exact rationals;
-* compiles ``fdoracle.c`` with gcc on first use (``build()``);
+* compiles both C files with gcc on first use (``build()``);
 * wraps the C entry points for numpy arrays;
 * adds the brute-force central finite-difference gradient.
 
-Readings of the paper taken here (each also listed in the design doc):
+Readings of the paper taken here:
 
 * stencil: paper Eq. FDstencil2 with rho^-1 = 1, kappa = c^2, generalised
   from 2nd to 2r-th order in space (difference form);
@@ -36,7 +38,7 @@ from fractions import Fraction
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fdoracle.c")
+_SRCS = [os.path.join(_HERE, "fdoracle.c"), os.path.join(_HERE, "vdoracle.c")]
 _LIB_PATH = os.path.join(_HERE, "_fdoracle.so")
 _lib = None
 
@@ -105,12 +107,12 @@ def _a_array(order: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def build(force: bool = False) -> str:
-    """Compile ``fdoracle.c`` into ``_fdoracle.so`` with gcc (OpenMP)."""
-    if force or not os.path.exists(_LIB_PATH) or (
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+    """Compile ``fdoracle.c`` and ``vdoracle.c`` into ``_fdoracle.so`` with gcc (OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or any(
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(src) for src in _SRCS):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -142,6 +144,17 @@ def _load():
         lib.orc_exact_gradient_ckpt.restype = I
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = I
+        vgrid = [I, P, D]
+        lib.orc_vd_operator.argtypes = vgrid + [P, P, P]
+        lib.orc_vd_operator.restype = None
+        lib.orc_vd_forward.argtypes = vgrid + [P, P, D, I, I, P, P, I, P, P, P, P]
+        lib.orc_vd_forward.restype = I
+        lib.orc_vd_adjoint.argtypes = vgrid + [P, P, D, I, I, P, P, P]
+        lib.orc_vd_adjoint.restype = I
+        lib.orc_vd_exact_gradient.argtypes = vgrid + [P, P, D, I, I, P, P, I, P, P, P, P, P, P, P, P]
+        lib.orc_vd_exact_gradient.restype = I
+        lib.orc_vd_superposition.argtypes = vgrid + [P, P, D, I, I, P, P, I, P, P, D, P, P, P, P]
+        lib.orc_vd_superposition.restype = I
         _lib = lib
     return _lib
 
@@ -337,3 +350,108 @@ def cfl_limit(ndim: int, order: int) -> float:
     a = central_weights(order)
     sym_pi = a[0] + 2 * sum(a[j] * (-1) ** j for j in range(1, len(a)))
     return float(2.0 / np.sqrt(ndim * abs(float(sym_pi))))
+
+
+# ---------------------------------------------------------------------------
+# the paper's second-order flux-form scheme with variable material (vdoracle.c)
+# ---------------------------------------------------------------------------
+
+def _vgrid_args(shape, dx):
+    shape = tuple(int(s) for s in shape)
+    sh = np.array(list(shape) + [1] * (3 - len(shape)), dtype=np.int64)
+    return [len(shape), sh.ctypes.data, float(dx)], sh
+
+
+def vd_operator(b, u, dx):
+    """(L_b u) with harmonic-mean faces and mirrored walls."""
+    b, u = _f64(b), _f64(u)
+    out = np.empty_like(u)
+    g, keep = _vgrid_args(u.shape, dx)
+    _load().orc_vd_operator(*g, b.ctypes.data, u.ctypes.data, out.ctypes.data)
+    return out
+
+
+def vd_forward(m, b, dx, dt, nt, src, wavelet, rec, history=False):
+    """Forward solve of m u_tt - div(b grad u) = f; returns ``(traces, hist, last2)``."""
+    m, b = _f64(m), _f64(b)
+    src, rec = _i64(src), _i64(rec)
+    wavelet = _f64(np.asarray(wavelet).reshape(nt, len(src)))
+    traces = np.empty((nt, len(rec)))
+    hist = np.empty((nt + 1,) + m.shape) if history else None
+    last2 = np.empty((2,) + m.shape)
+    g, keep = _vgrid_args(m.shape, dx)
+    _check(_load().orc_vd_forward(*g, m.ctypes.data, b.ctypes.data, float(dt), int(nt), len(src),
+                                  _ptr(src), wavelet.ctypes.data, len(rec), _ptr(rec),
+                                  traces.ctypes.data, _ptr(hist), last2.ctypes.data), "vd_forward")
+    return traces, hist, last2
+
+
+def vd_adjoint(m, b, dx, dt, nt, rec, fdag):
+    """Adjoint sweep with force ``fdag`` [nt][nrec] at the receivers; returns mu^0..mu^nt."""
+    m, b = _f64(m), _f64(b)
+    rec = _i64(rec)
+    fdag = _f64(np.asarray(fdag).reshape(nt, len(rec)))
+    hist = np.empty((nt + 1,) + m.shape)
+    g, keep = _vgrid_args(m.shape, dx)
+    _check(_load().orc_vd_adjoint(*g, m.ctypes.data, b.ctypes.data, float(dt), int(nt), len(rec),
+                                  _ptr(rec), fdag.ctypes.data, hist.ctypes.data), "vd_adjoint")
+    return hist
+
+
+def vd_exact_gradient(m, b, dx, dt, nt, src, wavelet, rec, observed):
+    """Exact discrete gradient (stored history).  Returns
+    ``(grad_m, grad_b, J, s2_m, s2_b, traces)``; s2_m and s2_b are the k^2 terms of the
+    superposition for the two fields."""
+    m, b = _f64(m), _f64(b)
+    src, rec = _i64(src), _i64(rec)
+    wavelet = _f64(np.asarray(wavelet).reshape(nt, len(src)))
+    observed = _f64(np.asarray(observed).reshape(nt, len(rec)))
+    gm, gb, s2m, s2b = (np.empty_like(m) for _ in range(4))
+    traces = np.empty((nt, len(rec)))
+    J = ctypes.c_double()
+    g, keep = _vgrid_args(m.shape, dx)
+    _check(_load().orc_vd_exact_gradient(*g, m.ctypes.data, b.ctypes.data, float(dt), int(nt),
+                                         len(src), _ptr(src), wavelet.ctypes.data, len(rec),
+                                         _ptr(rec), observed.ctypes.data, gm.ctypes.data,
+                                         gb.ctypes.data, ctypes.addressof(J), s2m.ctypes.data,
+                                         s2b.ctypes.data, traces.ctypes.data), "vd_exact_gradient")
+    return gm, gb, J.value, s2m, s2b, traces
+
+
+def vd_superposition_gradient(m, b, dx, dt, nt, src, wavelet, rec, observed, k):
+    """Alg. 1 for both fields at factor ``k``; returns ``(grad_m, grad_b, J, traces)``."""
+    m, b = _f64(m), _f64(b)
+    src, rec = _i64(src), _i64(rec)
+    wavelet = _f64(np.asarray(wavelet).reshape(nt, len(src)))
+    observed = _f64(np.asarray(observed).reshape(nt, len(rec)))
+    gm, gb = np.empty_like(m), np.empty_like(m)
+    traces = np.empty((nt, len(rec)))
+    J = ctypes.c_double()
+    g, keep = _vgrid_args(m.shape, dx)
+    _check(_load().orc_vd_superposition(*g, m.ctypes.data, b.ctypes.data, float(dt), int(nt),
+                                        len(src), _ptr(src), wavelet.ctypes.data, len(rec),
+                                        _ptr(rec), observed.ctypes.data, float(k), gm.ctypes.data,
+                                        gb.ctypes.data, ctypes.addressof(J), traces.ctypes.data),
+           "vd_superposition")
+    return gm, gb, J.value, traces
+
+
+def vd_misfit(m, b, dx, dt, nt, src, wavelet, rec, observed):
+    """J(m, b) by a forward solve."""
+    traces, _, _ = vd_forward(m, b, dx, dt, nt, src, wavelet, rec)
+    return misfit(traces, observed, dt)[0]
+
+
+def vd_fd_gradient(m, b, which, dx, dt, nt, src, wavelet, rec, observed, cells, eps=1e-6):
+    """Central finite differences of J with respect to m (``which="m"``) or b at ``cells``."""
+    m, b = _f64(m), _f64(b)
+    out = np.empty(len(cells))
+    for q, i in enumerate(cells):
+        vals = []
+        for sgn in (1.0, -1.0):
+            mp, bp = m.copy().reshape(-1), b.copy().reshape(-1)
+            (mp if which == "m" else bp)[i] += sgn * eps
+            vals.append(vd_misfit(mp.reshape(m.shape), bp.reshape(b.shape), dx, dt, nt, src,
+                                  wavelet, rec, observed))
+        out[q] = (vals[0] - vals[1]) / (2.0 * eps)
+    return out
