@@ -210,6 +210,39 @@ int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, doub
                      const void* observed, void* grad_c, double* J_host, void* traces_or_null,
                      const fd_opts* opts, void* stream);
 
+/* The paper's own second-order flux-form scheme with variable material (Sec. 3.1,
+ * Eqs. FDstencil1/FDstencil2), written as m u_tt - div(b grad u) = f with a mass
+ * coefficient m and a stiffness coefficient b per cell (rho-scaling, Eq.
+ * scalarwaveequation: m = gamma rho0, b = gamma rho0 c0^2; Eq. wavetopopt: m = 1/kappa,
+ * b = 1/rho):
+ *     u^{n+1} = 2 u^n - u^{n-1} + (dt^2 / m) (L_b u^n + f^n)
+ *     (L_b u)_i = dx^-2 sum over the 2d neighbours j:  h(b_i, b_j) (u_j - u_i),
+ *     h(p, q) = 2 p q / (p + q)  (harmonic mean at the face)
+ * Wall ghosts mirror the boundary cell and carry its material (no flux through a wall).
+ * grid->order must be 2.  m, b DEVICE [ncell], finite and positive; dt must satisfy
+ * dt sqrt(d max b / min m) <= dx (else FD_E_CFL).  Time axis, sources, receivers, shots
+ * and misfit as for the constant-density calls.  fd_opts.variant: 0, 1 or 2;
+ * max_group is ignored (one wavefield per launch). */
+int fd_vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
+                  int32_t nt, void* traces, const fd_opts* opts, void* stream);
+
+/* Alg. 1 for the variable-material scheme at factor k: J and the sensitivities
+ * grad_m = dJ/dm and grad_b = dJ/db, DEVICE [ncell] each, the two terms of the paper's
+ * kernel (Eqs. kernel1/kernel2) in discrete form.  The forward sweep accumulates
+ * K_m(u,u) = sum_n (u^{n+1} - u^n)^2 and K_b(u,u) = sum_n sum_faces dh/db_i
+ * (u_j^n - u_i^n)^2, the superposed backward sweep the same of v = u + k mu; then
+ *     grad_m = (K_m(u,u) - K_m(v,v)) / (2k),
+ *     grad_b = -(dt^2 / dx^2) (K_b(u,u) - K_b(v,v)) / (2k),
+ * which differ from the exact discrete gradient by -(k/2) sum_n (mu^{n+1} - mu^n)^2 and
+ * (dt^2/dx^2)(k/2) sum_n sum_faces dh/db_i (mu_j^n - mu_i^n)^2.  A gradient with respect
+ * to a design field gamma follows by the chain rule (e.g. rho-scaling: rho0 grad_m +
+ * rho0 c0^2 grad_b).  Scratch: two wavefields per shot, two accumulators and the
+ * residuals, allocated stream-ordered and freed by the call.  Synchronises `stream`. */
+int fd_vd_adjoint_sensitivity(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq,
+                              double dt, int32_t nt, const void* observed, double k, void* grad_m,
+                              void* grad_b, double* J_host, void* traces_or_null, const fd_opts* opts,
+                              void* stream);
+
 /* First half of fd_adjoint_sensitivity: the forward sweep with cost, adjoint force and
  * K(u,u) accumulation; leaves u^{nt-1}, u^nt, the accumulator and the residuals in
  * `state` (all four arrays overwritten).  J_host may be NULL. */

@@ -432,12 +432,22 @@ fdw::StepArgs base_args(const Geo& G, const Plan& P, const void* c, double dt)
     return a;
 }
 
+// The variable-material fields of a sweep: stiffness b and its accumulator (null for
+// the constant-density scheme, whose c argument is then the speed, not the mass).
+struct VdFields {
+    const void* stiff = nullptr;
+    void* acc_b = nullptr;
+};
+
 int step(const Geo& G, const Plan& P, const Group& gr, fdw::StepArgs a, hipStream_t s)
 {
     a.blk_off = gr.d_off;
     a.grp = gr.d_grp;
     a.ev = gr.d_ev;
-    HIPCHK(fdw::launch_step(G.ndim, G.r, G.dtype, G.acc_dtype, G.variant, gr.size, P.nblk, a, s));
+    if (a.stiff)
+        HIPCHK(fdw::launch_vd_step(G.ndim, G.dtype, G.acc_dtype, G.variant, P.nblk, a, s));
+    else
+        HIPCHK(fdw::launch_step(G.ndim, G.r, G.dtype, G.acc_dtype, G.variant, gr.size, P.nblk, a, s));
     return FD_OK;
 }
 
@@ -508,17 +518,23 @@ int prepare(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, in
 }
 
 // Forward sweep of every shot group (Alg. 1 forward loop); the wavefields of shot s
-// live at ua/ub + s * ncell.  `acc` null: no kernel accumulation (plain forward).
+// live at ua/ub + s * ncell.  `acc` null: no kernel accumulation (plain forward).  With
+// vd.stiff the variable-material step runs (c is then the mass coefficient) and, with
+// vd.acc_b, every launch adds the stiffness term of its current level.
 int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
                   const void* obs, void* ua, void* ub, void* acc, void* resid, void* traces,
-                  hipStream_t s)
+                  hipStream_t s, const VdFields& vd = VdFields())
 {
     const size_t fb = G.ncell * dsize(G.dtype) * nshots(acq);
     HIPCHK(hipMemsetAsync(ua, 0, fb, s));
     HIPCHK(hipMemsetAsync(ub, 0, fb, s));
     if (acc) HIPCHK(hipMemsetAsync(acc, 0, G.ncell * dsize(G.acc_dtype), s));
+    if (vd.acc_b) HIPCHK(hipMemsetAsync(vd.acc_b, 0, G.ncell * dsize(G.acc_dtype), s));
     fdw::StepArgs a = base_args(G, P, c, dt);
     a.acc = acc;
+    a.stiff = vd.stiff;
+    a.acc_b = vd.acc_b;
+    a.acc_face = vd.acc_b ? 1 : 0;   // levels 0..nt-1 (level 0 is zero)
     a.wavelet = acq->wavelet;
     a.nsrc = acq->nsrc;
     a.sample = 1;
@@ -560,7 +576,8 @@ void final_levels(void* ua, void* ub, int nt, void** prev, void** cur)
 }
 
 int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
-                   double k, void* ua, void* ub, void* acc, void* resid, hipStream_t s)
+                   double k, void* ua, void* ub, void* acc, void* resid, hipStream_t s,
+                   const VdFields& vd = VdFields())
 {
     void* up = nullptr;   // u^{nt-1} -> v^{nt-1}
     void* ul = nullptr;   // u^nt = v^nt
@@ -569,6 +586,9 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
     const size_t es = dsize(G.dtype);
     fdw::StepArgs a = base_args(G, P, c, dt);
     a.acc = acc;
+    a.stiff = vd.stiff;
+    a.acc_b = vd.acc_b;
+    a.acc_face = vd.acc_b ? -1 : 0;   // levels nt-1..1 of the superposed field
     a.wavelet = acq->wavelet;
     a.nsrc = acq->nsrc;
     a.inject_rec = 1;
@@ -582,7 +602,8 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
         char* vn = (char*)ul + (size_t)gr.g0 * G.ncell * es;   // v^{j+1}, overwritten by v^{j-1}
         if (acq->nrec > 0)
             HIPCHK(fdw::launch_terminal(G.dtype, G.acc_dtype, P.nuniq, P.d_ucell, P.d_uoff, P.d_uidx,
-                                        P.d_ushot, gr.g0, gr.size, G.ncell, c, dt * dt, vn, vj, acc,
+                                        P.d_ushot, gr.g0, gr.size, G.ncell, c, vd.stiff ? 1 : 0,
+                                        dt * dt, vn, vj, acc,
                                         (const char*)resid + (size_t)(nt - 1) * acq->nrec * es,
                                         rec_scale, s));
         if (gi == 0) tm.start();
@@ -675,6 +696,126 @@ int sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double 
     if ((rc = backward_sweep(G, P, c, acq, dt, nt, k, st->u_a, st->u_b, st->acc, st->residual, s)))
         return rc;
     HIPCHK(fdw::launch_finalize(G.dtype, G.acc_dtype, G.ncell, st->acc, c, grad_scale / k, grad, s));
+    return FD_OK;
+}
+
+// Mass and stiffness of the variable-material scheme: finite and positive, and the
+// time step inside the sufficient stability bound dt sqrt(d max b / min m) <= dx (the
+// Gershgorin bound of the scaled operator with the second-order symbol).
+int check_material(const Geo& G, const void* m, const void* b, double dt, hipStream_t s, Scratch& sc)
+{
+    void* part = nullptr;
+    void* out = nullptr;
+    HIPCHK(sc.get(&part, sizeof(double) * 3 * fdw::kReduceBlocks));
+    HIPCHK(sc.get(&out, sizeof(double) * 6));
+    HIPCHK(fdw::launch_speed_stats(G.dtype, m, G.ncell, (double*)out, (double*)part, s));
+    HIPCHK(fdw::launch_speed_stats(G.dtype, b, G.ncell, (double*)out + 3, (double*)part, s));
+    double h[6];
+    HIPCHK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h[2] > 0 || h[5] > 0) return fail(FD_E_NONFINITE, "material field has non-finite entries");
+    if (!(h[1] > 0.0) || !(h[4] > 0.0)) return fail(FD_E_NONFINITE, "mass and stiffness must be positive");
+    const double courant = dt * std::sqrt(G.ndim * h[3] / h[1]) / G.dx;
+    if (courant > 1.0 + 1e-12) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "dt sqrt(d max b / min m) / dx = %.6g exceeds 1", courant);
+        return fail(FD_E_CFL, buf);
+    }
+    return FD_OK;
+}
+
+// Grid, options and launch shape of the variable-material scheme: second order only,
+// tile variants 1 and 2, one wavefield per launch.
+int vd_setup(const fd_grid* grid, const fd_opts* opts, Geo* G)
+{
+    int rc = check_grid(grid, opts, G);
+    if (rc) return rc;
+    if (grid->order != 2) return fail(FD_E_ARG, "the variable-material scheme is second order (order 2)");
+    if (G->auto_variant) {
+        G->variant = (G->n2 % 2 == 0) ? 2 : 1;
+        G->auto_variant = false;
+    } else if (G->variant != 1 && G->variant != 2) {
+        return fail(FD_E_ARG, "the variable-material scheme runs tile variants 1 and 2");
+    }
+    G->max_group = 1;
+    return FD_OK;
+}
+
+int vd_gradient(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt, int nt,
+                const void* observed, double k, void* grad_m, void* grad_b, double* J_host, void* traces,
+                const fd_opts* opts, hipStream_t s)
+{
+    Geo G;
+    int rc = vd_setup(grid, opts, &G);
+    if (rc) return rc;
+    if ((rc = check_time(dt, nt))) return rc;
+    if (!acq) return fail(FD_E_ARG, "acq is null");
+    if ((rc = check_acq(acq, G, nt))) return rc;
+    if (!(k != 0.0) || !std::isfinite(k)) return fail(FD_E_ARG, "k must be finite and non-zero");
+    const size_t es = dsize(G.dtype);
+    const size_t tb = (size_t)nt * acq->nrec * es;
+    if ((rc = check_dev(m, G.ncell * es, "m"))) return rc;
+    if ((rc = check_dev(b, G.ncell * es, "b"))) return rc;
+    if ((rc = check_dev(grad_m, G.ncell * es, "grad_m"))) return rc;
+    if ((rc = check_dev(grad_b, G.ncell * es, "grad_b"))) return rc;
+    if ((rc = check_dev(observed, tb, "observed"))) return rc;
+    if (traces && (rc = check_dev(traces, tb, "traces"))) return rc;
+    Scratch sc(s);
+    if ((rc = check_material(G, m, b, dt, s, sc))) return rc;
+    const int ns = nshots(acq);
+    void *ua = nullptr, *ub = nullptr, *acc = nullptr, *accb = nullptr, *resid = nullptr;
+    HIPCHK(sc.get(&ua, G.ncell * es * ns));
+    HIPCHK(sc.get(&ub, G.ncell * es * ns));
+    HIPCHK(sc.get(&acc, G.ncell * dsize(G.acc_dtype)));
+    HIPCHK(sc.get(&accb, G.ncell * dsize(G.acc_dtype)));
+    HIPCHK(sc.get(&resid, std::max<size_t>(tb, es)));
+    Plan P;
+    if ((rc = make_plan(G, acq, true, s, sc, &P))) return rc;
+    VdFields vd;
+    vd.stiff = b;
+    vd.acc_b = accb;
+    if ((rc = forward_sweep(G, P, m, acq, dt, nt, observed, ua, ub, acc, resid, traces, s, vd))) return rc;
+    if (J_host) {
+        double ss = 0.0;
+        if ((rc = misfit_sum(G.dtype, resid, nullptr, nullptr, (int64_t)nt * acq->nrec, s, sc, &ss)))
+            return rc;
+        *J_host = 0.5 * dt * ss;
+        if (!std::isfinite(*J_host)) return fail(FD_E_NONFINITE, "misfit is not finite");
+    }
+    if ((rc = backward_sweep(G, P, m, acq, dt, nt, k, ua, ub, acc, resid, s, vd))) return rc;
+    // dJ/dm ~ (K_m(u,u) - K_m(v,v)) / (2k),  dJ/db ~ -(dt^2/dx^2)(K_b(u,u) - K_b(v,v)) / (2k)
+    HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, acc, 0.5 / k, grad_m, s));
+    HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, accb, -dt * dt / (G.dx * G.dx) * 0.5 / k, grad_b, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FD_OK;
+}
+
+int vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt, int nt,
+               void* traces, const fd_opts* opts, hipStream_t s)
+{
+    Geo G;
+    int rc = vd_setup(grid, opts, &G);
+    if (rc) return rc;
+    if ((rc = check_time(dt, nt))) return rc;
+    if (!acq) return fail(FD_E_ARG, "acq is null");
+    if ((rc = check_acq(acq, G, nt))) return rc;
+    const size_t es = dsize(G.dtype);
+    if ((rc = check_dev(m, G.ncell * es, "m"))) return rc;
+    if ((rc = check_dev(b, G.ncell * es, "b"))) return rc;
+    if ((rc = check_dev(traces, (size_t)nt * acq->nrec * es, "traces"))) return rc;
+    Scratch sc(s);
+    if ((rc = check_material(G, m, b, dt, s, sc))) return rc;
+    const int ns = nshots(acq);
+    void *ua = nullptr, *ub = nullptr;
+    HIPCHK(sc.get(&ua, G.ncell * es * ns));
+    HIPCHK(sc.get(&ub, G.ncell * es * ns));
+    Plan P;
+    if ((rc = make_plan(G, acq, false, s, sc, &P))) return rc;
+    VdFields vd;
+    vd.stiff = b;
+    if ((rc = forward_sweep(G, P, m, acq, dt, nt, nullptr, ua, ub, nullptr, nullptr, traces, s, vd)))
+        return rc;
+    HIPCHK(hipStreamSynchronize(s));
     return FD_OK;
 }
 
@@ -1220,7 +1361,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         void *up = nullptr, *ul = nullptr;
         final_levels(st[p].u_a, st[p].u_b, q.nt, &up, &ul);
         HIPCHK(fdw::launch_terminal(G[p].dtype, G[p].acc_dtype, P[p].nuniq, P[p].d_ucell, P[p].d_uoff,
-                                    P[p].d_uidx, P[p].d_ushot, 0, 1, G[p].ncell, q.c, q.dt * q.dt,
+                                    P[p].d_uidx, P[p].d_ushot, 0, 1, G[p].ncell, q.c, 0, q.dt * q.dt,
                                     ul, up, st[p].acc,
                                     (const char*)st[p].residual +
                                         (size_t)(q.nt - 1) * q.acq.nrec * dsize(G[p].dtype),
@@ -1369,6 +1510,23 @@ int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, doub
     if (!acq) return fail(FD_E_ARG, "acq is null");
     return exact_gradient(grid, c, acq, dt, nt, observed, grad_c, J_host, traces_or_null, opts,
                           (hipStream_t)stream);
+}
+
+int fd_vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
+                  int32_t nt, void* traces, const fd_opts* opts, void* stream)
+{
+    g_err.clear();
+    return vd_forward(grid, m, b, acq, dt, nt, traces, opts, (hipStream_t)stream);
+}
+
+int fd_vd_adjoint_sensitivity(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq,
+                              double dt, int32_t nt, const void* observed, double k, void* grad_m,
+                              void* grad_b, double* J_host, void* traces_or_null, const fd_opts* opts,
+                              void* stream)
+{
+    g_err.clear();
+    return vd_gradient(grid, m, b, acq, dt, nt, observed, k, grad_m, grad_b, J_host, traces_or_null, opts,
+                       (hipStream_t)stream);
 }
 
 int fd_autotune(const fd_grid* grid, int32_t nshot, const fd_opts* opts, int32_t steps,

@@ -33,8 +33,11 @@ __host__ __device__ inline int ev_shot(int k) { return k >> 1; }
 struct StepArgs {
     const void* ucur;    // level n (backward: j), first shot of the group
     void* unew;          // level n-1 on entry, n+1 on return (backward: j+1 -> j-1)
-    const void* c;       // wave speed, or dt^2 c^2 itself when coef_direct
+    const void* c;       // wave speed, or dt^2 c^2 itself when coef_direct; for the
+                         // variable-material step the mass coefficient m
     void* acc;           // sensitivity accumulator shared by the shots (acc_sign != 0)
+    const void* stiff;   // variable-material step: stiffness coefficient b per cell
+    void* acc_b;         // variable-material step: stiffness-term accumulator
     int64_t shot_stride; // elements between the wavefields of consecutive shots
     int32_t n0, n1, n2;  // extents; 2D grids run with n1 = 1
     double w[8];         // a_j / dx^2, j = 1..r
@@ -43,6 +46,7 @@ struct StepArgs {
     int32_t acc_sign;    // 0: no accumulation, +1: acc += sum_s d_s^2, -1: acc -= ...
     int32_t acc_cross;   // 1: the sum is over slot pairs, d_0 d_1 (+ d_2 d_3), not squares
     int32_t acc_prev;    // 1: also add the interval before, d = ucur - unew (on entry)
+    int32_t acc_face;    // variable-material step: 0, or the sign of the face terms into acc_b
     int32_t active;      // 0: the problem has no step here (multi-problem launches)
     // events
     const int32_t* blk_off;  // [nblk + 1] ranges into grp
@@ -96,6 +100,11 @@ hipError_t launch_step_persistent(int ndim, int r, int dtype, int acc_dtype, int
                                   int total_blocks, int nsteps, unsigned* d_barrier,
                                   long long timeout_ticks, hipStream_t s, int* grid_used);
 
+// One step of the variable-material second-order scheme (one wavefield; tile shapes of
+// step variants 1 and 2).  a.c is the mass coefficient, a.stiff the stiffness.
+hipError_t launch_vd_step(int ndim, int dtype, int acc_dtype, int variant, int nblk, const StepArgs& a,
+                          hipStream_t s);
+
 // Misc kernels.  All return hipError_t of the launch.
 hipError_t launch_speed_stats(int dtype, const void* c, int64_t n, double* d_out3, double* d_part,
                               hipStream_t s);
@@ -103,12 +112,13 @@ hipError_t launch_sum_squares(int dtype, const void* x, const void* y, void* dif
                               double* d_part, double* d_out, hipStream_t s);
 // Terminal hand-over for the shots [shot0, shot0 + nshots) of a problem: per distinct
 // receiver cell, receivers sorted by (cell, shot); u_last / u_prev point at the
-// group's first shot, shots shot_stride elements apart.
+// group's first shot, shots shot_stride elements apart.  The step coefficient is
+// dt2 c^2 from the speed c, or dt2 / c when `mass` (c is then the mass coefficient).
 hipError_t launch_terminal(int dtype, int acc_dtype, int nuniq, const int64_t* ucell,
                            const int32_t* uoff, const int32_t* uidx, const int32_t* ushot,
-                           int shot0, int nshots, int64_t shot_stride, const void* c, double dt2,
-                           const void* u_last, void* u_prev, void* acc, const void* resid_row,
-                           double rec_scale, hipStream_t s);
+                           int shot0, int nshots, int64_t shot_stride, const void* c, int mass,
+                           double dt2, const void* u_last, void* u_prev, void* acc,
+                           const void* resid_row, double rec_scale, hipStream_t s);
 // Terminal hand-over of the re-simulation sweep for the shots [shot0, shot0 + nshots):
 // mu^{nt-1} = coef * fdag^{nt} at the receiver cells of each shot (mu^{nt} = 0) and the
 // kernel of the last interval, -(u^nt - u^{nt-1}) mu^{nt-1}.  u_last / u_prev point at
@@ -121,6 +131,9 @@ hipError_t launch_terminal_exact(int dtype, int acc_dtype, int nuniq, const int6
                                  void* acc, const void* resid_row, double rec_scale, hipStream_t s);
 hipError_t launch_finalize(int dtype, int acc_dtype, int64_t n, const void* acc, const void* c,
                            double scale, void* grad, hipStream_t s);
+// out = scale * acc (accumulator dtype to grid dtype).
+hipError_t launch_scale(int dtype, int acc_dtype, int64_t n, const void* acc, double scale, void* out,
+                        hipStream_t s);
 
 constexpr int kReduceBlocks = 512;
 constexpr int kReduceThreads = 256;

@@ -146,7 +146,7 @@ template <typename T, typename AT>
 __global__ void terminal_kernel(int nuniq, const int64_t* __restrict__ ucell,
                                 const int32_t* __restrict__ uoff, const int32_t* __restrict__ uidx,
                                 const int32_t* __restrict__ ushot, int shot0, int nshots,
-                                int64_t shot_stride, const T* __restrict__ c, T dt2,
+                                int64_t shot_stride, const T* __restrict__ c, int mass, T dt2,
                                 const T* __restrict__ u_last, T* __restrict__ u_prev,
                                 AT* __restrict__ acc, const T* __restrict__ resid_row, T rec_scale)
 {
@@ -154,7 +154,7 @@ __global__ void terminal_kernel(int nuniq, const int64_t* __restrict__ ucell,
     if (u >= nuniq) return;
     const int64_t cell = ucell[u];
     const T cv = c[cell];
-    const T coef = dt2 * cv * cv;
+    const T coef = mass ? dt2 / cv : dt2 * cv * cv;
     AT delta = (AT)0;
     int q = uoff[u];
     const int q_end = uoff[u + 1];
@@ -179,26 +179,26 @@ __global__ void terminal_kernel(int nuniq, const int64_t* __restrict__ ucell,
 
 hipError_t launch_terminal(int dtype, int acc_dtype, int nuniq, const int64_t* ucell,
                            const int32_t* uoff, const int32_t* uidx, const int32_t* ushot,
-                           int shot0, int nshots, int64_t shot_stride, const void* c, double dt2,
-                           const void* u_last, void* u_prev, void* acc, const void* resid_row,
-                           double rec_scale, hipStream_t s)
+                           int shot0, int nshots, int64_t shot_stride, const void* c, int mass,
+                           double dt2, const void* u_last, void* u_prev, void* acc,
+                           const void* resid_row, double rec_scale, hipStream_t s)
 {
     if (nuniq <= 0) return hipSuccess;
     const int bs = 256, gs = (nuniq + bs - 1) / bs;
     if (dtype == 1)
         hipLaunchKernelGGL((terminal_kernel<double, double>), dim3(gs), dim3(bs), 0, s, nuniq, ucell,
-                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const double*)c, dt2,
+                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const double*)c, mass, dt2,
                            (const double*)u_last, (double*)u_prev, (double*)acc,
                            (const double*)resid_row, rec_scale);
     else if (acc_dtype == 1)
         hipLaunchKernelGGL((terminal_kernel<float, double>), dim3(gs), dim3(bs), 0, s, nuniq, ucell,
-                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const float*)c, (float)dt2,
-                           (const float*)u_last, (float*)u_prev, (double*)acc,
+                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const float*)c, mass,
+                           (float)dt2, (const float*)u_last, (float*)u_prev, (double*)acc,
                            (const float*)resid_row, (float)rec_scale);
     else
         hipLaunchKernelGGL((terminal_kernel<float, float>), dim3(gs), dim3(bs), 0, s, nuniq, ucell,
-                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const float*)c, (float)dt2,
-                           (const float*)u_last, (float*)u_prev, (float*)acc,
+                           uoff, uidx, ushot, shot0, nshots, shot_stride, (const float*)c, mass,
+                           (float)dt2, (const float*)u_last, (float*)u_prev, (float*)acc,
                            (const float*)resid_row, (float)rec_scale);
     return hipGetLastError();
 }
@@ -294,6 +294,33 @@ hipError_t launch_finalize(int dtype, int acc_dtype, int64_t n, const void* acc,
     else
         hipLaunchKernelGGL((finalize_kernel<float, float>), dim3(gs), dim3(bs), 0, s, n,
                            (const float*)acc, (const float*)c, (float)scale, (float*)grad);
+    return hipGetLastError();
+}
+
+// out = scale * acc
+template <typename T, typename AT>
+__global__ void scale_kernel(int64_t n, const AT* __restrict__ acc, AT scale, T* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (T)(scale * acc[i]);
+}
+
+hipError_t launch_scale(int dtype, int acc_dtype, int64_t n, const void* acc, double scale, void* out,
+                        hipStream_t s)
+{
+    const int bs = 256;
+    const int64_t gs64 = (n + bs - 1) / bs;
+    const int gs = (int)(gs64 < 65536 ? (gs64 > 0 ? gs64 : 1) : 65536);
+    if (dtype == 1)
+        hipLaunchKernelGGL((scale_kernel<double, double>), dim3(gs), dim3(bs), 0, s, n, (const double*)acc,
+                           scale, (double*)out);
+    else if (acc_dtype == 1)
+        hipLaunchKernelGGL((scale_kernel<float, double>), dim3(gs), dim3(bs), 0, s, n, (const double*)acc,
+                           scale, (float*)out);
+    else
+        hipLaunchKernelGGL((scale_kernel<float, float>), dim3(gs), dim3(bs), 0, s, n, (const float*)acc,
+                           (float)scale, (float*)out);
     return hipGetLastError();
 }
 

@@ -117,6 +117,121 @@ struct Shape {
     static constexpr int LDS = 2 * S * LSZ;                  // double buffer, all shots
 };
 
+// ---------------------------------------------------------------------------
+// sources and receivers of a block, plane by plane
+// ---------------------------------------------------------------------------
+
+// One plane's events staged in LDS, double-buffered by plane parity like the planes.
+template <typename T>
+struct EventStage {
+    int32_t key[2][kStagedEvents];   // lane << 8 | kind (kind = shot slot << 1 | source/receiver)
+    int32_t idx[2][kStagedEvents];   // source or receiver number
+    T val[2][kStagedEvents];         // injected value: wavelet / dx^d, or rec_scale * residual
+    T obs[2][kStagedEvents];         // observed value at a receiver (forward sampling)
+};
+
+// A block's walk over its plane groups (all fields block-uniform).  The next group
+// is read one plane group ahead; plane x's events are ev[ea, e).
+struct PlaneEvents {
+    int gi, g_end;
+    EvPlane next;
+    int ea, e, eb;
+    bool has, staged;
+};
+
+__device__ __forceinline__ void events_begin(PlaneEvents& pe, const StepArgs& a, int b)
+{
+    pe.gi = a.blk_off[b];
+    pe.g_end = a.blk_off[b + 1];
+    pe.next.plane = -1;
+    if (pe.gi < pe.g_end) pe.next = a.grp[pe.gi];
+}
+
+// Finds plane x's events and, when they fit, stages them with their values (all
+// threads of the block take part; the caller's barrier publishes them).
+template <typename T, int NT>
+__device__ __forceinline__ void events_at_plane(PlaneEvents& pe, const StepArgs& a, EventStage<T>& st,
+                                                int x, int tid)
+{
+    pe.has = pe.next.plane == x;
+    pe.ea = 0;
+    pe.e = 0;
+    pe.staged = false;
+    pe.eb = x & 1;
+    if (!pe.has) return;
+    pe.ea = pe.next.begin;
+    pe.e = pe.next.end;
+    pe.next.plane = -1;
+    if (++pe.gi < pe.g_end) pe.next = a.grp[pe.gi];
+    pe.staged = pe.e - pe.ea <= kStagedEvents;
+    if (!pe.staged) return;
+    for (int t = tid; t < pe.e - pe.ea; t += NT) {
+        const Event ev = a.ev[pe.ea + t];
+        T v = (T)0, o = (T)0;
+        if (ev_kind(ev.kind) == EV_SRC) {
+            v = ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
+        } else {
+            const int64_t r = (int64_t)a.row_rec * a.nrec + ev.idx;
+            if (a.inject_rec) v = (T)a.rec_scale * ((const T*)a.resid)[r];
+            if (a.sample && a.resid) o = ((const T*)a.obs)[r];
+        }
+        st.key[pe.eb][t] = (ev.lane << 8) | ev.kind;
+        st.idx[pe.eb][t] = ev.idx;
+        st.val[pe.eb][t] = v;
+        st.obs[pe.eb][t] = o;
+    }
+}
+
+// Point force at tile lane `lane`, shot slot s of this plane: the sources there and,
+// when injecting, the receivers, summed in event order.
+template <typename T>
+__device__ __forceinline__ T point_force(const PlaneEvents& pe, const StepArgs& a,
+                                         const EventStage<T>& st, int lane, int s)
+{
+    T f = (T)0;
+    if (pe.staged) {
+        const int want = ((lane << 8) | (s << 1)) >> 1;
+        for (int t = 0; t < pe.e - pe.ea; ++t) {
+            const int key = st.key[pe.eb][t];
+            if ((key >> 1) == want && ((key & 1) == EV_SRC || a.inject_rec)) f += st.val[pe.eb][t];
+        }
+    } else {
+        for (int v = pe.ea; v < pe.e; ++v) {
+            const Event ev = a.ev[v];
+            if (ev.lane != lane || ev_shot(ev.kind) != s) continue;
+            if (ev_kind(ev.kind) == EV_SRC)
+                f += ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
+            else if (a.inject_rec)
+                f += (T)a.rec_scale * ((const T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
+        }
+    }
+    return f;
+}
+
+// Trace and residual of the receivers at lane `lane`, shot slot s, for the new level.
+template <typename T>
+__device__ __forceinline__ void sample_receivers(const PlaneEvents& pe, const StepArgs& a,
+                                                 const EventStage<T>& st, int lane, int s, T uni)
+{
+    if (pe.staged) {
+        const int want = (lane << 8) | (s << 1) | EV_REC;
+        for (int t = 0; t < pe.e - pe.ea; ++t) {
+            if (st.key[pe.eb][t] != want) continue;
+            const int64_t o = (int64_t)a.row_rec * a.nrec + st.idx[pe.eb][t];
+            if (a.traces) ((T*)a.traces)[o] = uni;
+            if (a.resid) ((T*)a.resid)[o] = uni - st.obs[pe.eb][t];
+        }
+    } else {
+        for (int v = pe.ea; v < pe.e; ++v) {
+            const Event ev = a.ev[v];
+            if (ev.lane != lane || ev.kind != (EV_REC | (s << 1))) continue;
+            const int64_t o = (int64_t)a.row_rec * a.nrec + ev.idx;
+            if (a.traces) ((T*)a.traces)[o] = uni;
+            if (a.resid) ((T*)a.resid)[o] = uni - ((const T*)a.obs)[o];
+        }
+    }
+}
+
 // One block's share of one step: logical block b of problem `a`.  ACC = false compiles
 // a launch that never touches the accumulator (no registers held for it, which lets
 // more waves stay resident); with ACC = true a.acc_sign decides at run time.
@@ -230,19 +345,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
         }
     }
 
-    // events: the next plane group of this block, read one group ahead; the events of
-    // a plane (and their wavelet, adjoint force and observed values) are staged in
-    // LDS, double-buffered like the planes, so lanes scan them without global loads
-    // (staged event: key = lane << 8 | kind, kind = shot slot << 1 | source/receiver)
-    __shared__ int32_t skey[2][kStagedEvents];
-    __shared__ int32_t sidx[2][kStagedEvents];
-    __shared__ T sval[2][kStagedEvents];
-    __shared__ T sobs[2][kStagedEvents];
-    int gi = a.blk_off[b];
-    const int g_end = a.blk_off[b + 1];
-    EvPlane nextg;
-    nextg.plane = -1;
-    if (gi < g_end) nextg = a.grp[gi];
+    // events: a plane's sources and receivers (and their wavelet, adjoint force and
+    // observed values) are staged in LDS, so lanes scan them without global loads
+    __shared__ EventStage<T> est;
+    PlaneEvents pe;
+    events_begin(pe, a, b);
 
     for (int x = x0; x < x1; ++x) {
         const int64_t xo = (int64_t)x * ps;
@@ -287,35 +394,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
             for (int i = 0; i < NHZ; ++i)
                 if (hzl[i] >= 0) L[hzl[i]] = chz[s][i];
         }
-        // events of this plane (block-uniform): ev[ea, e)
-        const bool has_ev = nextg.plane == x;
-        int ea = 0, e = 0;
-        bool staged = false;
-        const int eb = x & 1;
-        if (has_ev) {
-            ea = nextg.begin;
-            e = nextg.end;
-            nextg.plane = -1;
-            if (++gi < g_end) nextg = a.grp[gi];
-            staged = e - ea <= kStagedEvents;
-            if (staged) {
-                for (int t = tid; t < e - ea; t += NT) {
-                    const Event ev = a.ev[ea + t];
-                    T v = (T)0, o = (T)0;
-                    if (ev_kind(ev.kind) == EV_SRC) {
-                        v = ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
-                    } else {
-                        const int64_t r = (int64_t)a.row_rec * a.nrec + ev.idx;
-                        if (a.inject_rec) v = (T)a.rec_scale * ((const T*)a.resid)[r];
-                        if (a.sample && a.resid) o = ((const T*)a.obs)[r];
-                    }
-                    skey[eb][t] = (ev.lane << 8) | ev.kind;
-                    sidx[eb][t] = ev.idx;
-                    sval[eb][t] = v;
-                    sobs[eb][t] = o;
-                }
-            }
-        }
+        events_at_plane<T, NT>(pe, a, est, x, tid);
         __syncthreads();
 
 #pragma unroll
@@ -347,28 +426,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     for (int j = 1; j <= R; ++j)
                         lap += w[j - 1] * ((L[s0 + i + j] - u0) + (L[s0 + i - j] - u0));
 
-                    if (has_ev) {   // a source or receiver lies in this plane
-                        T f = (T)0;
-                        if (staged) {
-                            // sources of this cell and slot, and receivers when injecting
-                            const int want = (((lane0[k] + i) << 8) | (s << 1)) >> 1;
-                            for (int t = 0; t < e - ea; ++t) {
-                                const int key = skey[eb][t];
-                                if ((key >> 1) == want && ((key & 1) == EV_SRC || a.inject_rec))
-                                    f += sval[eb][t];
-                            }
-                        } else {
-                            for (int v = ea; v < e; ++v) {
-                                const Event ev = a.ev[v];
-                                if (ev.lane != lane0[k] + i || ev_shot(ev.kind) != s) continue;
-                                if (ev_kind(ev.kind) == EV_SRC)
-                                    f += ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
-                                else if (a.inject_rec)
-                                    f += (T)a.rec_scale * ((const T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
-                            }
-                        }
-                        lap += f;
-                    }
+                    if (pe.has) lap += point_force(pe, a, est, lane0[k] + i, s);
 
                     const T uni = (u0 + u0) - el<T, VZ>(cu[s][k], i) + coef * lap;
                     set_el<T, VZ>(un[s], i, uni);
@@ -382,25 +440,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     } else {
                         dsum += d * d + dp * dp;
                     }
-                    if (a.sample && has_ev) {
-                        if (staged) {
-                            const int want = ((lane0[k] + i) << 8) | (s << 1) | EV_REC;
-                            for (int t = 0; t < e - ea; ++t) {
-                                if (skey[eb][t] != want) continue;
-                                const int64_t o = (int64_t)a.row_rec * a.nrec + sidx[eb][t];
-                                if (a.traces) ((T*)a.traces)[o] = uni;
-                                if (a.resid) ((T*)a.resid)[o] = uni - sobs[eb][t];
-                            }
-                        } else {
-                            for (int v = ea; v < e; ++v) {
-                                const Event ev = a.ev[v];
-                                if (ev.lane != lane0[k] + i || ev.kind != (EV_REC | (s << 1))) continue;
-                                const int64_t o = (int64_t)a.row_rec * a.nrec + ev.idx;
-                                if (a.traces) ((T*)a.traces)[o] = uni;
-                                if (a.resid) ((T*)a.resid)[o] = uni - ((const T*)a.obs)[o];
-                            }
-                        }
-                    }
+                    if (a.sample && pe.has) sample_receivers(pe, a, est, lane0[k] + i, s, uni);
                 }
                 if (use_acc) {
                     const AT ai = el<AT, VZ>(ca[k], i);

@@ -1,0 +1,293 @@
+// The paper's own second-order flux-form step with variable material (Sec. 3.1, Eqs.
+// FDstencil1/FDstencil2 in d dimensions), written as m u_tt - div(b grad u) = f with
+// a mass coefficient m and a stiffness coefficient b per cell:
+//
+//   u^{n+1} = 2 u^n - u^{n-1} + (dt^2 / m) (L_b u^n + f^n)
+//   (L_b u)_i = dx^-2 sum over the neighbours j of i:  h(b_i, b_j) (u_j - u_i),
+//   h(p, q) = 2 p q / (p + q)                        (harmonic mean at the face)
+//
+// Ghost cells mirror the boundary cell and carry its material, so wall faces carry no
+// flux.  The launch fuses the same per-step work as the constant-density step
+// (injection, sampling, residuals) and accumulates the two kernel terms of the
+// paper's gradient (Eqs. kernel1/kernel2) in discrete form:
+//   * mass term: (u^{n+1} - u^n)^2 per interval, into acc (two intervals every other
+//     launch, as in the constant-density sweeps);
+//   * stiffness term: sum over the faces of the cell of dh/db_i (u_j - u_i)^2 for the
+//     current level, with dh(p, q)/dp = 2 q^2 / (p + q)^2, into acc_b every launch.
+//
+// Layout of the work follows the constant-density step (2.5D marching along axis 0,
+// three-plane register queues for u and b, the current planes of u and b staged in
+// LDS with a one-cell halo, loads of plane x+1 issued before plane x is computed,
+// XCD-aware block order); one wavefield per launch.
+
+#include "fdw_step_body.h"
+
+namespace fdw {
+
+template <typename T, typename AT, int NDIM, int TZ, int TY, int VZ, bool ACC>
+__device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __restrict__ lds)
+{
+    typedef typename Vec<T, VZ>::type vec;
+    typedef typename Vec<AT, VZ>::type avec;
+    constexpr int NT = TZ * TY;
+    constexpr int WZ = TZ * VZ;
+    constexpr int RYH = (NDIM == 3) ? 1 : 0;
+    constexpr int PADL = VZ;                       // one halo cell, rows kept VZ-aligned
+    constexpr int LZ = PADL + WZ + PADL;
+    constexpr int LSZ = (TY + 2 * RYH) * LZ;       // one plane of one field
+    constexpr int HYV = (NDIM == 3) ? 2 * TZ : 0;  // halo row vectors above and below
+    constexpr int HZ = 2 * TY;                     // halo cells left and right
+    constexpr int NHY = (HYV + NT - 1) / NT;
+    constexpr int NHZ = (HZ + NT - 1) / NT;
+    constexpr int NHY1 = NHY > 0 ? NHY : 1;
+
+    const int tzb = b % a.ntz;
+    const int rest = b / a.ntz;
+    const int tyb = rest % a.nty;
+    const int chb = rest / a.nty;
+    const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
+    const int z0 = tzb * WZ, y0 = tyb * TY;
+    const int x0 = chb * a.chunk_len;
+    const int x1 = min(x0 + a.chunk_len, n0);
+    const int tid = threadIdx.x;
+    const int lz = tid % TZ;
+    const int ly = tid / TZ;
+    const int z = z0 + lz * VZ;
+    const int y = y0 + ly;
+    const bool live = z < n2 && y < n1;
+    const int64_t ps = (int64_t)n1 * n2;
+    const int roff = ghost(y, n1) * n2;
+    const int lofs = (ly + RYH) * LZ + PADL + lz * VZ;
+    const int lane0 = ly * WZ + lz * VZ;
+
+    const T* __restrict__ ucur = (const T*)a.ucur;
+    T* __restrict__ unew = (T*)a.unew;
+    const T* __restrict__ mass = (const T*)a.c;
+    const T* __restrict__ stiff = (const T*)a.stiff;
+    AT* __restrict__ acc = (AT*)a.acc;
+    AT* __restrict__ accb = (AT*)a.acc_b;
+    const bool use_acc = ACC && a.acc_sign != 0;
+    const bool use_accb = ACC && a.acc_face != 0;
+    const T inv_dx2 = (T)a.w[0];
+    const T dt2 = (T)a.dt2;
+
+    // halo rows (3D) and halo columns: LDS slot and in-plane offset
+    int hyl[NHY1], hyr[NHY1], hyz[NHY1];
+#pragma unroll
+    for (int i = 0; i < NHY; ++i) {
+        const int h = tid + i * NT;
+        const int row = h / TZ;                   // 0: the row above the tile, 1: below
+        const int sy = row < 1 ? 0 : TY + 1;
+        const int cz = (h % TZ) * VZ;
+        hyl[i] = h < HYV ? sy * LZ + PADL + cz : -1;
+        hyr[i] = ghost(y0 + sy - 1, n1) * n2;
+        hyz[i] = z0 + cz;
+    }
+    int hzl[NHZ], hzg[NHZ];
+#pragma unroll
+    for (int i = 0; i < NHZ; ++i) {
+        const int h = tid + i * NT;
+        const int row = h / 2;
+        const int sz = (h % 2) == 0 ? PADL - 1 : PADL + WZ;
+        hzl[i] = h < HZ ? (RYH + row) * LZ + sz : -1;
+        hzg[i] = ghost(y0 + (h < HZ ? row : 0), n1) * n2 + ghost(z0 + sz - PADL, n2);
+    }
+
+    // register queues along axis 0: planes x-1, x, x+1 of u^n and of b
+    vec qu[3], qb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t xo = (int64_t)ghost(x0 - 1 + d, n0) * ps + roff;
+        qu[d] = load_row<T, VZ, false, true>(ucur + xo, z, n2);
+        qb[d] = load_row<T, VZ, false, true>(stiff + xo, z, n2);
+    }
+    // plane-x operands, loaded one plane ahead
+    vec cu, cm, chyu[NHY1], chyb[NHY1];
+    avec ca, cab;
+    T chzu[NHZ], chzb[NHZ];
+    {
+        const int64_t xo = (int64_t)x0 * ps;
+        cu = load_row<T, VZ, true, false>(unew + xo + roff, z, n2);
+        cm = load_row<T, VZ, true, false>(mass + xo + roff, z, n2);
+        if (use_acc) ca = load_row<AT, VZ, true, false>(acc + xo + roff, z, n2);
+        if (use_accb) cab = load_row<AT, VZ, true, false>(accb + xo + roff, z, n2);
+#pragma unroll
+        for (int i = 0; i < NHY; ++i)
+            if (hyl[i] >= 0) {
+                chyu[i] = load_row<T, VZ, false, true>(ucur + xo + hyr[i], hyz[i], n2);
+                chyb[i] = load_row<T, VZ, false, true>(stiff + xo + hyr[i], hyz[i], n2);
+            }
+#pragma unroll
+        for (int i = 0; i < NHZ; ++i) {
+            chzu[i] = hzl[i] >= 0 ? ucur[xo + hzg[i]] : (T)0;
+            chzb[i] = hzl[i] >= 0 ? stiff[xo + hzg[i]] : (T)0;
+        }
+    }
+
+    __shared__ EventStage<T> est;
+    PlaneEvents pe;
+    events_begin(pe, a, b);
+
+    for (int x = x0; x < x1; ++x) {
+        const int64_t xo = (int64_t)x * ps;
+        // issue the loads of plane x + 1
+        vec nqu, nqb, ncu, ncm, nhyu[NHY1], nhyb[NHY1];
+        avec nca, ncab;
+        T nhzu[NHZ], nhzb[NHZ];
+        const bool more = x + 1 < x1;
+        if (more) {
+            const int64_t xn = xo + ps;
+            const int64_t xq = (int64_t)ghost(x + 2, n0) * ps + roff;
+            nqu = load_row<T, VZ, false, true>(ucur + xq, z, n2);
+            nqb = load_row<T, VZ, false, true>(stiff + xq, z, n2);
+            ncu = load_row<T, VZ, true, false>(unew + xn + roff, z, n2);
+            ncm = load_row<T, VZ, true, false>(mass + xn + roff, z, n2);
+            if (use_acc) nca = load_row<AT, VZ, true, false>(acc + xn + roff, z, n2);
+            if (use_accb) ncab = load_row<AT, VZ, true, false>(accb + xn + roff, z, n2);
+#pragma unroll
+            for (int i = 0; i < NHY; ++i)
+                if (hyl[i] >= 0) {
+                    nhyu[i] = load_row<T, VZ, false, true>(ucur + xn + hyr[i], hyz[i], n2);
+                    nhyb[i] = load_row<T, VZ, false, true>(stiff + xn + hyr[i], hyz[i], n2);
+                }
+#pragma unroll
+            for (int i = 0; i < NHZ; ++i) {
+                nhzu[i] = hzl[i] >= 0 ? ucur[xn + hzg[i]] : (T)0;
+                nhzb[i] = hzl[i] >= 0 ? stiff[xn + hzg[i]] : (T)0;
+            }
+        }
+
+        // stage plane x of u and of b
+        T* Lu = lds + (x & 1) * 2 * LSZ;
+        T* Lb = Lu + LSZ;
+        *(vec*)(Lu + lofs) = qu[1];
+        *(vec*)(Lb + lofs) = qb[1];
+#pragma unroll
+        for (int i = 0; i < NHY; ++i)
+            if (hyl[i] >= 0) {
+                *(vec*)(Lu + hyl[i]) = chyu[i];
+                *(vec*)(Lb + hyl[i]) = chyb[i];
+            }
+#pragma unroll
+        for (int i = 0; i < NHZ; ++i)
+            if (hzl[i] >= 0) {
+                Lu[hzl[i]] = chzu[i];
+                Lb[hzl[i]] = chzb[i];
+            }
+        events_at_plane<T, NT>(pe, a, est, x, tid);
+        __syncthreads();
+
+        if (live) {
+            vec un;
+            avec an, abn;
+#pragma unroll
+            for (int i = 0; i < VZ; ++i) {
+                const T u0 = el<T, VZ>(qu[1], i);
+                const T b0 = el<T, VZ>(qb[1], i);
+                T lap = (T)0;
+                AT fb = (AT)0;
+                auto face = [&](T uj, T bj) {
+                    const T sb = b0 + bj;
+                    const T d = uj - u0;
+                    lap += (T)2 * b0 * bj / sb * d;
+                    if (use_accb) {
+                        const AT w = (AT)2 * (AT)bj * (AT)bj / ((AT)sb * (AT)sb);
+                        fb += w * (AT)d * (AT)d;
+                    }
+                };
+                face(el<T, VZ>(qu[0], i), el<T, VZ>(qb[0], i));
+                face(el<T, VZ>(qu[2], i), el<T, VZ>(qb[2], i));
+                if (NDIM == 3) {
+                    face(Lu[lofs + i - LZ], Lb[lofs + i - LZ]);
+                    face(Lu[lofs + i + LZ], Lb[lofs + i + LZ]);
+                }
+                face(Lu[lofs + i - 1], Lb[lofs + i - 1]);
+                face(Lu[lofs + i + 1], Lb[lofs + i + 1]);
+                lap *= inv_dx2;
+                if (pe.has) lap += point_force(pe, a, est, lane0 + i, 0);
+                const T cui = el<T, VZ>(cu, i);
+                const T coef = dt2 / el<T, VZ>(cm, i);
+                const T uni = (u0 + u0) - cui + coef * lap;
+                set_el<T, VZ>(un, i, uni);
+                if (a.sample && pe.has) sample_receivers(pe, a, est, lane0 + i, 0, uni);
+                if (use_acc) {
+                    const AT d = (AT)(uni - u0);
+                    const AT dp = a.acc_prev ? (AT)(u0 - cui) : (AT)0;
+                    const AT dsum = d * d + dp * dp;
+                    const AT ai = el<AT, VZ>(ca, i);
+                    set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + dsum : ai - dsum);
+                }
+                if (use_accb) {
+                    const AT bi = el<AT, VZ>(cab, i);
+                    set_el<AT, VZ>(abn, i, a.acc_face > 0 ? bi + fb : bi - fb);
+                }
+            }
+            __builtin_nontemporal_store(un, (vec*)(unew + xo + roff + z));
+            if (use_acc) __builtin_nontemporal_store(an, (avec*)(acc + xo + roff + z));
+            if (use_accb) __builtin_nontemporal_store(abn, (avec*)(accb + xo + roff + z));
+        }
+
+        // rotate to plane x + 1
+        if (more) {
+            qu[0] = qu[1]; qu[1] = qu[2]; qu[2] = nqu;
+            qb[0] = qb[1]; qb[1] = qb[2]; qb[2] = nqb;
+            cu = ncu;
+            cm = ncm;
+            if (use_acc) ca = nca;
+            if (use_accb) cab = ncab;
+#pragma unroll
+            for (int i = 0; i < NHY; ++i) { chyu[i] = nhyu[i]; chyb[i] = nhyb[i]; }
+#pragma unroll
+            for (int i = 0; i < NHZ; ++i) { chzu[i] = nhzu[i]; chzb[i] = nhzb[i]; }
+        }
+    }
+}
+
+template <typename T, typename AT, int NDIM, int TZ, int TY, int VZ, bool ACC>
+__global__ __launch_bounds__(TZ * TY) void vd_step_kernel(StepArgs a)
+{
+    constexpr int LZ = 2 * VZ + TZ * VZ;
+    constexpr int LSZ = (TY + ((NDIM == 3) ? 2 : 0)) * LZ;
+    __shared__ __attribute__((aligned(16))) T lds[2 * 2 * LSZ];
+    const int b = logical_block(a.nblk);
+    if (b >= a.nblk) return;
+    vd_body<T, AT, NDIM, TZ, TY, VZ, ACC>(a, b, lds);
+}
+
+template <typename T, typename AT, int NDIM, int TZ, int TY, int VZ>
+static hipError_t launch_vd_one(int nblk, const StepArgs& a, hipStream_t s)
+{
+    const int grid = ((nblk + 7) / 8) * 8;
+    if (a.acc_sign != 0 || a.acc_face != 0)
+        hipLaunchKernelGGL((vd_step_kernel<T, AT, NDIM, TZ, TY, VZ, true>), dim3(grid), dim3(TZ * TY), 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL((vd_step_kernel<T, AT, NDIM, TZ, TY, VZ, false>), dim3(grid), dim3(TZ * TY),
+                           0, s, a);
+    return hipGetLastError();
+}
+
+// The tile shapes of step variants 1 and 2 (one or two cells per lane), so the
+// block decomposition and event lists of a plan serve both kernels.
+template <typename T, typename AT>
+static hipError_t launch_vd_rt(int ndim, int variant, int nblk, const StepArgs& a, hipStream_t s)
+{
+    if (ndim == 3) {
+        if (variant == 1) return launch_vd_one<T, AT, 3, 64, 8, 1>(nblk, a, s);
+        if (variant == 2) return launch_vd_one<T, AT, 3, 64, 8, 2>(nblk, a, s);
+    } else {
+        if (variant == 1) return launch_vd_one<T, AT, 2, 64, 1, 1>(nblk, a, s);
+        if (variant == 2) return launch_vd_one<T, AT, 2, 64, 1, 2>(nblk, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_vd_step(int ndim, int dtype, int acc_dtype, int variant, int nblk, const StepArgs& a,
+                          hipStream_t s)
+{
+    if (dtype == 1) return launch_vd_rt<double, double>(ndim, variant, nblk, a, s);
+    if (acc_dtype == 1) return launch_vd_rt<float, double>(ndim, variant, nblk, a, s);
+    return launch_vd_rt<float, float>(ndim, variant, nblk, a, s);
+}
+
+}  // namespace fdw

@@ -91,6 +91,8 @@ def _load():
         "fd_misfit": ([I, I, I, D, P, P, P, DP, P], ctypes.c_int),
         "fd_adjoint_sensitivity": ([G, P, A, D, I, P, D, P, DP, P, O, P], ctypes.c_int),
         "fd_adjoint_exact": ([G, P, A, D, I, P, P, DP, P, O, P], ctypes.c_int),
+        "fd_vd_forward": ([G, P, P, A, D, I, P, O, P], ctypes.c_int),
+        "fd_vd_adjoint_sensitivity": ([G, P, P, A, D, I, P, D, P, P, DP, P, O, P], ctypes.c_int),
         "fd_sens_forward": ([G, P, A, D, I, P, S, P, DP, O, P], ctypes.c_int),
         "fd_sens_backward": ([G, P, A, D, I, D, S, D, P, O, P], ctypes.c_int),
         "fd_adjoint_sensitivity_batched": ([ctypes.POINTER(fd_problem), I, DP, O, P], ctypes.c_int),
@@ -281,6 +283,34 @@ def fd_adjoint_exact(c, dx, order, src, wavelet, rec, dt, nt, observed, grad=Non
                                  _dev(observed, "observed"), _dev(grad, "grad"), ctypes.byref(J),
                                  _dev(traces, "traces"), ctypes.byref(o), _stream()))
     return grad, J.value
+
+
+def fd_vd_forward(m, b, dx, src, wavelet, rec, dt, nt, traces=None, shots=None, **opts):
+    """Traces [nt][nrec] of the variable-material second-order scheme (mass m, stiffness b)."""
+    acq = _acq(src, wavelet, rec, shots)
+    if traces is None:
+        traces = torch.empty((int(nt), acq.c.nrec), dtype=m.dtype, device=m.device)
+    g = make_grid(m.shape, dx, 2, _dtype_code(m))
+    o = make_opts(**opts)
+    _raise(_lib.fd_vd_forward(ctypes.byref(g), _dev(m, "m"), _dev(b, "b"), ctypes.byref(acq.c), float(dt),
+                              int(nt), _dev(traces, "traces"), ctypes.byref(o), _stream()))
+    return traces
+
+
+def fd_vd_adjoint_sensitivity(m, b, dx, src, wavelet, rec, dt, nt, observed, k, grad_m=None, grad_b=None,
+                              traces=None, shots=None, **opts):
+    """(grad_m, grad_b, J) of Alg. 1 for the variable-material second-order scheme."""
+    acq = _acq(src, wavelet, rec, shots)
+    grad_m = torch.empty_like(m) if grad_m is None else grad_m
+    grad_b = torch.empty_like(m) if grad_b is None else grad_b
+    g = make_grid(m.shape, dx, 2, _dtype_code(m))
+    o = make_opts(**opts)
+    J = ctypes.c_double()
+    _raise(_lib.fd_vd_adjoint_sensitivity(ctypes.byref(g), _dev(m, "m"), _dev(b, "b"), ctypes.byref(acq.c),
+                                          float(dt), int(nt), _dev(observed, "observed"), float(k),
+                                          _dev(grad_m, "grad_m"), _dev(grad_b, "grad_b"), ctypes.byref(J),
+                                          _dev(traces, "traces"), ctypes.byref(o), _stream()))
+    return grad_m, grad_b, J.value
 
 
 class SweepState:

@@ -126,6 +126,25 @@ def test_exact_validation(fdw):
              None) == fdw.FD_E_ARG
 
 
+def test_vd_rejects_other_orders_and_variants(fdw):
+    """The variable-material scheme is second order and runs tile variants 1 and 2; both
+    are checked before any device work."""
+    a = fdw.fd_acq()
+    J = ctypes.c_double()
+    f = fdw.lib().fd_vd_adjoint_sensitivity
+    g4 = fdw.make_grid((16, 16), 1.0, 4, fdw.FD_F64)
+    assert f(ctypes.byref(g4), None, None, ctypes.byref(a), 0.1, 10, None, 0.1, None, None,
+             ctypes.byref(J), None, None, None) == fdw.FD_E_ARG
+    assert "second order" in fdw.lib().fd_last_error().decode()
+    g2 = fdw.make_grid((16, 16), 1.0, 2, fdw.FD_F64)
+    o = fdw.make_opts(variant=3)
+    assert f(ctypes.byref(g2), None, None, ctypes.byref(a), 0.1, 10, None, 0.1, None, None,
+             ctypes.byref(J), None, ctypes.byref(o), None) == fdw.FD_E_ARG
+    assert "variants 1 and 2" in fdw.lib().fd_last_error().decode()
+    assert fdw.lib().fd_vd_forward(ctypes.byref(g2), None, None, None, 0.1, 10, None, None,
+                                   None) == fdw.FD_E_ARG
+
+
 def test_variant_info_reports_fields_per_launch(fdw):
     for nd in (2, 3):
         fields = [fdw.fd_variant_info(nd, v)["max_fields"] for v in range(1, fdw.fd_variant_count(nd) + 1)]

@@ -1,0 +1,178 @@
+"""The paper's own second-order flux-form scheme with variable material on the device
+(fd_vd_forward, fd_vd_adjoint_sensitivity) against the oracle's vdoracle.c: traces,
+J and both sensitivities (mass m and stiffness b) element by element at the same k,
+the gap to the oracle's exact gradient against its closed forms, the reduction to the
+constant-density order-2 path for b = 1, shot batches and the error paths.
+
+Tolerances: f64 traces and J 1e-12, sensitivities 1e-9 relative L2; f32 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2509_15744_amd import workloads as wl
+from helpers import rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fdw():
+    assert torch.cuda.is_available(), "the gpu tests need a HIP device"
+    from paper_2509_15744_amd import fdwave
+    return fdwave
+
+
+def _medium(shape, seed, nt, nsrc=2, nrec=9, layered=False):
+    """Random (or layered) mass and stiffness, random cells for sources and receivers
+    with a duplicate receiver and a receiver on a source."""
+    rng = np.random.default_rng(seed)
+    if layered:
+        depth = np.arange(shape[0])[(slice(None),) + (None,) * (len(shape) - 1)]
+        m = np.broadcast_to(1.0 + 0.8 * (depth > shape[0] // 2), shape).copy()
+        b = np.broadcast_to(1.0 + 2.0 * (depth > shape[0] // 3), shape).copy()
+        m *= 1.0 + 0.05 * rng.standard_normal(shape)
+    else:
+        m = 0.5 + rng.random(shape)
+        b = 0.5 + rng.random(shape)
+    dt = 0.45 / np.sqrt(len(shape) * b.max() / m.min())
+    n = int(np.prod(shape))
+    src = rng.integers(0, n, nsrc).astype(np.int64)
+    rec = rng.integers(0, n, nrec).astype(np.int64)
+    rec[-1] = rec[0]
+    rec[1] = src[0]
+    w = rng.standard_normal((nt, nsrc))
+    obs = 0.05 * rng.standard_normal((nt, nrec))
+    return m, b, dt, src, rec, w, obs
+
+
+def _run(fdw, m, b, dt, nt, src, w, rec, obs, k, dtype, dx=1.0, **opts):
+    tr = torch.empty((nt, len(rec)), dtype=dtype, device="cuda")
+    gm, gb, J = fdw.fd_vd_adjoint_sensitivity(to_dev(m, dtype), to_dev(b, dtype), dx, src, to_dev(w, dtype),
+                                              rec, dt, nt, to_dev(obs, dtype), k, traces=tr, **opts)
+    torch.cuda.synchronize()
+    return gm.double().cpu().numpy(), gb.double().cpu().numpy(), J, tr.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("shape,nt,seed,dx", [
+    ((50, 70), 60, 1, 1.0),          # 2D, ragged tail along the contiguous axis
+    ((37, 130), 45, 2, 0.5),         # 2D, several tiles plus a tail, dx != 1
+    ((14, 11, 70), 40, 3, 1.0),      # 3D, ragged in both in-plane axes
+    ((20, 18, 132), 30, 4, 2.0),
+    ((5, 3, 4), 20, 5, 1.0),         # narrower than every tile
+])
+def test_vd_matches_oracle_f64(fdw, shape, nt, seed, dx):
+    m, b, dt, src, rec, w, obs = _medium(shape, seed, nt)
+    dt *= dx
+    k = 0.03
+    om, ob, oJ, otr = oracle.vd_superposition_gradient(m, b, dx, dt, nt, src, w, rec, obs, k)
+    for variant in (1, 2):
+        if shape[-1] % variant:
+            continue
+        say("vd f64", shape, nt, "variant", variant)
+        gm, gb, J, tr = _run(fdw, m, b, dt, nt, src, w, rec, obs, k, torch.float64, dx=dx, variant=variant)
+        assert rel(tr, otr) < 1e-12
+        assert abs(J - oJ) <= 1e-12 * oJ
+        assert rel(gm, om) < 1e-9, rel(gm, om)
+        assert rel(gb, ob) < 1e-9, rel(gb, ob)
+
+
+def test_vd_gap_matches_closed_forms(fdw):
+    """Device Alg. 1 minus the oracle's exact gradient equals -(k/2) s2_m (mass) and
+    (dt^2/dx^2)(k/2) s2_b (stiffness), computed from the oracle's adjoint field."""
+    shape, nt = (26, 19, 70), 50
+    m, b, dt, src, rec, w, obs = _medium(shape, 21, nt, nrec=12)
+    em, eb, _, s2m, s2b, _ = oracle.vd_exact_gradient(m, b, 1.0, dt, nt, src, w, rec, obs)
+    k = 0.05
+    say("vd gap closed forms")
+    gm, gb, _, _ = _run(fdw, m, b, dt, nt, src, w, rec, obs, k, torch.float64)
+    assert rel(gm - em, -0.5 * k * s2m) < 1e-6
+    assert rel(gb - eb, 0.5 * k * dt * dt * s2b) < 1e-6
+
+
+@pytest.mark.parametrize("acc", ["f64", "f32"])
+def test_vd_f32(fdw, acc):
+    shape, nt = (40, 24, 128), 300
+    m, b, dt, src, rec, w, obs = _medium(shape, 9, nt, nrec=16, layered=True)
+    k = 0.05
+    om, ob, oJ, otr = oracle.vd_superposition_gradient(m, b, 1.0, dt, nt, src, w, rec, obs, k)
+    say("vd f32, acc", acc)
+    gm, gb, J, tr = _run(fdw, m, b, dt, nt, src, w, rec, obs, k, torch.float32, acc_dtype=acc)
+    assert rel(tr, otr) < 1e-4
+    assert abs(J - oJ) < 1e-4 * oJ
+    tol = 1e-4 if acc == "f64" else 1e-3
+    assert rel(gm, om) < tol, rel(gm, om)
+    assert rel(gb, ob) < tol, rel(gb, ob)
+
+
+def test_vd_with_unit_stiffness_is_the_order2_path(fdw):
+    """b = 1, m = 1/c^2: traces and J equal the constant-density order-2 path and
+    -(2/c^3) grad_m equals its grad_c (f64, rounding level)."""
+    p = wl.small_random((16, 12, 66), order=2, nt=40, dtype="f64", seed=8)
+    f64 = torch.float64
+    obs = np.zeros((p.nt, len(p.rec)))
+    k = 0.04
+    say("vd with b = 1 vs order-2 path")
+    tr_c = torch.empty((p.nt, len(p.rec)), dtype=f64, device="cuda")
+    gc, Jc = fdw.fd_adjoint_sensitivity(to_dev(p.c, f64), 1.0, 2, p.src, to_dev(p.wavelet, f64), p.rec, p.dt,
+                                        p.nt, to_dev(obs, f64), k, traces=tr_c)
+    gm, gb, J, tr = _run(fdw, 1.0 / p.c ** 2, np.ones(p.c.shape), p.dt, p.nt, p.src, p.wavelet, p.rec, obs,
+                         k, f64)
+    assert rel(tr, tr_c.cpu().numpy()) < 1e-12
+    assert abs(J - Jc) <= 1e-12 * Jc
+    assert rel(-2.0 / p.c ** 3 * gm, gc.cpu().numpy()) < 1e-9
+
+
+def test_vd_shots_and_forward(fdw):
+    """Three shots on one medium equal the sum of per-shot oracle runs; fd_vd_forward
+    traces equal the oracle's forward solve."""
+    shape, nt = (18, 13, 64), 35
+    m, b, dt, _, _, _, _ = _medium(shape, 31, nt)
+    rng = np.random.default_rng(32)
+    n = int(np.prod(shape))
+    src = rng.integers(0, n, 3).astype(np.int64)
+    rec = rng.integers(0, n, 9).astype(np.int64)
+    src_shot = np.arange(3, dtype=np.int32)
+    rec_shot = np.repeat(np.arange(3, dtype=np.int32), 3)
+    w = rng.standard_normal((nt, 3))
+    obs = 0.05 * rng.standard_normal((nt, 9))
+    k = 0.02
+    om, ob, oJ = np.zeros(shape), np.zeros(shape), 0.0
+    for s in range(3):
+        ri = np.where(rec_shot == s)[0]
+        a, bb, J, _ = oracle.vd_superposition_gradient(m, b, 1.0, dt, nt, src[s:s + 1], w[:, s:s + 1], rec[ri],
+                                                       obs[:, ri], k)
+        om += a
+        ob += bb
+        oJ += J
+    f64 = torch.float64
+    say("vd shots")
+    gm, gb, J = fdw.fd_vd_adjoint_sensitivity(to_dev(m, f64), to_dev(b, f64), 1.0, src, to_dev(w, f64), rec, dt,
+                                              nt, to_dev(obs, f64), k, shots=(src_shot, rec_shot, 3))
+    assert abs(J - oJ) <= 1e-12 * oJ
+    assert rel(gm.cpu().numpy(), om) < 1e-9 and rel(gb.cpu().numpy(), ob) < 1e-9
+    tr = fdw.fd_vd_forward(to_dev(m, f64), to_dev(b, f64), 1.0, src[:1], to_dev(w[:, :1], f64), rec, dt, nt)
+    otr, _, _ = oracle.vd_forward(m, b, 1.0, dt, nt, src[:1], w[:, :1], rec)
+    assert rel(tr.cpu().numpy(), otr) < 1e-12
+
+
+def test_vd_error_paths(fdw):
+    shape, nt = (12, 10, 64), 10
+    m, b, dt, src, rec, w, obs = _medium(shape, 41, nt)
+    f64 = torch.float64
+    md, bd, wd, od = to_dev(m, f64), to_dev(b, f64), to_dev(w, f64), to_dev(obs, f64)
+    with pytest.raises(fdw.FdError) as e:      # stability bound
+        fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, 3 * dt, nt, od, 0.1)
+    assert e.value.code == fdw.FD_E_CFL
+    with pytest.raises(fdw.FdError) as e:      # a non-positive mass
+        m2 = m.copy()
+        m2[3, 4, 5] = 0.0
+        fdw.fd_vd_adjoint_sensitivity(to_dev(m2, f64), bd, 1.0, src, wd, rec, dt, nt, od, 0.1)
+    assert e.value.code == fdw.FD_E_NONFINITE
+    with pytest.raises(fdw.FdError) as e:      # tile variant without a variable-material kernel
+        fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, dt, nt, od, 0.1, variant=3)
+    assert e.value.code == fdw.FD_E_ARG
+    with pytest.raises(fdw.FdError) as e:      # k = 0
+        fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, dt, nt, od, 0.0)
+    assert e.value.code == fdw.FD_E_ARG
