@@ -13,8 +13,10 @@ is autotuned in the untimed setup.
 
 Workloads: layered3d (default; 1024^3, order 8, nt 3000, one shot), layered2d (2048^2,
 order 8, nt 4000), shots3d (4 shots on 1024^3), shots2d (32 shots on 2048^2),
-problems2d (16 independent layered problems, sides 256..2048).  ``--method exact`` times
-the exact re-simulation gradient (fd_adjoint_exact) instead of the superposition.
+problems2d (16 independent layered problems, sides 256..2048), vd3d (the paper's own
+second-order flux-form scheme with variable mass and stiffness on a layered 1024^3
+medium, both sensitivities).  ``--method exact`` times the exact re-simulation gradient
+(fd_adjoint_exact) instead of the superposition.
 
 After the timed region (single-medium workloads, superposition): the gap of the
 gradient to the exact discrete gradient at full size (fd_adjoint_exact on the device),
@@ -50,6 +52,14 @@ def step_bytes(group, acc):
     kernel terms also reads and writes the accumulator once.  Returns (with, without)."""
     a = 8 if acc == "f64" else 4
     return 12 * group + 4 + 2 * a, 12 * group + 4
+
+
+def vd_step_bytes(acc):
+    """Algorithmic HBM bytes per cell of one variable-material step launch: read u^n, b,
+    m, u^{n-1}, write u^{n+1}, and read and write the stiffness accumulator; a launch
+    that adds mass terms also reads and writes the mass accumulator.  (with, without)."""
+    a = 8 if acc == "f64" else 4
+    return 20 + 4 * a, 20 + 2 * a
 
 
 def accumulating_launches(nt):
@@ -297,6 +307,83 @@ def run_single(args, np, torch, fdw, wl):
     return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, bpu), p, c, acc_info
 
 
+def cpu_baseline_vd(q, m_dev, b_dev, wl):
+    """The FP64 oracle of the variable-material scheme on a bounded sample of the same
+    workload: a 128 x 256 x 256 crop around the source with the receivers inside it,
+    nt = 20 (forward + superposed backward sweep)."""
+    import numpy as np
+    import oracle
+    shape = q["shape"]
+    crop = (min(128, shape[0]), min(256, shape[1]), min(256, shape[2]))
+    nt_s = 20
+    sx = [int(v) for v in np.unravel_index(int(q["src"][0]), shape)]
+    lo = [max(0, min(sx[a] - crop[a] // 2, shape[a] - crop[a])) for a in range(3)]
+    sl = tuple(slice(lo[a], lo[a] + crop[a]) for a in range(3))
+    m = m_dev[sl].double().cpu().numpy()
+    b = b_dev[sl].double().cpu().numpy()
+    rc = np.array(np.unravel_index(q["rec"], shape)).T
+    inside = np.all([(rc[:, a] >= lo[a]) & (rc[:, a] < lo[a] + crop[a]) for a in range(3)], axis=0)
+    rec = wl.flat(crop, rc[inside] - np.array(lo))
+    src = wl.flat(crop, [[sx[a] - lo[a] for a in range(3)]])
+    obs = np.zeros((nt_s, len(rec)))
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.vd_superposition_gradient(m, b, q["dx"], q["dt"], nt_s, src, q["wavelet"][:nt_s], rec, obs, 1e-3)
+    el = time.perf_counter() - t0
+    upd = int(np.prod(crop)) * (2 * nt_s - 1)
+    return {"value": upd / el / 1e9, "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle (variable material), crop {'x'.join(map(str, crop))} of the same medium "
+                      f"around the source, {len(rec)} receivers, nt={nt_s}, one shot "
+                      f"({upd:.3g} cell-updates in {el:.1f} s)"}
+
+
+def run_vd(args, np, torch, fdw, wl):
+    """The paper's second-order flux-form scheme with variable mass and stiffness on the
+    layered 1024^3 medium: one gradient = fd_vd_adjoint_sensitivity (both sensitivities)."""
+    from paper_2509_15744_amd import calibrate
+    n = args.n or 1024
+    nt = args.nt or 3000
+    q = wl.layered_material_3d(n=n, nt=nt, device="cuda")
+    desc = (f"vd3d {n}^3 f32 order-2 variable mass and stiffness nt={nt}, 1 shot(s), "
+            f"{len(q['rec'])} receivers each")
+    log("workload:", desc, f"dt={q['dt']:.5g}")
+    w = torch.as_tensor(q["wavelet"], dtype=torch.float32, device="cuda")
+    variant = args.variant or 2
+    opts = dict(acc_dtype=args.acc, variant=variant, chunk=args.chunk)
+    obs = fdw.fd_vd_forward(q["m_ref"], q["b_ref"], q["dx"], q["src"], w, q["rec"], q["dt"], nt, **opts)
+    tr = fdw.fd_vd_forward(q["m"], q["b"], q["dx"], q["src"], w, q["rec"], q["dt"], nt, **opts)
+    J0 = fdw.fd_misfit(tr, obs, q["dt"])
+    del q["m_ref"], q["b_ref"], tr
+    k = calibrate.auto_k(J0, q["dt"], float(np.linalg.norm(q["wavelet"])), q["dx"], 3, args.beta)
+    gm, gb = torch.empty_like(q["m"]), torch.empty_like(q["m"])
+    torch.cuda.synchronize()
+    timings, holder = [], {}
+
+    def one_step(record):
+        t = fdw.fd_timing()
+        _, _, J = fdw.fd_vd_adjoint_sensitivity(q["m"], q["b"], q["dx"], q["src"], w, q["rec"], q["dt"], nt,
+                                                obs, k, grad_m=gm, grad_b=gb, timing=t, **opts)
+        holder["J"] = J
+        if record:
+            timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
+
+    elapsed = timed(args, torch, one_step)
+    ncell = n ** 3
+    upd = ncell * (2 * nt - 1)
+    launches = sum(t[1] + t[3] for t in timings)
+    kern_ms = sum(t[0] + t[2] for t in timings)
+    per_cell = gradient_bytes(nt, vd_step_bytes(args.acc), vd_step_bytes(args.acc))
+    bytes_all = ncell * per_cell * args.steps
+    cfg = {"workload": desc, "grid": [n, n, n], "nt": nt, "order": 2, "shots": 1, "receivers": len(q["rec"]),
+           "accumulator": args.acc, "method": "superposition", "k": k, "J": holder["J"],
+           "launch_shape": {"variant": variant, "chunk": args.chunk}, "cell_updates_per_step": upd}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, variable material) ...")
+        cfg["_cpu_baseline"] = cpu_baseline_vd(q, q["m"], q["b"], wl)
+    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, per_cell / (2 * nt - 1)), None, None, None
+
+
 def run_problems(args, np, torch, fdw, wl):
     """16 independent layered problems with sides drawn uniformly from 256..2048 (seeded),
     each with its own medium, dt, source at the top centre and receivers every 4 cells."""
@@ -393,7 +480,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="layered3d",
-                    choices=["layered3d", "layered2d", "shots3d", "shots2d", "problems2d"])
+                    choices=["layered3d", "layered2d", "shots3d", "shots2d", "problems2d", "vd3d"])
     ap.add_argument("--n", type=int, default=0, help="grid side (default: 1024 in 3D, 2048 in 2D)")
     ap.add_argument("--nt", type=int, default=0, help="time steps (default: 3000 in 3D, 4000 in 2D)")
     ap.add_argument("--acc", default="f64", choices=["f64", "f32"])
@@ -421,7 +508,7 @@ def main():
 
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    runner = run_problems if args.workload == "problems2d" else run_single
+    runner = {"problems2d": run_problems, "vd3d": run_vd}.get(args.workload, run_single)
     upd, elapsed, cfg, (bytes_launch, avg_ms, bpu), p0, c0, accuracy = runner(args, np, torch, fdw, wl)
     if accuracy is not None:
         log("accuracy: 256^3 gradients against the oracle references ...")
@@ -453,7 +540,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args),
-            "kernel": "fdw::step_kernel" if args.workload != "problems2d" else "fdw::step_multi_kernel",
+            "kernel": {"problems2d": "fdw::step_multi_kernel", "vd3d": "fdw::vd_step_kernel"}.get(
+                args.workload, "fdw::step_kernel"),
             "avg_launch_ms": round(avg_ms, 4),
             "bytes_per_launch": bytes_launch,
             "bytes_per_shot_cell_update": bpu,
@@ -461,7 +549,9 @@ def main():
     }
     if accuracy is not None:
         out["accuracy"] = accuracy
-    if not args.no_cpu_baseline:
+    if "_cpu_baseline" in cfg:
+        out["cpu_baseline"] = cfg.pop("_cpu_baseline")
+    elif not args.no_cpu_baseline and p0 is not None:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p0, c0, wl)
     print(json.dumps(out), flush=True)

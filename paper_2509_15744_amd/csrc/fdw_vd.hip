@@ -24,6 +24,10 @@
 
 namespace fdw {
 
+// 1/x: the hardware reciprocal for f32 (within 1 ulp), an exact division for f64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename T, typename AT, int NDIM, int TZ, int TY, int VZ, bool ACC>
 __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __restrict__ lds)
 {
@@ -185,15 +189,13 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
                 const T u0 = el<T, VZ>(qu[1], i);
                 const T b0 = el<T, VZ>(qb[1], i);
                 T lap = (T)0;
-                AT fb = (AT)0;
+                T fb = (T)0;   // this level's stiffness terms, added to the accumulator in AT
                 auto face = [&](T uj, T bj) {
-                    const T sb = b0 + bj;
+                    // with t = b_j / (b_0 + b_j): h = 2 b_0 t, dh/db_0 = 2 t^2
+                    const T t = bj * recip(b0 + bj);
                     const T d = uj - u0;
-                    lap += (T)2 * b0 * bj / sb * d;
-                    if (use_accb) {
-                        const AT w = (AT)2 * (AT)bj * (AT)bj / ((AT)sb * (AT)sb);
-                        fb += w * (AT)d * (AT)d;
-                    }
+                    lap += (b0 * (t + t)) * d;
+                    if (use_accb) fb += ((t + t) * t) * (d * d);
                 };
                 face(el<T, VZ>(qu[0], i), el<T, VZ>(qb[0], i));
                 face(el<T, VZ>(qu[2], i), el<T, VZ>(qb[2], i));
@@ -206,7 +208,7 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
                 lap *= inv_dx2;
                 if (pe.has) lap += point_force(pe, a, est, lane0 + i, 0);
                 const T cui = el<T, VZ>(cu, i);
-                const T coef = dt2 / el<T, VZ>(cm, i);
+                const T coef = dt2 * recip(el<T, VZ>(cm, i));
                 const T uni = (u0 + u0) - cui + coef * lap;
                 set_el<T, VZ>(un, i, uni);
                 if (a.sample && pe.has) sample_receivers(pe, a, est, lane0 + i, 0, uni);
@@ -219,7 +221,7 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
                 }
                 if (use_accb) {
                     const AT bi = el<AT, VZ>(cab, i);
-                    set_el<AT, VZ>(abn, i, a.acc_face > 0 ? bi + fb : bi - fb);
+                    set_el<AT, VZ>(abn, i, a.acc_face > 0 ? bi + (AT)fb : bi - (AT)fb);
                 }
             }
             __builtin_nontemporal_store(un, (vec*)(unew + xo + roff + z));

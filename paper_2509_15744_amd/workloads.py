@@ -238,6 +238,39 @@ def layered_3d(n: int = 1024, nt: int = 3000, order: int = 8, dtype: str = "f32"
                    meta={"courant": courant, "f_peak": f_peak, "seed": seed})
 
 
+def layered_material_3d(n: int = 1024, nt: int = 3000, seed: int = 5, rec_every: int = 8,
+                        bound_frac: float = 0.9, device=None) -> dict:
+    """Variable-material twin of ``layered_3d`` for the second-order flux-form scheme
+    m u_tt - div(b grad u) = f: mass m = 1/c^2 of the perturbed layered medium,
+    stiffness b = a second layered profile (8 layers, values in [0.5, 1.5]) times the
+    same 5% smoothed perturbation (b / b_layers = c / c_layers); the reference medium of
+    the observed data is m_ref = 1/c_ref^2, b_ref = 1.  dt is ``bound_frac`` of the
+    stability bound dt sqrt(3 max b / min m) <= dx (dx = 1).  Source at the top-face
+    centre, receiver plane on x0 = 0 every ``rec_every`` cells, Ricker at 20 cells per
+    wavelength of the slowest speed sqrt(min b / max m).  With ``device`` the fields are
+    generated there (torch tensors, float32)."""
+    import torch
+    shape = (n, n, n)
+    c, c_ref = _layered_perturbed_torch(shape, seed, device)
+    prof = layered_speed((n, 1), 8, 0.5, 1.5, seed + 7)[:, 0]
+    b_lay = torch.as_tensor(prof, device=device, dtype=torch.float32).view(n, 1, 1)
+    m = (1.0 / (c * c)).contiguous()
+    b = (b_lay * (c / c_ref)).contiguous()
+    m_ref = (1.0 / (c_ref * c_ref)).contiguous()
+    b_ref = torch.ones_like(m_ref)
+    bmax = max(float(b.max()), 1.0)
+    mmin = min(float(m.min()), float(m_ref.min()))
+    dt = bound_frac / math.sqrt(3.0 * bmax / mmin)
+    slow = math.sqrt(min(float(b.min()), 1.0) / max(float(m.max()), float(m_ref.max())))
+    src = flat(shape, [[0, n // 2, n // 2]])
+    h = rec_every // 2
+    rec = flat(shape, [[0, rec_every * a + h, rec_every * q + h]
+                       for a in range(n // rec_every) for q in range(n // rec_every)])
+    wavelet = ricker(nt, dt, slow / 20.0).reshape(nt, 1)
+    return dict(shape=shape, dx=1.0, dt=dt, nt=nt, m=m, b=b, m_ref=m_ref, b_ref=b_ref, src=src,
+                rec=rec, wavelet=wavelet)
+
+
 def _layered_perturbed_torch(shape, seed, device, n_layers=8, c_lo=1.5, c_hi=4.5,
                              sigma=8.0, amp=0.05):
     """Device-side twin of ``layered_perturbed`` for grids too large for host smoothing:
