@@ -1,6 +1,7 @@
 """Parity at the full benchmark sizes, in the launch configuration the benchmark uses
-(library-chosen shape, variant 0): 1024^3 layered (order 8, f32, 16384 receivers) and
-2048^2 layered (order 8, f32, 512 receivers).
+(library-chosen shape): 1024^3 layered (order 8, f32, 16384 receivers), 2048^2
+layered (order 8, f32, 512 receivers) and the 1024^3 layered material of the
+variable-material scheme (order 2, f32, 16384 receivers, both sensitivities).
 
 The oracle cannot run these grids for thousands of steps, so:
 
@@ -33,36 +34,31 @@ def fdw():
     return fdwave
 
 
-def _window_check(fdw, p, c_dev, centre, half, k):
-    """Full-size run of nt = NT steps vs the oracle on the window around ``centre``."""
-    shape = p.shape
+def _window_check(shape, src, rec, wavelet, dt, r, centre, half, run_gpu, run_oracle):
+    """Full-size run of nt = NT steps (``run_gpu(w, obs)`` -> (gradient fields, J, traces),
+    device tensors) vs the oracle on the window around ``centre`` (``run_oracle(win,
+    src_w, w_w, rec_w, obs_w)`` -> (gradient fields, J, traces) on the window)."""
     nd = len(shape)
     rng = np.random.default_rng(7)
-    obs = 1e-3 * rng.standard_normal((NT, len(p.rec)))
-    w = p.wavelet[:NT]
-    f32 = torch.float32
-    tr = torch.empty((NT, len(p.rec)), dtype=f32, device="cuda")
-    g, J = fdw.fd_adjoint_sensitivity(c_dev, p.dx, p.order, p.src, to_dev(w, f32), p.rec, p.dt, NT,
-                                      to_dev(obs, f32), k, traces=tr)
+    obs = 1e-3 * rng.standard_normal((NT, len(rec)))
+    w = wavelet[:NT]
+    grads, J, tr = run_gpu(w, obs)
     torch.cuda.synchronize()
-    r = p.order // 2
     reach = 2 * r * NT
     lo = [max(0, centre[a] - half) for a in range(nd)]
     hi = [min(shape[a], centre[a] + half + 1) for a in range(nd)]
     win = tuple(slice(lo[a], hi[a]) for a in range(nd))
-    cw = c_dev[win].double().cpu().numpy()
-    wshape = cw.shape
+    wshape = tuple(hi[a] - lo[a] for a in range(nd))
 
     def inside(cells):
         co = np.array(np.unravel_index(cells, shape)).T
         m = np.all([(co[:, a] >= lo[a]) & (co[:, a] < hi[a]) for a in range(nd)], axis=0)
         return m, co - np.array(lo)
 
-    ms, cs = inside(p.src)
-    mr, cr = inside(p.rec)
-    g_o, J_o, tr_o = oracle.superposition_gradient(
-        cw, p.dx, p.order, p.dt, NT, wl.flat(wshape, cs[ms]), w[:, ms], wl.flat(wshape, cr[mr]),
-        obs[:, mr], k)
+    ms, cs = inside(src)
+    mr, cr = inside(rec)
+    grads_o, J_o, tr_o = run_oracle(win, wl.flat(wshape, cs[ms]), w[:, ms], wl.flat(wshape, cr[mr]),
+                                    obs[:, mr])
     # cells whose domain of dependence stays inside the window
     core = []
     for a in range(nd):
@@ -70,36 +66,53 @@ def _window_check(fdw, p, c_dev, centre, half, k):
         a1 = hi[a] if hi[a] == shape[a] else hi[a] - reach
         core.append(slice(a0 - lo[a], a1 - lo[a]))
     core = tuple(core)
-    g_gpu = g[win].double().cpu().numpy()
-    e_g = rel(g_gpu[core], g_o[core])
+    errs = [rel(g[win].double().cpu().numpy()[core], go[core]) for g, go in zip(grads, grads_o)]
     # receivers in the core: traces
-    rec_core = mr & np.all([(np.array(np.unravel_index(p.rec, shape)).T[:, a] >= lo[a] + core[a].start)
-                            & (np.array(np.unravel_index(p.rec, shape)).T[:, a] < lo[a] + core[a].stop)
+    rx = np.array(np.unravel_index(rec, shape)).T
+    rec_core = mr & np.all([(rx[:, a] >= lo[a] + core[a].start) & (rx[:, a] < lo[a] + core[a].stop)
                             for a in range(nd)], axis=0)
     idx_in_win = np.cumsum(mr) - 1
     tr_gpu = tr.double().cpu().numpy()
     e_tr = rel(tr_gpu[:, rec_core], tr_o[:, idx_in_win[rec_core]])
     # far receivers: exact zeros
-    sx = np.array(np.unravel_index(p.src, shape)).T
-    rx = np.array(np.unravel_index(p.rec, shape)).T
+    sx = np.array(np.unravel_index(src, shape)).T
     dist = np.min(np.abs(rx[:, None, :] - sx[None, :, :]).max(axis=2), axis=1)
     far = dist > r * NT
-    J_far = 0.5 * p.dt * float(np.sum(obs[:, far] ** 2))
-    J_near = 0.5 * p.dt * float(np.sum((tr_o[:, idx_in_win[~far]] - obs[:, ~far]) ** 2))
-    say(f"  window {wshape}: grad core {e_g:.2e} ({int(np.prod([s.stop - s.start for s in core]))} cells), "
-        f"traces {e_tr:.2e} ({int(rec_core.sum())} receivers), far receivers {int(far.sum())}")
+    J_far = 0.5 * dt * float(np.sum(obs[:, far] ** 2))
+    J_near = 0.5 * dt * float(np.sum((tr_o[:, idx_in_win[~far]] - obs[:, ~far]) ** 2))
+    say(f"  window {wshape}: gradient core {', '.join(f'{e:.2e}' for e in errs)} "
+        f"({int(np.prod([s.stop - s.start for s in core]))} cells), traces {e_tr:.2e} "
+        f"({int(rec_core.sum())} receivers), far receivers {int(far.sum())}")
     assert np.all(~far <= mr), "every receiver near the source must lie in the window"
-    assert e_g < 1e-4 and e_tr < 1e-4
+    assert max(errs) < 1e-4 and e_tr < 1e-4
     assert np.all(tr_gpu[:, far] == 0.0)
     assert abs(J - (J_far + J_near)) < 1e-5 * J
-    return g
+    return grads
+
+
+def _constant_density(fdw, p, c_dev, centre, half, k):
+    f32 = torch.float32
+
+    def run_gpu(w, obs):
+        tr = torch.empty((NT, len(p.rec)), dtype=f32, device="cuda")
+        g, J = fdw.fd_adjoint_sensitivity(c_dev, p.dx, p.order, p.src, to_dev(w, f32), p.rec, p.dt, NT,
+                                          to_dev(obs, f32), k, traces=tr)
+        return (g,), J, tr
+
+    def run_oracle(win, src_w, w_w, rec_w, obs_w):
+        cw = c_dev[win].double().cpu().numpy()
+        g, J, tr = oracle.superposition_gradient(cw, p.dx, p.order, p.dt, NT, src_w, w_w, rec_w, obs_w, k)
+        return (g,), J, tr
+
+    return _window_check(p.shape, p.src, p.rec, p.wavelet, p.dt, p.order // 2, centre, half,
+                         run_gpu, run_oracle)[0]
 
 
 def test_fullsize_3d_sampled_parity(fdw):
     p = wl.layered_3d(n=1024, nt=NT, device="cuda")
     c = p.c.float().contiguous()
     say("1024^3 layered, nt", NT)
-    g = _window_check(fdw, p, c, (0, 512, 512), 64, k=0.5)
+    g = _constant_density(fdw, p, c, (0, 512, 512), 64, k=0.5)
     # far from every source and receiver the gradient is exactly zero
     assert torch.count_nonzero(g[600:]).item() == 0
 
@@ -108,7 +121,35 @@ def test_fullsize_2d_sampled_parity(fdw):
     p = wl.layered_2d(n=2048, nt=NT)
     c = torch.as_tensor(p.c, dtype=torch.float32, device="cuda")
     say("2048^2 layered, nt", NT)
-    _window_check(fdw, p, c, (0, 1024), 96, k=0.5)
+    _constant_density(fdw, p, c, (0, 1024), 96, k=0.5)
+
+
+def test_fullsize_vd_sampled_parity(fdw):
+    """The variable-material second-order scheme on the 1024^3 layered material of the
+    vd3d benchmark (f32, variant 2, library chunk): both sensitivities and the traces
+    on the window core against the oracle's vdoracle.c."""
+    q = wl.layered_material_3d(n=1024, nt=NT, device="cuda")
+    del q["m_ref"], q["b_ref"]
+    f32 = torch.float32
+    k = 0.5
+
+    def run_gpu(w, obs):
+        tr = torch.empty((NT, len(q["rec"])), dtype=f32, device="cuda")
+        gm, gb, J = fdw.fd_vd_adjoint_sensitivity(q["m"], q["b"], q["dx"], q["src"], to_dev(w, f32), q["rec"],
+                                                  q["dt"], NT, to_dev(obs, f32), k, traces=tr, variant=2)
+        return (gm, gb), J, tr
+
+    def run_oracle(win, src_w, w_w, rec_w, obs_w):
+        mw = q["m"][win].double().cpu().numpy()
+        bw = q["b"][win].double().cpu().numpy()
+        gm, gb, J, tr = oracle.vd_superposition_gradient(mw, bw, q["dx"], q["dt"], NT, src_w, w_w, rec_w,
+                                                         obs_w, k)
+        return (gm, gb), J, tr
+
+    say("1024^3 variable material, nt", NT)
+    gm, gb = _window_check(q["shape"], q["src"], q["rec"], q["wavelet"], q["dt"], 1, (0, 512, 512), 48,
+                           run_gpu, run_oracle)
+    assert torch.count_nonzero(gm[200:]).item() == 0 and torch.count_nonzero(gb[200:]).item() == 0
 
 
 @pytest.mark.parametrize("shape,modes,nsteps", [((1024, 1024, 1024), (3, 5, 2), 150),
