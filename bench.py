@@ -240,7 +240,8 @@ def run_single(args, np, torch, fdw, wl):
     log("workload:", desc, f"dt={p.dt:.5g}")
     w = torch.as_tensor(wav, dtype=torch.float32, device="cuda")
     if args.variant:
-        best = {"variant": args.variant, "chunk": args.chunk, "max_group": 0}
+        best = {"variant": args.variant, "chunk": args.chunk, "max_group": 0,
+                "variant_plain": args.variant_plain, "chunk_plain": args.chunk_plain}
         log("launch shape (given):", best)
     else:
         best, best_ms = fdw.fd_autotune(p.shape, p.dx, p.order, torch.float32, nshot=nshot, steps=4,
@@ -255,7 +256,8 @@ def run_single(args, np, torch, fdw, wl):
     holder, timings = {}, []
     acq = fdw.Acquisition(src, w, rec, *(shots if shots else (None, None, 0)))
     opts = dict(acc_dtype=args.acc, variant=best["variant"], chunk=best["chunk"],
-                max_group=best["max_group"])
+                max_group=best["max_group"], variant_plain=best["variant_plain"],
+                chunk_plain=best["chunk_plain"])
 
     def exact_step(record):
         t = fdw.fd_timing()
@@ -486,6 +488,9 @@ def main():
     ap.add_argument("--acc", default="f64", choices=["f64", "f32"])
     ap.add_argument("--variant", type=int, default=0, help="force a tile variant (default: autotuned)")
     ap.add_argument("--chunk", type=int, default=0, help="with --variant: planes per block (0: library)")
+    ap.add_argument("--variant-plain", type=int, default=0,
+                    help="with --variant: tile variant of the launches without accumulator (0: same)")
+    ap.add_argument("--chunk-plain", type=int, default=0, help="with --variant-plain: planes per block")
     ap.add_argument("--graph", type=int, default=1, help="problems2d: replay sweeps as hipGraphs")
     ap.add_argument("--persistent", type=int, default=0, help="problems2d: one cooperative launch per sweep")
     ap.add_argument("--beta", type=float, default=0.005,

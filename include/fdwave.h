@@ -117,6 +117,11 @@ typedef struct fd_opts {
     int32_t barrier_timeout_us; /* persistent launches: longest wait at one grid barrier
                            before the launch gives up and the call returns FD_E_DEVICE
                            (0: 2 s) */
+    int32_t variant_plain; /* tile variant of the step launches that do not touch the
+                           accumulator (about half of each sweep); 0: the same as `variant`
+                           (or the remembered choice when `variant` is 0).  Used only where
+                           it groups the shots as `variant` does; results are identical */
+    int32_t chunk_plain;   /* planes per block for those launches; 0: library choice */
 } fd_opts;
 
 /* Caller-owned device state that carries one gradient from its forward sweep
@@ -161,12 +166,13 @@ int32_t fd_variant_count(int32_t ndim);
 int fd_variant_info(int32_t ndim, int32_t variant, int32_t* tile_z, int32_t* tile_y,
                     int32_t* threads, int32_t* cells_per_lane, int32_t* max_fields);
 
-/* Autotuner: times `steps` pairs of fused steps (one without accumulator access, one
- * adding two kernel terms, the mix the sweeps run) for every tile variant that
- * fits the grid, several axis-0 chunk lengths and, for nshot > 1, the shot-group sizes,
- * on scratch fields of this grid allocated and freed by the call; writes the fastest
- * (time per shot-cell update) into *best (variant, chunk, max_group; other fields copied
- * from opts) and remembers it for this process under the key (GPU architecture, HIP
+/* Autotuner: times `steps` fused steps of each kind the sweeps alternate (adding two
+ * kernel terms; touching no accumulator) for every tile variant that fits the grid,
+ * several axis-0 chunk lengths and, for nshot > 1, the shot-group sizes, on scratch
+ * fields of this grid allocated and freed by the call; writes the fastest shape of each
+ * kind for the best shot-group size (time per shot-cell update of the pair) into *best
+ * (variant, chunk, max_group, variant_plain, chunk_plain; other fields copied from
+ * opts) and remembers it for this process under the key (GPU architecture, HIP
  * runtime version, ndim, order, dtype, accumulator dtype, shape, shot count).  Calls
  * whose fd_opts.variant is 0 use a remembered entry of their key (their chunk and
  * max_group too, unless set).  If the environment variable FDWAVE_TUNE_CACHE names a

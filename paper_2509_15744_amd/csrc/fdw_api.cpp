@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -78,6 +79,8 @@ struct Geo {
     int persistent = 0;
     int barrier_timeout_us = 0;
     bool auto_variant = true;   // the caller left the variant to the library
+    int variant_plain = 0;      // launches without accumulator access: tile variant (0: variant)
+    int chunk_plain = 0;        //   and planes per block (0: library choice)
     int n0, n1, n2;      // internal extents (2D: n1 = 1)
     int64_t ncell;
     double dx, inv_vol;
@@ -123,6 +126,11 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
         G.persistent = o->persistent;
         if (o->barrier_timeout_us < 0) return fail(FD_E_ARG, "barrier_timeout_us is negative");
         G.barrier_timeout_us = o->barrier_timeout_us;
+        if (o->variant_plain < 0 || o->variant_plain > fdw::variant_count(g->ndim))
+            return fail(FD_E_ARG, "variant_plain out of range");
+        if (o->chunk_plain < 0) return fail(FD_E_ARG, "chunk_plain is negative");
+        G.variant_plain = o->variant_plain;
+        G.chunk_plain = o->chunk_plain;
     }
     if (G.dtype == FD_F64) G.acc_dtype = FD_F64;
     G.n0 = (int)n[0];
@@ -250,7 +258,11 @@ struct Group {
 // receiver cells (terminal hand-over).
 struct Plan {
     fdw::Variant v;
+    int variant = 1;
     int nty = 0, ntz = 0, nch = 0, chunk = 0, nblk = 0;
+    // the launch shape of the launches that do not touch the accumulator, when it
+    // differs and groups the shots the same way (else null: this plan serves both)
+    std::shared_ptr<Plan> plain;
     std::vector<Group> groups;
     int nuniq = 0;
     int64_t* d_ucell = nullptr;
@@ -275,6 +287,7 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
         return fail(FD_E_ARG, "variant " + std::to_string(G.variant) +
                                   " needs the contiguous extent to be a multiple of " + std::to_string(v.vz));
     P->v = v;
+    P->variant = G.variant;
     P->ntz = (G.n2 + v.tz - 1) / v.tz;
     P->nty = (G.n1 + v.ty - 1) / v.ty;
     const int64_t tiles = (int64_t)P->ntz * P->nty;
@@ -413,6 +426,29 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
     }
     // the host vectors die with this frame: finish the copies first
     HIPCHK(hipStreamSynchronize(s));
+
+    // second launch shape for the launches without accumulator access
+    if (!pairs && G.variant_plain > 0 &&
+        (G.variant_plain != G.variant || (G.chunk_plain > 0 && G.chunk_plain != P->chunk))) {
+        const fdw::Variant w = fdw::variant_shape(G.ndim, G.variant_plain);
+        int gsz = 1;
+        for (const Group& gr : P->groups) gsz = std::max(gsz, gr.size);
+        if (w.tz != 0 && G.n2 % w.vz == 0 && w.max_shots >= gsz) {
+            Geo G2 = G;
+            G2.variant = G.variant_plain;
+            G2.chunk = G.chunk_plain;
+            G2.auto_variant = false;
+            G2.variant_plain = 0;
+            G2.max_group = gsz;
+            auto P2 = std::make_shared<Plan>();
+            int rc2 = make_plan(G2, acq, false, s, sc, P2.get());
+            if (rc2) return rc2;
+            bool same = P2->groups.size() == P->groups.size();
+            for (size_t i = 0; same && i < P->groups.size(); ++i)
+                same = P2->groups[i].g0 == P->groups[i].g0 && P2->groups[i].size == P->groups[i].size;
+            if (same) P->plain = P2;
+        }
+    }
     return FD_OK;
 }
 
@@ -439,16 +475,30 @@ struct VdFields {
     void* acc_b = nullptr;
 };
 
-int step(const Geo& G, const Plan& P, const Group& gr, fdw::StepArgs a, hipStream_t s)
+// One step launch of group `gr` with the launch shape of plan P.
+int step_group(const Geo& G, const Plan& P, const Group& gr, fdw::StepArgs a, hipStream_t s)
 {
     a.blk_off = gr.d_off;
     a.grp = gr.d_grp;
     a.ev = gr.d_ev;
+    a.nty = P.nty;
+    a.ntz = P.ntz;
+    a.chunk_len = P.chunk;
+    a.nblk = P.nblk;
     if (a.stiff)
-        HIPCHK(fdw::launch_vd_step(G.ndim, G.dtype, G.acc_dtype, G.variant, P.nblk, a, s));
+        HIPCHK(fdw::launch_vd_step(G.ndim, G.dtype, G.acc_dtype, P.variant, P.nblk, a, s));
     else
-        HIPCHK(fdw::launch_step(G.ndim, G.r, G.dtype, G.acc_dtype, G.variant, gr.size, P.nblk, a, s));
+        HIPCHK(fdw::launch_step(G.ndim, G.r, G.dtype, G.acc_dtype, P.variant, gr.size, P.nblk, a, s));
     return FD_OK;
+}
+
+// One step launch of shot group gi: launches that touch no accumulator take the plan's
+// second launch shape when it has one.
+int step(const Geo& G, const Plan& P, int gi, const fdw::StepArgs& a, hipStream_t s)
+{
+    const bool plain = a.acc_sign == 0 && a.acc_face == 0 && P.plain;
+    const Plan& Q = plain ? *P.plain : P;
+    return step_group(G, Q, Q.groups[gi], a, s);
 }
 
 // Kernel terms of launch l in a run of `count` consecutive accumulating launches of one
@@ -545,7 +595,8 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
     const size_t es = dsize(G.dtype);
     SweepTimer tm(G.timing != nullptr, s);
     tm.start();
-    for (const Group& gr : P.groups) {
+    for (int gi = 0; gi < (int)P.groups.size(); ++gi) {
+        const Group& gr = P.groups[gi];
         char* prev = (char*)ua + (size_t)gr.g0 * G.ncell * es;   // level n-1
         char* cur = (char*)ub + (size_t)gr.g0 * G.ncell * es;    // level n
         for (int n = 0; n < nt; ++n) {
@@ -555,7 +606,7 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
             set_acc(a, acc ? acc_terms(n, nt - 1) : 0, 1);
             a.row_src = n;
             a.row_rec = n;
-            int rc = step(G, P, gr, a, s);
+            int rc = step(G, P, gi, a, s);
             if (rc) return rc;
             std::swap(prev, cur);
         }
@@ -613,7 +664,7 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
             a.row_src = j;
             a.row_rec = j - 1;
             set_acc(a, acc_terms(nt - 1 - j, nt - 1), -1);   // intervals nt-2..0
-            int rc = step(G, P, gr, a, s);
+            int rc = step(G, P, (int)gi, a, s);
             if (rc) return rc;
             std::swap(vj, vn);
         }
@@ -738,6 +789,7 @@ int vd_setup(const fd_grid* grid, const fd_opts* opts, Geo* G)
         return fail(FD_E_ARG, "the variable-material scheme runs tile variants 1 and 2");
     }
     G->max_group = 1;
+    G->variant_plain = 0;   // one launch shape for every launch
     return FD_OK;
 }
 
@@ -907,7 +959,8 @@ int exact_gradient(const fd_grid* grid, const void* c, const fd_acq* acq, double
     a.rec_scale = rec_scale;
     SweepTimer tm(G.timing != nullptr && nt > 1, s);
     tm.start();
-    for (const Group& gr : Pb.groups) {
+    for (int gi = 0; gi < (int)Pb.groups.size(); ++gi) {
+        const Group& gr = Pb.groups[gi];
         char* xj = (char*)up + (size_t)gr.g0 * G.ncell * es;   // level j
         char* xn = (char*)ul + (size_t)gr.g0 * G.ncell * es;   // level j+1, overwritten by j-1
         for (int j = nt - 1; j >= 1; --j) {
@@ -916,7 +969,7 @@ int exact_gradient(const fd_grid* grid, const void* c, const fd_acq* acq, double
             a.row_src = j;
             a.row_rec = j - 1;
             set_acc(a, acc_terms(nt - 1 - j, nt - 1), 1);   // intervals nt-2..0
-            if ((rc = step(Gb, Pb, gr, a, s))) return rc;
+            if ((rc = step(Gb, Pb, gi, a, s))) return rc;
             std::swap(xj, xn);
         }
     }
@@ -936,6 +989,7 @@ int exact_gradient(const fd_grid* grid, const void* c, const fd_acq* acq, double
 
 struct Tuned {
     int variant = 1, chunk = 0, group = 1;
+    int variant_plain = 0, chunk_plain = 0;   // launches without accumulator access (0: same)
     double ms = 0.0;
 };
 
@@ -965,8 +1019,9 @@ std::string tune_key(const Geo& G, int nshot)
 
 const char* tune_file() { return std::getenv("FDWAVE_TUNE_CACHE"); }
 
-// Reads "key" and the integers after "variant", "chunk", "max_group" and "ms" from one
-// JSON line written by tune_save (no general JSON parser is needed for that format).
+// Reads "key" and the numbers after "variant", "chunk", "max_group", "variant_plain",
+// "chunk_plain" and "ms" from one JSON line written by tune_save (no general JSON parser
+// is needed for that format).
 bool parse_line(const std::string& ln, std::string* key, Tuned* t)
 {
     auto str_after = [&](const char* name, std::string* out) {
@@ -986,13 +1041,17 @@ bool parse_line(const std::string& ln, std::string* key, Tuned* t)
         *out = std::atof(ln.c_str() + p + pat.size());
         return true;
     };
-    double v, c, g, ms;
+    double v, c, g, ms, vp = 0.0, cp = 0.0;
     if (!str_after("key", key) || !num_after("variant", &v) || !num_after("chunk", &c) ||
         !num_after("max_group", &g) || !num_after("ms", &ms))
         return false;
+    (void)num_after("variant_plain", &vp);   // absent in entries with one launch shape
+    (void)num_after("chunk_plain", &cp);
     t->variant = (int)v;
     t->chunk = (int)c;
     t->group = (int)g;
+    t->variant_plain = (int)vp;
+    t->chunk_plain = (int)cp;
     t->ms = ms;
     return true;
 }
@@ -1021,8 +1080,10 @@ void tune_save_locked(const std::string& key, const Tuned& t)
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "{\"key\": \"%s\", \"variant\": %d, \"chunk\": %d, \"max_group\": %d, \"ms\": %.6f}\n",
-                 key.c_str(), t.variant, t.chunk, t.group, t.ms);
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"variant\": %d, \"chunk\": %d, \"max_group\": %d, "
+                 "\"variant_plain\": %d, \"chunk_plain\": %d, \"ms\": %.6f}\n",
+                 key.c_str(), t.variant, t.chunk, t.group, t.variant_plain, t.chunk_plain, t.ms);
     std::fclose(f);
 }
 
@@ -1038,6 +1099,10 @@ bool apply_tuned(Geo& G, int nshot)
     G.variant = it->second.variant;
     if (G.chunk == 0) G.chunk = it->second.chunk;
     if (G.max_group == 0) G.max_group = it->second.group;
+    if (G.variant_plain == 0) {
+        G.variant_plain = it->second.variant_plain;
+        if (G.chunk_plain == 0) G.chunk_plain = it->second.chunk_plain;
+    }
     return true;
 }
 
@@ -1074,8 +1139,29 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evs{e0, e1};
-    Tuned bestv;
-    double best_per_shot = 1e300;
+    // per shot-group size: the fastest shape of the launches that add kernel terms and,
+    // separately, of the launches that touch no accumulator (the sweeps alternate them)
+    struct Best { double ms = 1e300; int variant = 0, chunk = 0; };
+    std::map<int, Best> best_acc, best_plain;
+    auto time_launches = [&](const Geo& T, const Plan& P, const Group& gr, fdw::StepArgs a, int terms,
+                             double* ms_out) -> int {
+        void *prev = ua, *cur = ub;
+        for (int n = 0; n < steps + 1; ++n) {   // one untimed warm-up launch
+            if (n == 1) HIPCHK(hipEventRecord(e0, s));
+            a.ucur = cur;
+            a.unew = prev;
+            set_acc(a, terms, 1);
+            int rc2 = step_group(T, P, gr, a, s);
+            if (rc2) return rc2;
+            std::swap(prev, cur);
+        }
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        *ms_out = ms / steps;
+        return FD_OK;
+    };
     for (int variant = 1; variant <= fdw::variant_count(G.ndim); ++variant) {
         const fdw::Variant v = fdw::variant_shape(G.ndim, variant);
         if (G.n2 % v.vz != 0) continue;
@@ -1091,6 +1177,7 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
                 T.auto_variant = false;
                 T.chunk = chunk;
                 T.max_group = group;
+                T.variant_plain = 0;
                 T.timing = nullptr;
                 Scratch sc(s);
                 Plan P;
@@ -1099,30 +1186,32 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
                 gr.size = group;
                 fdw::StepArgs a = base_args(T, P, c, 0.1);
                 a.acc = acc;
-                // the sweeps' mix: launches alternate between no accumulator access and
-                // two kernel terms; `steps` such pairs are timed after one warm-up launch
-                void *prev = ua, *cur = ub;
-                for (int n = 0; n < 2 * steps + 1; ++n) {
-                    if (n == 1) HIPCHK(hipEventRecord(e0, s));
-                    a.ucur = cur;
-                    a.unew = prev;
-                    set_acc(a, (n & 1) ? 3 : 0, 1);
-                    if ((rc = step(T, P, gr, a, s))) return rc;
-                    std::swap(prev, cur);
-                }
-                HIPCHK(hipEventRecord(e1, s));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                const double per_step = ms / (2 * steps);
-                if (per_step / group < best_per_shot) {
-                    best_per_shot = per_step / group;
-                    bestv.variant = variant;
-                    bestv.chunk = chunk == 0 ? P.chunk : chunk;
-                    bestv.group = group;
-                    bestv.ms = per_step;
-                }
+                double ms_acc = 0.0, ms_plain = 0.0;
+                if ((rc = time_launches(T, P, gr, a, 3, &ms_acc))) return rc;
+                if ((rc = time_launches(T, P, gr, a, 0, &ms_plain))) return rc;
+                const int resolved = chunk == 0 ? P.chunk : chunk;
+                Best& ba = best_acc[group];
+                if (ms_acc < ba.ms) ba = Best{ms_acc, variant, resolved};
+                Best& bp = best_plain[group];
+                if (ms_plain < bp.ms) bp = Best{ms_plain, variant, resolved};
             }
+        }
+    }
+    Tuned bestv;
+    double best_per_shot = 1e300;
+    for (int group : groups) {
+        if (!best_acc.count(group) || !best_plain.count(group)) continue;
+        const Best& ba = best_acc[group];
+        const Best& bp = best_plain[group];
+        const double per_pair = ba.ms + bp.ms;
+        if (per_pair / group < best_per_shot) {
+            best_per_shot = per_pair / group;
+            bestv.variant = ba.variant;
+            bestv.chunk = ba.chunk;
+            bestv.group = group;
+            bestv.variant_plain = bp.variant;
+            bestv.chunk_plain = bp.chunk;
+            bestv.ms = per_pair / 2;
         }
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -1136,6 +1225,8 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
     best->variant = bestv.variant;
     best->chunk = bestv.chunk;
     best->max_group = bestv.group;
+    best->variant_plain = bestv.variant_plain;
+    best->chunk_plain = bestv.chunk_plain;
     if (best_ms) *best_ms = bestv.ms;
     return FD_OK;
 }
@@ -1567,7 +1658,7 @@ int fd_propagate(const fd_grid* grid, const void* coef, void* u_prev, void* u_cu
     for (int n = 0; n < nsteps; ++n) {
         a.ucur = cur;
         a.unew = prev;
-        if ((rc = step(G, P, P.groups[0], a, s))) return rc;
+        if ((rc = step(G, P, 0, a, s))) return rc;
         std::swap(prev, cur);
     }
     if (nsteps & 1) {   // newest level sits in u_prev: swap the two buffers' contents

@@ -59,7 +59,8 @@ class fd_opts(ctypes.Structure):
     _fields_ = [("acc_dtype", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("timing", ctypes.POINTER(fd_timing)), ("chunk", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32),
+                ("variant_plain", ctypes.c_int32), ("chunk_plain", ctypes.c_int32)]
 
 
 class fd_state(ctypes.Structure):
@@ -182,8 +183,10 @@ class Acquisition:
 
 
 def make_opts(acc_dtype=None, variant=0, timing=None, chunk=0, max_group=0, graph=False,
-              persistent=False, barrier_timeout_us=0) -> fd_opts:
+              persistent=False, barrier_timeout_us=0, variant_plain=0, chunk_plain=0) -> fd_opts:
     o = fd_opts()
+    o.variant_plain = int(variant_plain)
+    o.chunk_plain = int(chunk_plain)
     o.persistent = int(bool(persistent))
     o.barrier_timeout_us = int(barrier_timeout_us)
     if acc_dtype is None or acc_dtype in ("f64", torch.float64, FD_F64):
@@ -394,14 +397,16 @@ def fd_adjoint_sensitivity_batched(problems, **opts):
 
 def fd_autotune(shape, dx, order, dtype=torch.float32, nshot=1, steps=3, **opts):
     """Time the launch shapes for this grid class; the library remembers the fastest for
-    later calls with variant 0.  Returns ({variant, chunk, max_group}, ms per step)."""
+    later calls with variant 0.  Returns ({variant, chunk, max_group, variant_plain,
+    chunk_plain}, ms per step)."""
     g = make_grid(shape, dx, order, FD_F64 if dtype == torch.float64 else FD_F32)
     o = make_opts(**opts)
     best = fd_opts()
     ms = ctypes.c_double()
     _raise(_lib.fd_autotune(ctypes.byref(g), int(nshot), ctypes.byref(o), int(steps),
                             ctypes.byref(best), ctypes.byref(ms), _stream()))
-    return {"variant": best.variant, "chunk": best.chunk, "max_group": best.max_group}, ms.value
+    return {"variant": best.variant, "chunk": best.chunk, "max_group": best.max_group,
+            "variant_plain": best.variant_plain, "chunk_plain": best.chunk_plain}, ms.value
 
 
 def fd_propagate(coef, u_prev, u_cur, nsteps, dx, order, **opts):

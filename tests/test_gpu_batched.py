@@ -144,8 +144,12 @@ def test_autotune_picks_a_valid_shape_and_persists(fdw, tmp_path, monkeypatch):
     info = fdw.fd_variant_info(3, best["variant"])
     assert shape[-1] % info["cells_per_lane"] == 0
     assert best["max_group"] in (1, 2, 4) and best["chunk"] >= 1 and ms > 0
+    plain = fdw.fd_variant_info(3, best["variant_plain"])   # the shape of launches without accumulator
+    assert shape[-1] % plain["cells_per_lane"] == 0 and plain["max_fields"] >= best["max_group"]
+    assert best["chunk_plain"] >= 1
     lines = cache.read_text().strip().splitlines()
     assert lines and '"variant": %d' % best["variant"] in lines[-1]
+    assert '"variant_plain": %d' % best["variant_plain"] in lines[-1]
     P = shot_problem(shape, 4, 8, 20, "f32", seed=5)
     g_o, J_o, _ = _oracle_sum(P, 0.05)
     f32 = torch.float32

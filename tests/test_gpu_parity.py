@@ -217,6 +217,23 @@ def test_variants_are_bitwise_identical(fdw):
             assert out[1] == ref[1]
 
 
+def test_second_launch_shape_is_bitwise_identical(fdw):
+    """Launches that touch no accumulator may run another tile shape (variant_plain,
+    chunk_plain): the per-cell arithmetic is the same, so the gradient, J and traces are
+    bitwise those of a single launch shape."""
+    p = wl.small_random((33, 20, 128), order=8, nt=30, dtype="f32", seed=17)
+    case = OracleCase(p, k=0.05, exact=False)
+    say("second launch shape")
+    g1, J1, t1 = run_sens(fdw, p, case, variant=2)
+    for vp, cp in ((7, 0), (3, 8), (6, 16), (1, 33)):
+        dt_ = torch_dtype(p.dtype)
+        tr = torch.empty((p.nt, len(p.rec)), dtype=dt_, device="cuda")
+        g2, J2 = fdw.fd_adjoint_sensitivity(to_dev(p.c, dt_), p.dx, p.order, p.src, to_dev(p.wavelet, dt_), p.rec,
+                                            p.dt, p.nt, to_dev(case.obs, dt_), case.k, traces=tr, variant=2,
+                                            variant_plain=vp, chunk_plain=cp)
+        assert J2 == J1 and np.array_equal(g2.cpu().numpy(), g1) and np.array_equal(tr.cpu().numpy(), t1)
+
+
 def test_variant_needing_wider_rows_is_rejected(fdw):
     p = wl.small_random((10, 10, 70), order=4, nt=5, dtype="f32", seed=1)
     bad = [v for v in range(1, fdw.fd_variant_count(3) + 1)
