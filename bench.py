@@ -351,7 +351,7 @@ def run_vd(args, np, torch, fdw, wl):
             f"{len(q['rec'])} receivers each")
     log("workload:", desc, f"dt={q['dt']:.5g}")
     w = torch.as_tensor(q["wavelet"], dtype=torch.float32, device="cuda")
-    variant = args.variant or 2
+    variant = args.variant or 1
     opts = dict(acc_dtype=args.acc, variant=variant, chunk=args.chunk)
     obs = fdw.fd_vd_forward(q["m_ref"], q["b_ref"], q["dx"], q["src"], w, q["rec"], q["dt"], nt, **opts)
     tr = fdw.fd_vd_forward(q["m"], q["b"], q["dx"], q["src"], w, q["rec"], q["dt"], nt, **opts)

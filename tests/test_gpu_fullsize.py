@@ -126,7 +126,7 @@ def test_fullsize_2d_sampled_parity(fdw):
 
 def test_fullsize_vd_sampled_parity(fdw):
     """The variable-material second-order scheme on the 1024^3 layered material of the
-    vd3d benchmark (f32, variant 2, library chunk): both sensitivities and the traces
+    vd3d benchmark (f32, the library's launch shape): both sensitivities and the traces
     on the window core against the oracle's vdoracle.c."""
     q = wl.layered_material_3d(n=1024, nt=NT, device="cuda")
     del q["m_ref"], q["b_ref"]
@@ -136,7 +136,7 @@ def test_fullsize_vd_sampled_parity(fdw):
     def run_gpu(w, obs):
         tr = torch.empty((NT, len(q["rec"])), dtype=f32, device="cuda")
         gm, gb, J = fdw.fd_vd_adjoint_sensitivity(q["m"], q["b"], q["dx"], q["src"], to_dev(w, f32), q["rec"],
-                                                  q["dt"], NT, to_dev(obs, f32), k, traces=tr, variant=2)
+                                                  q["dt"], NT, to_dev(obs, f32), k, traces=tr)
         return (gm, gb), J, tr
 
     def run_oracle(win, src_w, w_w, rec_w, obs_w):
