@@ -249,6 +249,20 @@ int fd_vd_adjoint_sensitivity(const fd_grid* grid, const void* m, const void* b,
                               void* grad_b, double* J_host, void* traces_or_null, const fd_opts* opts,
                               void* stream);
 
+/* The two halves of fd_vd_adjoint_sensitivity with caller-owned state (as for the
+ * constant-density split below): `state` holds the wavefields, the mass-term
+ * accumulator and the residuals, `acc_b` DEVICE [ncell] (accumulator dtype) the
+ * stiffness-term accumulator.  The forward half leaves u^{nt-1}, u^nt, both
+ * accumulators and the residuals; the backward half consumes them and writes
+ * grad_m = grad_scale dJ/dm and grad_b = grad_scale dJ/db.  Same grid, m, b, acq, dt, nt
+ * and opts in both calls. */
+int fd_vd_sens_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
+                       int32_t nt, const void* observed, const fd_state* state, void* acc_b,
+                       void* traces_or_null, double* J_host, const fd_opts* opts, void* stream);
+int fd_vd_sens_backward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
+                        int32_t nt, double k, const fd_state* state, void* acc_b, double grad_scale,
+                        void* grad_m, void* grad_b, const fd_opts* opts, void* stream);
+
 /* First half of fd_adjoint_sensitivity: the forward sweep with cost, adjoint force and
  * K(u,u) accumulation; leaves u^{nt-1}, u^nt, the accumulator and the residuals in
  * `state` (all four arrays overwritten).  J_host may be NULL. */

@@ -1,4 +1,4 @@
-"""The misfit as a differentiable function of the wave-speed field.
+"""The misfit as a differentiable function of the material.
 
 ``FdMisfit.apply(c, problem, k)`` returns J(c) (Eq. cost1) and records the forward
 sweep of Alg. 1 (``fd_sens_forward``: propagation, cost, adjoint force and K(u,u)
@@ -76,3 +76,43 @@ class FdMisfit(torch.autograd.Function):
 def misfit(c: torch.Tensor, prob: SensProblem, k: float) -> torch.Tensor:
     """J(c) as a differentiable scalar (float64 tensor on c's device)."""
     return FdMisfit.apply(c, prob, k)
+
+
+class FdVdMisfit(torch.autograd.Function):
+    """J(m, b) of the variable-material second-order scheme (the paper's Sec. 3.1
+    flux form, mass m and stiffness b) with Alg. 1 as its backward: the forward records
+    the forward sweep (``fd_vd_sens_forward``), the backward runs the superposed sweep
+    (``fd_vd_sens_backward``) and returns (dJ/dm, dJ/db) scaled by the incoming
+    gradient.  ``prob.order`` is ignored (the scheme is second order)."""
+
+    @staticmethod
+    def forward(ctx, m: torch.Tensor, b: torch.Tensor, prob: SensProblem, k: float):
+        m, b = m.contiguous(), b.contiguous()
+        nshot = prob.shots[2] if prob.shots is not None else 1
+        state = fdwave.VdSweepState(m, prob.nt, len(prob.rec), acc_dtype=prob.acc_dtype, nshot=nshot)
+        J = fdwave.fd_vd_sens_forward(m, b, prob.dx, prob.src, prob.wavelet, prob.rec, prob.dt, prob.nt,
+                                      prob.observed, state, shots=prob.shots, acc_dtype=prob.acc_dtype,
+                                      variant=prob.variant, chunk=prob.chunk)
+        ctx.save_for_backward(m, b)
+        ctx.state = state
+        ctx.prob = prob
+        ctx.k = float(k)
+        return torch.tensor(J, dtype=torch.float64, device=m.device)
+
+    @staticmethod
+    def backward(ctx, gJ: torch.Tensor):
+        m, b = ctx.saved_tensors
+        if ctx.state is None:
+            raise RuntimeError("FdVdMisfit: the backward sweep consumes the forward state; "
+                               "differentiate each apply() once")
+        prob = ctx.prob
+        gm, gb = fdwave.fd_vd_sens_backward(m, b, prob.dx, prob.src, prob.wavelet, prob.rec, prob.dt, prob.nt,
+                                            ctx.k, ctx.state, grad_scale=float(gJ.item()), shots=prob.shots,
+                                            acc_dtype=prob.acc_dtype, variant=prob.variant, chunk=prob.chunk)
+        ctx.state = None
+        return gm, gb, None, None
+
+
+def vd_misfit(m: torch.Tensor, b: torch.Tensor, prob: SensProblem, k: float) -> torch.Tensor:
+    """J(m, b) as a differentiable scalar (float64 tensor on m's device)."""
+    return FdVdMisfit.apply(m, b, prob, k)

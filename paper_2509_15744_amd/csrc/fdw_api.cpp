@@ -793,53 +793,112 @@ int vd_setup(const fd_grid* grid, const fd_opts* opts, Geo* G)
     return FD_OK;
 }
 
+// Validation shared by the two halves of the variable-material gradient.
+int vd_prepare(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt, int nt,
+               const fd_opts* opts, Geo* G)
+{
+    int rc = vd_setup(grid, opts, G);
+    if (rc) return rc;
+    if ((rc = check_time(dt, nt))) return rc;
+    if (!acq) return fail(FD_E_ARG, "acq is null");
+    if ((rc = check_acq(acq, *G, nt))) return rc;
+    const size_t es = dsize(G->dtype);
+    if ((rc = check_dev(m, G->ncell * es, "m"))) return rc;
+    if ((rc = check_dev(b, G->ncell * es, "b"))) return rc;
+    return FD_OK;
+}
+
+int check_vd_state(const fd_state* st, const void* acc_b, const Geo& G, int nt, const fd_acq* acq)
+{
+    int rc = check_state(st, G, nt, acq);
+    if (rc) return rc;
+    return check_dev(acc_b, G.ncell * dsize(G.acc_dtype), "acc_b");
+}
+
+// First half: forward sweep with cost, adjoint force and both kernel terms of u.
+int vd_sens_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt, int nt,
+                    const void* observed, const fd_state* st, void* acc_b, void* traces, double* J_host,
+                    const fd_opts* opts, hipStream_t s, bool own_state)
+{
+    Geo G;
+    int rc = vd_prepare(grid, m, b, acq, dt, nt, opts, &G);
+    if (rc) return rc;
+    if (!own_state && (rc = check_vd_state(st, acc_b, G, nt, acq))) return rc;
+    const size_t tb = (size_t)nt * acq->nrec * dsize(G.dtype);
+    if ((rc = check_dev(observed, tb, "observed"))) return rc;
+    if (traces && (rc = check_dev(traces, tb, "traces"))) return rc;
+    Scratch sc(s);
+    if ((rc = check_material(G, m, b, dt, s, sc))) return rc;
+    Plan P;
+    if ((rc = make_plan(G, acq, false, s, sc, &P))) return rc;
+    VdFields vd;
+    vd.stiff = b;
+    vd.acc_b = acc_b;
+    if ((rc = forward_sweep(G, P, m, acq, dt, nt, observed, st->u_a, st->u_b, st->acc, st->residual, traces,
+                            s, vd)))
+        return rc;
+    if (J_host) {
+        double ss = 0.0;
+        if ((rc = misfit_sum(G.dtype, st->residual, nullptr, nullptr, (int64_t)nt * acq->nrec, s, sc, &ss)))
+            return rc;
+        *J_host = 0.5 * dt * ss;
+        if (!std::isfinite(*J_host)) return fail(FD_E_NONFINITE, "misfit is not finite");
+    }
+    return FD_OK;
+}
+
+// Second half: superposed backward sweep from the state (consumed) and
+//   grad_m = s (K_m(u,u) - K_m(v,v)) / (2k),  grad_b = -s (dt^2/dx^2)(K_b(u,u) - K_b(v,v)) / (2k)
+// with s = grad_scale.
+int vd_sens_backward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt, int nt,
+                     double k, const fd_state* st, void* acc_b, double grad_scale, void* grad_m, void* grad_b,
+                     const fd_opts* opts, hipStream_t s, bool own_state)
+{
+    Geo G;
+    int rc = vd_prepare(grid, m, b, acq, dt, nt, opts, &G);
+    if (rc) return rc;
+    if (!(k != 0.0) || !std::isfinite(k)) return fail(FD_E_ARG, "k must be finite and non-zero");
+    if (!std::isfinite(grad_scale)) return fail(FD_E_ARG, "grad_scale must be finite");
+    if (!own_state && (rc = check_vd_state(st, acc_b, G, nt, acq))) return rc;
+    const size_t es = dsize(G.dtype);
+    if ((rc = check_dev(grad_m, G.ncell * es, "grad_m"))) return rc;
+    if ((rc = check_dev(grad_b, G.ncell * es, "grad_b"))) return rc;
+    Scratch sc(s);
+    Plan P;
+    if ((rc = make_plan(G, acq, true, s, sc, &P))) return rc;
+    VdFields vd;
+    vd.stiff = b;
+    vd.acc_b = acc_b;
+    if ((rc = backward_sweep(G, P, m, acq, dt, nt, k, st->u_a, st->u_b, st->acc, st->residual, s, vd)))
+        return rc;
+    HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, st->acc, grad_scale * 0.5 / k, grad_m, s));
+    HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, acc_b, -grad_scale * dt * dt / (G.dx * G.dx) * 0.5 / k,
+                             grad_b, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FD_OK;
+}
+
 int vd_gradient(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt, int nt,
                 const void* observed, double k, void* grad_m, void* grad_b, double* J_host, void* traces,
                 const fd_opts* opts, hipStream_t s)
 {
     Geo G;
-    int rc = vd_setup(grid, opts, &G);
+    int rc = vd_prepare(grid, m, b, acq, dt, nt, opts, &G);
     if (rc) return rc;
-    if ((rc = check_time(dt, nt))) return rc;
-    if (!acq) return fail(FD_E_ARG, "acq is null");
-    if ((rc = check_acq(acq, G, nt))) return rc;
     if (!(k != 0.0) || !std::isfinite(k)) return fail(FD_E_ARG, "k must be finite and non-zero");
-    const size_t es = dsize(G.dtype);
-    const size_t tb = (size_t)nt * acq->nrec * es;
-    if ((rc = check_dev(m, G.ncell * es, "m"))) return rc;
-    if ((rc = check_dev(b, G.ncell * es, "b"))) return rc;
-    if ((rc = check_dev(grad_m, G.ncell * es, "grad_m"))) return rc;
-    if ((rc = check_dev(grad_b, G.ncell * es, "grad_b"))) return rc;
-    if ((rc = check_dev(observed, tb, "observed"))) return rc;
-    if (traces && (rc = check_dev(traces, tb, "traces"))) return rc;
     Scratch sc(s);
-    if ((rc = check_material(G, m, b, dt, s, sc))) return rc;
+    const size_t es = dsize(G.dtype);
     const int ns = nshots(acq);
-    void *ua = nullptr, *ub = nullptr, *acc = nullptr, *accb = nullptr, *resid = nullptr;
-    HIPCHK(sc.get(&ua, G.ncell * es * ns));
-    HIPCHK(sc.get(&ub, G.ncell * es * ns));
-    HIPCHK(sc.get(&acc, G.ncell * dsize(G.acc_dtype)));
+    fd_state st;
+    void* accb = nullptr;
+    HIPCHK(sc.get(&st.u_a, G.ncell * es * ns));
+    HIPCHK(sc.get(&st.u_b, G.ncell * es * ns));
+    HIPCHK(sc.get(&st.acc, G.ncell * dsize(G.acc_dtype)));
     HIPCHK(sc.get(&accb, G.ncell * dsize(G.acc_dtype)));
-    HIPCHK(sc.get(&resid, std::max<size_t>(tb, es)));
-    Plan P;
-    if ((rc = make_plan(G, acq, true, s, sc, &P))) return rc;
-    VdFields vd;
-    vd.stiff = b;
-    vd.acc_b = accb;
-    if ((rc = forward_sweep(G, P, m, acq, dt, nt, observed, ua, ub, acc, resid, traces, s, vd))) return rc;
-    if (J_host) {
-        double ss = 0.0;
-        if ((rc = misfit_sum(G.dtype, resid, nullptr, nullptr, (int64_t)nt * acq->nrec, s, sc, &ss)))
-            return rc;
-        *J_host = 0.5 * dt * ss;
-        if (!std::isfinite(*J_host)) return fail(FD_E_NONFINITE, "misfit is not finite");
-    }
-    if ((rc = backward_sweep(G, P, m, acq, dt, nt, k, ua, ub, acc, resid, s, vd))) return rc;
-    // dJ/dm ~ (K_m(u,u) - K_m(v,v)) / (2k),  dJ/db ~ -(dt^2/dx^2)(K_b(u,u) - K_b(v,v)) / (2k)
-    HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, acc, 0.5 / k, grad_m, s));
-    HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, accb, -dt * dt / (G.dx * G.dx) * 0.5 / k, grad_b, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return FD_OK;
+    HIPCHK(sc.get(&st.residual, std::max<size_t>((size_t)nt * acq->nrec * es, es)));
+    if ((rc = vd_sens_forward(grid, m, b, acq, dt, nt, observed, &st, accb, traces, J_host, opts, s, true)))
+        return rc;
+    return vd_sens_backward(grid, m, b, acq, dt, nt, k, &st, accb, 1.0, grad_m, grad_b, opts, s, true);
 }
 
 int vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt, int nt,
@@ -1618,6 +1677,24 @@ int fd_vd_adjoint_sensitivity(const fd_grid* grid, const void* m, const void* b,
     g_err.clear();
     return vd_gradient(grid, m, b, acq, dt, nt, observed, k, grad_m, grad_b, J_host, traces_or_null, opts,
                        (hipStream_t)stream);
+}
+
+int fd_vd_sens_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
+                       int32_t nt, const void* observed, const fd_state* state, void* acc_b,
+                       void* traces_or_null, double* J_host, const fd_opts* opts, void* stream)
+{
+    g_err.clear();
+    return vd_sens_forward(grid, m, b, acq, dt, nt, observed, state, acc_b, traces_or_null, J_host, opts,
+                           (hipStream_t)stream, false);
+}
+
+int fd_vd_sens_backward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
+                        int32_t nt, double k, const fd_state* state, void* acc_b, double grad_scale,
+                        void* grad_m, void* grad_b, const fd_opts* opts, void* stream)
+{
+    g_err.clear();
+    return vd_sens_backward(grid, m, b, acq, dt, nt, k, state, acc_b, grad_scale, grad_m, grad_b, opts,
+                            (hipStream_t)stream, false);
 }
 
 int fd_autotune(const fd_grid* grid, int32_t nshot, const fd_opts* opts, int32_t steps,

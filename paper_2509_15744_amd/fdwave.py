@@ -94,6 +94,8 @@ def _load():
         "fd_adjoint_exact": ([G, P, A, D, I, P, P, DP, P, O, P], ctypes.c_int),
         "fd_vd_forward": ([G, P, P, A, D, I, P, O, P], ctypes.c_int),
         "fd_vd_adjoint_sensitivity": ([G, P, P, A, D, I, P, D, P, P, DP, P, O, P], ctypes.c_int),
+        "fd_vd_sens_forward": ([G, P, P, A, D, I, P, S, P, P, DP, O, P], ctypes.c_int),
+        "fd_vd_sens_backward": ([G, P, P, A, D, I, D, S, P, D, P, P, O, P], ctypes.c_int),
         "fd_sens_forward": ([G, P, A, D, I, P, S, P, DP, O, P], ctypes.c_int),
         "fd_sens_backward": ([G, P, A, D, I, D, S, D, P, O, P], ctypes.c_int),
         "fd_adjoint_sensitivity_batched": ([ctypes.POINTER(fd_problem), I, DP, O, P], ctypes.c_int),
@@ -336,6 +338,44 @@ class SweepState:
         s.residual = self.residual.data_ptr()
         return s
 
+
+
+class VdSweepState(SweepState):
+    """Caller-owned device state between fd_vd_sens_forward and fd_vd_sens_backward:
+    the constant-density state plus the stiffness-term accumulator."""
+
+    def __init__(self, m: torch.Tensor, nt: int, nrec: int, acc_dtype=None, nshot: int = 1):
+        super().__init__(m, nt, nrec, acc_dtype=acc_dtype, nshot=nshot)
+        self.acc_b = torch.empty_like(self.acc)
+
+
+def fd_vd_sens_forward(m, b, dx, src, wavelet, rec, dt, nt, observed, state: VdSweepState, traces=None,
+                       shots=None, **opts) -> float:
+    acq = _acq(src, wavelet, rec, shots)
+    g = make_grid(m.shape, dx, 2, _dtype_code(m))
+    o = make_opts(**opts)
+    J = ctypes.c_double()
+    st = state.c_struct()
+    _raise(_lib.fd_vd_sens_forward(ctypes.byref(g), _dev(m, "m"), _dev(b, "b"), ctypes.byref(acq.c), float(dt),
+                                   int(nt), _dev(observed, "observed"), ctypes.byref(st),
+                                   _dev(state.acc_b, "acc_b"), _dev(traces, "traces"), ctypes.byref(J),
+                                   ctypes.byref(o), _stream()))
+    return J.value
+
+
+def fd_vd_sens_backward(m, b, dx, src, wavelet, rec, dt, nt, k, state: VdSweepState, grad_scale=1.0,
+                        grad_m=None, grad_b=None, shots=None, **opts):
+    acq = _acq(src, wavelet, rec, shots)
+    grad_m = torch.empty_like(m) if grad_m is None else grad_m
+    grad_b = torch.empty_like(m) if grad_b is None else grad_b
+    g = make_grid(m.shape, dx, 2, _dtype_code(m))
+    o = make_opts(**opts)
+    st = state.c_struct()
+    _raise(_lib.fd_vd_sens_backward(ctypes.byref(g), _dev(m, "m"), _dev(b, "b"), ctypes.byref(acq.c), float(dt),
+                                    int(nt), float(k), ctypes.byref(st), _dev(state.acc_b, "acc_b"),
+                                    float(grad_scale), _dev(grad_m, "grad_m"), _dev(grad_b, "grad_b"),
+                                    ctypes.byref(o), _stream()))
+    return grad_m, grad_b
 
 def fd_sens_forward(c, dx, order, src, wavelet, rec, dt, nt, observed, state: SweepState,
                     traces=None, shots=None, **opts) -> float:

@@ -176,3 +176,51 @@ def test_vd_error_paths(fdw):
     with pytest.raises(fdw.FdError) as e:      # k = 0
         fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, dt, nt, od, 0.0)
     assert e.value.code == fdw.FD_E_ARG
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_vd_split_equals_fused_call(fdw, dtype):
+    """fd_vd_sens_forward then fd_vd_sens_backward gives the fused call's J, traces and
+    both sensitivities bit for bit; grad_scale multiplies both sensitivities."""
+    shape, nt = (22, 17, 70), 45
+    m, b, dt, src, rec, w, obs = _medium(shape, 51, nt)
+    k = 0.04
+    say("vd split vs fused", dtype)
+    gm, gb, J, tr = _run(fdw, m, b, dt, nt, src, w, rec, obs, k, dtype)
+    md, bd, wd, od = to_dev(m, dtype), to_dev(b, dtype), to_dev(w, dtype), to_dev(obs, dtype)
+    st = fdw.VdSweepState(md, nt, len(rec))
+    tr2 = torch.empty((nt, len(rec)), dtype=dtype, device="cuda")
+    J2 = fdw.fd_vd_sens_forward(md, bd, 1.0, src, wd, rec, dt, nt, od, st, traces=tr2)
+    gm2, gb2 = fdw.fd_vd_sens_backward(md, bd, 1.0, src, wd, rec, dt, nt, k, st)
+    torch.cuda.synchronize()
+    assert J2 == J
+    assert np.array_equal(tr2.double().cpu().numpy(), tr)
+    assert np.array_equal(gm2.double().cpu().numpy(), gm) and np.array_equal(gb2.double().cpu().numpy(), gb)
+    st = fdw.VdSweepState(md, nt, len(rec))
+    fdw.fd_vd_sens_forward(md, bd, 1.0, src, wd, rec, dt, nt, od, st)
+    gm3, gb3 = fdw.fd_vd_sens_backward(md, bd, 1.0, src, wd, rec, dt, nt, k, st, grad_scale=-0.25)
+    assert rel(gm3.double().cpu().numpy(), -0.25 * gm) < 1e-6
+    assert rel(gb3.double().cpu().numpy(), -0.25 * gb) < 1e-6
+
+
+def test_vd_autograd_matches_oracle(fdw):
+    """vd_misfit(m, b).backward() gives the oracle's Alg. 1 sensitivities (f64, same k),
+    scaled by the incoming gradient; a second backward raises."""
+    from paper_2509_15744_amd import autograd
+    shape, nt = (30, 41), 80
+    m, b, dt, src, rec, w, obs = _medium(shape, 61, nt, nrec=7)
+    k = 0.03
+    om, ob, oJ, _ = oracle.vd_superposition_gradient(m, b, 1.0, dt, nt, src, w, rec, obs, k)
+    f64 = torch.float64
+    prob = autograd.SensProblem(dx=1.0, order=2, src=src, rec=rec, wavelet=to_dev(w, f64),
+                                observed=to_dev(obs, f64), dt=dt, nt=nt)
+    md = to_dev(m, f64).requires_grad_(True)
+    bd = to_dev(b, f64).requires_grad_(True)
+    say("vd autograd")
+    J = autograd.vd_misfit(md, bd, prob, k)
+    (3.0 * J).backward(retain_graph=True)
+    assert abs(J.item() - oJ) <= 1e-12 * oJ
+    assert rel(md.grad.cpu().numpy(), 3.0 * om) < 1e-9
+    assert rel(bd.grad.cpu().numpy(), 3.0 * ob) < 1e-9
+    with pytest.raises(RuntimeError):
+        J.backward()
