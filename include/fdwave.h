@@ -226,7 +226,10 @@ int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, doub
  *     h(p, q) = 2 p q / (p + q)  (harmonic mean at the face)
  * Wall ghosts mirror the boundary cell and carry its material (no flux through a wall).
  * grid->order must be 2.  m, b DEVICE [ncell], finite and positive; dt must satisfy
- * dt sqrt(d max b / min m) <= dx (else FD_E_CFL).  Time axis, sources, receivers, shots
+ * dt^2 max_i s_i <= 4 dx^2 (else FD_E_CFL), s_i = sum over the interior faces of cell i
+ * of h_f (1/m_i + 1/sqrt(m_i m_j)): the Gershgorin bound of the leapfrog limit
+ * dt^2 lambda_max(M^-1 K) < 4, equal to dt sqrt(d b/m) <= dx in a homogeneous medium
+ * and local where materials mix.  Time axis, sources, receivers, shots
  * and misfit as for the constant-density calls.  fd_opts.variant: 0, 1 or 2;
  * max_group is ignored (one wavefield per launch). */
 int fd_vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
@@ -293,6 +296,58 @@ int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, doubl
  * coef DEVICE [ncell] is dt^2 c^2 itself (no CFL check). */
 int fd_propagate(const fd_grid* grid, const void* coef, void* u_prev, void* u_cur,
                  int32_t nsteps, const fd_opts* opts, void* stream);
+
+/* ---- gradient-based design around the sweeps ------------------------------------
+ * A design field gamma lives on a box of cells inside the grid (one value per box
+ * cell, C order over the box).  The material of the variable-material calls is made
+ * from it by the topology-optimisation chain of Sec. 2.3 (Constraints):
+ *   filtered   gt_i = sum_k w_ik gamma_k / sum_k w_ik,  w_ik = r_f - |x_i - x_k| for
+ *              |x_i - x_k| < r_f (in cells), k over the box (density filter with
+ *              linear decay);
+ *   projected  h_i = (tanh(beta eta) + tanh(beta (gt_i - eta)))
+ *                    / (tanh(beta eta) + tanh(beta (1 - eta)))   (smoothed Heaviside);
+ *   clipped    g_i = min(max(h_i, lo), hi);
+ *   material   m = m0 + g dm,  b = b0 + g db   at the grid cell of box cell i.
+ * Both of the paper's maps are this affine form: rho-scaling (Eq.
+ * scalarwaveequation) m0 = b0 = 0, dm = rho0, db = rho0 c0^2; the two-material map
+ * (Eq. wavetopopt) m0 = 1/kappa1, dm = 1/kappa2 - 1/kappa1, b0 = 1/rho1,
+ * db = 1/rho2 - 1/rho1.  Grid cells outside the box keep their values. */
+typedef struct fd_design {
+    int32_t ndim;          /* 2 or 3 */
+    int64_t shape[3];      /* grid extents (m, b and their gradients are [shape], C order) */
+    int64_t origin[3];     /* first grid cell of the box, per axis */
+    int64_t extent[3];     /* box extents (>= 1); the box must lie inside the grid */
+    int32_t dtype;         /* FD_F32 or FD_F64 for every field of these calls */
+    double filter_radius;  /* r_f in cells, at most 32; r_f <= 1 means no filter */
+    double beta, eta;      /* projection sharpness (> 0) and threshold in [0, 1]; beta <= 0: none */
+    double lo, hi;         /* clip interval of the projected field, lo <= hi */
+    double m0, dm, b0, db; /* affine material map (finite) */
+} fd_design;
+
+/* Material from the design field: writes m and b DEVICE [shape] at the box cells and,
+ * when gamma_bar is not NULL, the clipped projected field DEVICE [box] (the field the
+ * material is affine in).  gamma DEVICE [box].  FD_E_ARG on a bad description or null
+ * pointers; no synchronisation. */
+int fd_design_map(const fd_design* design, const void* gamma, void* m, void* b, void* gamma_bar,
+                  void* stream);
+
+/* The chain rule of fd_design_map (Sec. 2.3): from grad_m = dC/dm and grad_b = dC/db
+ * (DEVICE [shape]; read at the box cells) to grad_gamma = dC/dgamma DEVICE [box]:
+ *   dC/dgamma_k = sum_i w_ik / W_i * [lo <= h_i <= hi] * dh/dgt(gt_i) * (dm grad_m_i + db grad_b_i),
+ * W_i = sum_k w_ik, the derivative of the clip taken as 1 on the closed interval and 0
+ * outside.  Takes one box-sized scratch buffer (stream-ordered); FD_E_NOMEM if it cannot. */
+int fd_design_adjoint(const fd_design* design, const void* gamma, const void* grad_m, const void* grad_b,
+                      void* grad_gamma, void* stream);
+
+/* One Adam step (the optimiser the paper pairs with Eq. gradientdescent) on x DEVICE [n]
+ * from grad DEVICE [n], with first and second moments m1, m2 DEVICE [n] updated in place
+ * (zero before step 1):
+ *   m1 = beta1 m1 + (1 - beta1) g,   m2 = beta2 m2 + (1 - beta2) g^2,
+ *   x -= lr (m1 / (1 - beta1^step)) / (sqrt(m2 / (1 - beta2^step)) + eps),
+ * then x is clipped to [lo, hi] (the paper clips the design field after each update).
+ * step >= 1; 0 <= beta1, beta2 < 1; eps >= 0; lr finite; lo <= hi. */
+int fd_adam_step(int64_t n, int32_t dtype, void* x, const void* grad, void* m1, void* m2, int32_t step,
+                 double lr, double beta1, double beta2, double eps, double lo, double hi, void* stream);
 
 #ifdef __cplusplus
 }

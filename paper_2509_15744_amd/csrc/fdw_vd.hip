@@ -20,6 +20,7 @@
 // LDS with a one-cell halo, loads of plane x+1 issued before plane x is computed,
 // XCD-aware block order); one wavefield per launch.
 
+#include "fdw_aux.h"
 #include "fdw_step_body.h"
 
 namespace fdw {
@@ -290,6 +291,85 @@ hipError_t launch_vd_step(int ndim, int dtype, int acc_dtype, int variant, int n
     if (dtype == 1) return launch_vd_rt<double, double>(ndim, variant, nblk, a, s);
     if (acc_dtype == 1) return launch_vd_rt<float, double>(ndim, variant, nblk, a, s);
     return launch_vd_rt<float, float>(ndim, variant, nblk, a, s);
+}
+
+// ---------------------------------------------------------------------------
+// stability bound of the variable-material scheme
+// ---------------------------------------------------------------------------
+
+// Per cell, the Gershgorin row sum of the symmetric form M^-1/2 K M^-1/2 of the
+// spatial operator (times dx^2):
+//   s_i = sum over the interior faces f of cell i of h_f (1/m_i + 1/sqrt(m_i m_j)),
+// h_f the harmonic-mean face stiffness; wall faces carry no flux and add nothing.
+// Partial maxima per block in f64 (n1 = 1 for 2D grids).
+template <typename T>
+__global__ __launch_bounds__(kReduceThreads) void vd_bound_partial(const T* __restrict__ m,
+                                                                   const T* __restrict__ b, int64_t n0,
+                                                                   int64_t n1, int64_t n2,
+                                                                   double* __restrict__ part)
+{
+    __shared__ double smax[kReduceThreads];
+    const int64_t ncell = n0 * n1 * n2;
+    const int64_t strides[3] = {n1 * n2, n2, 1};
+    const int64_t ext[3] = {n0, n1, n2};
+    double mx = 0.0;
+    for (int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
+         cell += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t idx[3] = {cell / strides[0], (cell / n2) % n1, cell % n2};
+        const double mi = (double)m[cell];
+        const double bi = (double)b[cell];
+        double sum = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            for (int dir = -1; dir <= 1; dir += 2) {
+                const int64_t q = idx[ax] + dir;
+                if (q < 0 || q >= ext[ax]) continue;
+                const int64_t j = cell + dir * strides[ax];
+                const double mj = (double)m[j];
+                const double bj = (double)b[j];
+                const double h = 2.0 * bi * bj / (bi + bj);
+                sum += h * (1.0 / mi + 1.0 / sqrt(mi * mj));
+            }
+        }
+        mx = fmax(mx, sum);
+    }
+    const int t = threadIdx.x;
+    smax[t] = mx;
+    __syncthreads();
+    for (int off = kReduceThreads / 2; off > 0; off >>= 1) {
+        if (t < off) smax[t] = fmax(smax[t], smax[t + off]);
+        __syncthreads();
+    }
+    if (t == 0) part[blockIdx.x] = smax[0];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void max_final(const double* __restrict__ part, int nparts,
+                                                            double* __restrict__ out)
+{
+    __shared__ double smax[kReduceThreads];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kReduceThreads) mx = fmax(mx, part[i]);
+    const int t = threadIdx.x;
+    smax[t] = mx;
+    __syncthreads();
+    for (int off = kReduceThreads / 2; off > 0; off >>= 1) {
+        if (t < off) smax[t] = fmax(smax[t], smax[t + off]);
+        __syncthreads();
+    }
+    if (t == 0) out[0] = smax[0];
+}
+
+hipError_t launch_vd_bound(int dtype, const void* m, const void* b, int64_t n0, int64_t n1, int64_t n2,
+                           double* d_out, double* d_part, hipStream_t s)
+{
+    if (dtype == 1)
+        hipLaunchKernelGGL(vd_bound_partial<double>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s,
+                           (const double*)m, (const double*)b, n0, n1, n2, d_part);
+    else
+        hipLaunchKernelGGL(vd_bound_partial<float>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s,
+                           (const float*)m, (const float*)b, n0, n1, n2, d_part);
+    hipLaunchKernelGGL(max_final, dim3(1), dim3(kReduceThreads), 0, s, (const double*)d_part, kReduceBlocks,
+                       d_out);
+    return hipGetLastError();
 }
 
 }  // namespace fdw

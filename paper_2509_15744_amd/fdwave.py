@@ -14,6 +14,7 @@ default, or "f32"), ``variant`` (tile variant, 0 = library choice), ``chunk``
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -74,6 +75,14 @@ class fd_problem(ctypes.Structure):
                 ("grad_c", ctypes.c_void_p), ("traces", ctypes.c_void_p)]
 
 
+class fd_design(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("shape", ctypes.c_int64 * 3), ("origin", ctypes.c_int64 * 3),
+                ("extent", ctypes.c_int64 * 3), ("dtype", ctypes.c_int32), ("filter_radius", ctypes.c_double),
+                ("beta", ctypes.c_double), ("eta", ctypes.c_double), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double), ("m0", ctypes.c_double), ("dm", ctypes.c_double),
+                ("b0", ctypes.c_double), ("db", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -101,6 +110,9 @@ def _load():
         "fd_adjoint_sensitivity_batched": ([ctypes.POINTER(fd_problem), I, DP, O, P], ctypes.c_int),
         "fd_propagate": ([G, P, P, P, I, O, P], ctypes.c_int),
         "fd_autotune": ([G, I, O, I, O, DP, P], ctypes.c_int),
+        "fd_design_map": ([ctypes.POINTER(fd_design), P, P, P, P, P], ctypes.c_int),
+        "fd_design_adjoint": ([ctypes.POINTER(fd_design), P, P, P, P, P], ctypes.c_int),
+        "fd_adam_step": ([ctypes.c_int64, I, P, P, P, P, I, D, D, D, D, D, D, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -141,6 +153,42 @@ def _dev(t, what):
 
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _fits(t, n, like, what):
+    """The library reads or writes n values of the field dtype through t's pointer:
+    t (when given) must hold at least n values of like's dtype.  The library's own
+    range check sees whole allocator blocks, so undersized tensors are caught here."""
+    if t is None:
+        return
+    if t.dtype != like.dtype:
+        raise TypeError(f"{what} is {t.dtype}, the field is {like.dtype}")
+    if t.numel() < n:
+        raise ValueError(f"{what} has {t.numel()} values, {n} are needed")
+
+
+def _check_io(field, nt, acq, wavelet=None, observed=None, traces=None, extra_fields=()):
+    """Sizes of the arrays a sweep touches: wavelet [nt][nsrc], observed and traces
+    [nt][nrec], other grid fields [ncell]."""
+    n = field.numel()
+    nt = int(nt)
+    _fits(wavelet if wavelet is not None else acq.wavelet, nt * acq.c.nsrc, field, "wavelet")
+    _fits(observed, nt * acq.c.nrec, field, "observed")
+    _fits(traces, nt * acq.c.nrec, field, "traces")
+    for what, t in extra_fields:
+        _fits(t, n, field, what)
+
+
+def _check_state(field, nt, acq, state, nshot=1):
+    n = field.numel()
+    ns = max(int(nshot), 1)
+    for what, t, need in (("state.u_a", state.u_a, ns * n), ("state.u_b", state.u_b, ns * n),
+                          ("state.residual", state.residual, int(nt) * acq.c.nrec)):
+        _fits(t, need, field, what)
+    for what in ("acc", "acc_b"):
+        t = getattr(state, what, None)
+        if t is not None and t.numel() < n:
+            raise ValueError(f"state.{what} has {t.numel()} values, {n} are needed")
 
 
 def make_grid(shape, dx, order, dtype_code) -> fd_grid:
@@ -242,6 +290,7 @@ def fd_forward(c, dx, order, src, wavelet, rec, dt, nt, traces=None, shots=None,
     acq = _acq(src, wavelet, rec, shots)
     if traces is None:
         traces = torch.empty((nt, len(acq.rec)), dtype=c.dtype, device=c.device)
+    _check_io(c, nt, acq, traces=traces)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
     o = make_opts(**opts)
     _raise(_lib.fd_forward(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt),
@@ -252,6 +301,8 @@ def fd_forward(c, dx, order, src, wavelet, rec, dt, nt, traces=None, shots=None,
 def fd_misfit(traces, observed, dt, residual=None) -> float:
     """J = dt/2 sum (traces - observed)^2; fills ``residual`` when given."""
     nt, nrec = traces.shape
+    _fits(observed, traces.numel(), traces, "observed")
+    _fits(residual, traces.numel(), traces, "residual")
     J = ctypes.c_double()
     _raise(_lib.fd_misfit(int(nt), int(nrec), _dtype_code(traces), float(dt),
                           _dev(traces, "traces"), _dev(observed, "observed"),
@@ -265,6 +316,7 @@ def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k,
     acq = _acq(src, wavelet, rec, shots)
     if grad is None:
         grad = torch.empty_like(c)
+    _check_io(c, nt, acq, observed=observed, traces=traces, extra_fields=[("grad", grad)])
     g = make_grid(c.shape, dx, order, _dtype_code(c))
     o = make_opts(**opts)
     J = ctypes.c_double()
@@ -281,6 +333,7 @@ def fd_adjoint_exact(c, dx, order, src, wavelet, rec, dt, nt, observed, grad=Non
     acq = _acq(src, wavelet, rec, shots)
     if grad is None:
         grad = torch.empty_like(c)
+    _check_io(c, nt, acq, observed=observed, traces=traces, extra_fields=[("grad", grad)])
     g = make_grid(c.shape, dx, order, _dtype_code(c))
     o = make_opts(**opts)
     J = ctypes.c_double()
@@ -295,6 +348,7 @@ def fd_vd_forward(m, b, dx, src, wavelet, rec, dt, nt, traces=None, shots=None, 
     acq = _acq(src, wavelet, rec, shots)
     if traces is None:
         traces = torch.empty((int(nt), acq.c.nrec), dtype=m.dtype, device=m.device)
+    _check_io(m, nt, acq, traces=traces, extra_fields=[("b", b)])
     g = make_grid(m.shape, dx, 2, _dtype_code(m))
     o = make_opts(**opts)
     _raise(_lib.fd_vd_forward(ctypes.byref(g), _dev(m, "m"), _dev(b, "b"), ctypes.byref(acq.c), float(dt),
@@ -308,6 +362,8 @@ def fd_vd_adjoint_sensitivity(m, b, dx, src, wavelet, rec, dt, nt, observed, k, 
     acq = _acq(src, wavelet, rec, shots)
     grad_m = torch.empty_like(m) if grad_m is None else grad_m
     grad_b = torch.empty_like(m) if grad_b is None else grad_b
+    _check_io(m, nt, acq, observed=observed, traces=traces,
+              extra_fields=[("b", b), ("grad_m", grad_m), ("grad_b", grad_b)])
     g = make_grid(m.shape, dx, 2, _dtype_code(m))
     o = make_opts(**opts)
     J = ctypes.c_double()
@@ -352,6 +408,8 @@ class VdSweepState(SweepState):
 def fd_vd_sens_forward(m, b, dx, src, wavelet, rec, dt, nt, observed, state: VdSweepState, traces=None,
                        shots=None, **opts) -> float:
     acq = _acq(src, wavelet, rec, shots)
+    _check_io(m, nt, acq, observed=observed, traces=traces, extra_fields=[("b", b)])
+    _check_state(m, nt, acq, state, acq.nshot)
     g = make_grid(m.shape, dx, 2, _dtype_code(m))
     o = make_opts(**opts)
     J = ctypes.c_double()
@@ -368,6 +426,8 @@ def fd_vd_sens_backward(m, b, dx, src, wavelet, rec, dt, nt, k, state: VdSweepSt
     acq = _acq(src, wavelet, rec, shots)
     grad_m = torch.empty_like(m) if grad_m is None else grad_m
     grad_b = torch.empty_like(m) if grad_b is None else grad_b
+    _check_io(m, nt, acq, extra_fields=[("b", b), ("grad_m", grad_m), ("grad_b", grad_b)])
+    _check_state(m, nt, acq, state, acq.nshot)
     g = make_grid(m.shape, dx, 2, _dtype_code(m))
     o = make_opts(**opts)
     st = state.c_struct()
@@ -380,6 +440,8 @@ def fd_vd_sens_backward(m, b, dx, src, wavelet, rec, dt, nt, k, state: VdSweepSt
 def fd_sens_forward(c, dx, order, src, wavelet, rec, dt, nt, observed, state: SweepState,
                     traces=None, shots=None, **opts) -> float:
     acq = _acq(src, wavelet, rec, shots)
+    _check_io(c, nt, acq, observed=observed, traces=traces)
+    _check_state(c, nt, acq, state, acq.nshot)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
     o = make_opts(**opts)
     st = state.c_struct()
@@ -395,6 +457,8 @@ def fd_sens_backward(c, dx, order, src, wavelet, rec, dt, nt, k, state: SweepSta
     acq = _acq(src, wavelet, rec, shots)
     if grad is None:
         grad = torch.empty_like(c)
+    _check_io(c, nt, acq, extra_fields=[("grad", grad)])
+    _check_state(c, nt, acq, state, acq.nshot)
     g = make_grid(c.shape, dx, order, _dtype_code(c))
     o = make_opts(**opts)
     st = state.c_struct()
@@ -412,6 +476,7 @@ class Problem:
         self.acq = Acquisition(src, wavelet, rec)
         self.grad = torch.empty_like(c) if grad is None else grad
         self.traces = traces
+        _check_io(c, nt, self.acq, observed=observed, traces=traces, extra_fields=[("grad", self.grad)])
         p = fd_problem()
         p.grid = make_grid(c.shape, dx, order, _dtype_code(c))
         p.c = _dev(c, "c")
@@ -451,8 +516,82 @@ def fd_autotune(shape, dx, order, dtype=torch.float32, nshot=1, steps=3, **opts)
 
 def fd_propagate(coef, u_prev, u_cur, nsteps, dx, order, **opts):
     """In place: (u_prev, u_cur) advance by ``nsteps`` source-free steps."""
+    for what, t in (("u_prev", u_prev), ("u_cur", u_cur)):
+        _fits(t, coef.numel(), coef, what)
     g = make_grid(coef.shape, dx, order, _dtype_code(coef))
     o = make_opts(**opts)
     _raise(_lib.fd_propagate(ctypes.byref(g), _dev(coef, "coef"), _dev(u_prev, "u_prev"),
                              _dev(u_cur, "u_cur"), int(nsteps), ctypes.byref(o), _stream()))
     return u_prev, u_cur
+
+
+# ---- gradient-based design ---------------------------------------------------------
+
+def make_design(shape, origin, extent, dtype_code, material, filter_radius=0.0, beta=0.0, eta=0.5,
+                lo=0.0, hi=1.0) -> fd_design:
+    """Description of a design box and its chain (fd_design).  ``material`` is the affine
+    map (m0, dm, b0, db); ``rho_scaling`` and ``two_material`` build the paper's two."""
+    d = fd_design()
+    d.ndim = len(shape)
+    for i in range(len(shape)):
+        d.shape[i] = int(shape[i])
+        d.origin[i] = int(origin[i])
+        d.extent[i] = int(extent[i])
+    d.dtype = int(dtype_code)
+    d.filter_radius = float(filter_radius)
+    d.beta = float(beta)
+    d.eta = float(eta)
+    d.lo = float(lo)
+    d.hi = float(hi)
+    d.m0, d.dm, d.b0, d.db = (float(v) for v in material)
+    return d
+
+
+def rho_scaling(rho0: float, c0: float):
+    """(m0, dm, b0, db) of gamma rho0 u_tt - div(gamma rho0 c0^2 grad u) = f (Eq. scalarwaveequation)."""
+    return 0.0, rho0, 0.0, rho0 * c0 * c0
+
+
+def two_material(rho1: float, rho2: float, kappa1: float, kappa2: float):
+    """(m0, dm, b0, db) of the linear inverse bulk modulus and inverse density maps of
+    Eq. wavetopopt (gamma = 0: material 1, gamma = 1: material 2)."""
+    return 1.0 / kappa1, 1.0 / kappa2 - 1.0 / kappa1, 1.0 / rho1, 1.0 / rho2 - 1.0 / rho1
+
+
+def _design_sizes(design: fd_design, box_fields, grid_fields):
+    nbox = math.prod(int(design.extent[i]) for i in range(design.ndim))
+    ngrid = math.prod(int(design.shape[i]) for i in range(design.ndim))
+    for name, t in box_fields:
+        if t is not None and t.numel() != nbox:
+            raise ValueError(f"{name} has {t.numel()} values, the design box {nbox}")
+    for name, t in grid_fields:
+        if t.numel() != ngrid:
+            raise ValueError(f"{name} has {t.numel()} values, the grid {ngrid}")
+
+
+def fd_design_map(design: fd_design, gamma, m, b, gamma_bar=None):
+    """Write the material of the design field into m and b (box cells only)."""
+    _design_sizes(design, [("gamma", gamma), ("gamma_bar", gamma_bar)], [("m", m), ("b", b)])
+    _raise(_lib.fd_design_map(ctypes.byref(design), _dev(gamma, "gamma"), _dev(m, "m"), _dev(b, "b"),
+                              _dev(gamma_bar, "gamma_bar"), _stream()))
+    return m, b
+
+
+def fd_design_adjoint(design: fd_design, gamma, grad_m, grad_b, grad_gamma=None):
+    """dC/dgamma from dC/dm and dC/db through the chain of fd_design_map."""
+    grad_gamma = torch.empty_like(gamma) if grad_gamma is None else grad_gamma
+    _design_sizes(design, [("gamma", gamma), ("grad_gamma", grad_gamma)], [("grad_m", grad_m), ("grad_b", grad_b)])
+    _raise(_lib.fd_design_adjoint(ctypes.byref(design), _dev(gamma, "gamma"), _dev(grad_m, "grad_m"),
+                                  _dev(grad_b, "grad_b"), _dev(grad_gamma, "grad_gamma"), _stream()))
+    return grad_gamma
+
+
+def fd_adam_step(x, grad, m1, m2, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, lo=-math.inf, hi=math.inf):
+    """One Adam update of x in place (moments m1, m2 in place), then x clipped to [lo, hi]."""
+    for name, t in (("grad", grad), ("m1", m1), ("m2", m2)):
+        if t.numel() != x.numel():
+            raise ValueError(f"{name} has {t.numel()} values, x {x.numel()}")
+    _raise(_lib.fd_adam_step(x.numel(), _dtype_code(x), _dev(x, "x"), _dev(grad, "grad"), _dev(m1, "m1"),
+                             _dev(m2, "m2"), int(step), float(lr), float(beta1), float(beta2), float(eps),
+                             float(lo), float(hi), _stream()))
+    return x

@@ -77,3 +77,21 @@ def shot_problem(shape, nshot, order, nt, dtype, seed):
     obs = 0.01 * rng.standard_normal((nt, len(rec)))
     return dict(shape=shape, order=order, nt=nt, dtype=dtype, c=c, dt=dt, src=src, rec=rec,
                 src_shot=src_shot, rec_shot=rec_shot, wavelet=wavelet, obs=obs, nshot=nshot)
+
+
+def gershgorin_rows(m, b):
+    """Row sums s_i = sum over interior faces of h_f (1/m_i + 1/sqrt(m_i m_j)) of the
+    symmetric form M^-1/2 K M^-1/2 (times dx^2), the per-cell stability bound the
+    library checks."""
+    s = np.zeros(m.shape)
+    for ax in range(m.ndim):
+        n = m.shape[ax]
+        lo = [slice(None)] * m.ndim
+        hi = [slice(None)] * m.ndim
+        lo[ax] = slice(0, n - 1)
+        hi[ax] = slice(1, n)
+        lo, hi = tuple(lo), tuple(hi)
+        h = 2 * b[lo] * b[hi] / (b[lo] + b[hi])
+        s[lo] += h * (1 / m[lo] + 1 / np.sqrt(m[lo] * m[hi]))
+        s[hi] += h * (1 / m[hi] + 1 / np.sqrt(m[lo] * m[hi]))
+    return s

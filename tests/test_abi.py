@@ -172,3 +172,40 @@ def test_error_message_is_thread_local_and_cleared(fdw):
     t.join()
     assert seen == [""]
     assert fdw.lib().fd_last_error().decode() != ""
+
+
+def test_design_validation(fdw):
+    """fd_design_map / fd_design_adjoint / fd_adam_step reject bad descriptions and
+    arguments before touching device memory."""
+    f = fdw.lib().fd_design_map
+    mat = (0.0, 1.0, 0.0, 1.0)
+    cases = [
+        (fdw.make_design((10, 12), (8, 0), (4, 4), fdw.FD_F64, mat), "inside the grid"),
+        (fdw.make_design((10, 12), (0, 0), (0, 4), fdw.FD_F64, mat), "inside the grid"),
+        (fdw.make_design((10, 12), (0, 0), (4, 4), 3, mat), "dtype"),
+        (fdw.make_design((10, 12), (0, 0), (4, 4), fdw.FD_F64, mat, 40.0), "filter_radius"),
+        (fdw.make_design((10, 12), (0, 0), (4, 4), fdw.FD_F64, mat, 1.5, 2.0, 1.5), "eta"),
+        (fdw.make_design((10, 12), (0, 0), (4, 4), fdw.FD_F64, mat, lo=1.0, hi=0.0), "lo <= hi"),
+        (fdw.make_design((10, 12), (0, 0), (4, 4), fdw.FD_F64, (0.0, float("inf"), 0.0, 1.0)), "finite"),
+    ]
+    for d, msg in cases:
+        assert f(ctypes.byref(d), None, None, None, None, None) == fdw.FD_E_ARG
+        assert msg in fdw.lib().fd_last_error().decode(), msg
+    ok = fdw.make_design((10, 12), (0, 0), (4, 4), fdw.FD_F64, mat)
+    assert f(ctypes.byref(ok), None, None, None, None, None) == fdw.FD_E_ARG
+    assert "gamma is null" in fdw.lib().fd_last_error().decode()
+    assert fdw.lib().fd_design_adjoint(None, None, None, None, None, None) == fdw.FD_E_ARG
+    a = fdw.lib().fd_adam_step
+    assert a(8, fdw.FD_F64, None, None, None, None, 0, 0.1, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == fdw.FD_E_ARG
+    assert "step" in fdw.lib().fd_last_error().decode()
+    assert a(8, fdw.FD_F64, None, None, None, None, 1, 0.1, 1.0, 0.999, 1e-8, 0.0, 1.0, None) == fdw.FD_E_ARG
+    assert a(8, fdw.FD_F64, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, 1.0, 0.0, None) == fdw.FD_E_ARG
+    assert a(8, fdw.FD_F64, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == fdw.FD_E_ARG
+    assert "x is null" in fdw.lib().fd_last_error().decode()
+
+
+def test_stable_dt_reduces_to_the_homogeneous_limit():
+    """design.stable_dt over a one-value material range is frac * dx / sqrt(d b/m)."""
+    from paper_2509_15744_amd import design as dz
+    dt = dz.stable_dt((2.0, 0.0, 8.0, 0.0), 0.0, 1.0, 0.5, 2, frac=1.0)
+    assert abs(dt - 0.5 / np.sqrt(2 * 8.0 / 2.0)) < 1e-15

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_2509_15744_amd import workloads as wl
-from helpers import rel, say, to_dev
+from helpers import gershgorin_rows, rel, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -163,7 +163,7 @@ def test_vd_error_paths(fdw):
     f64 = torch.float64
     md, bd, wd, od = to_dev(m, f64), to_dev(b, f64), to_dev(w, f64), to_dev(obs, f64)
     with pytest.raises(fdw.FdError) as e:      # stability bound
-        fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, 3 * dt, nt, od, 0.1)
+        fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, 4 * dt, nt, od, 0.1)
     assert e.value.code == fdw.FD_E_CFL
     with pytest.raises(fdw.FdError) as e:      # a non-positive mass
         m2 = m.copy()
@@ -176,6 +176,10 @@ def test_vd_error_paths(fdw):
     with pytest.raises(fdw.FdError) as e:      # k = 0
         fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, dt, nt, od, 0.0)
     assert e.value.code == fdw.FD_E_ARG
+    with pytest.raises(ValueError):            # observed smaller than [nt][nrec]
+        fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, dt, nt, od[:-1].contiguous(), 0.1)
+    with pytest.raises(TypeError):             # stiffness of another dtype
+        fdw.fd_vd_adjoint_sensitivity(md, bd.float(), 1.0, src, wd, rec, dt, nt, od, 0.1)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -224,3 +228,30 @@ def test_vd_autograd_matches_oracle(fdw):
     assert rel(bd.grad.cpu().numpy(), 3.0 * ob) < 1e-9
     with pytest.raises(RuntimeError):
         J.backward()
+
+
+def test_vd_stability_bound_is_per_cell(fdw):
+    """Blocky air/solid medium (the topology-optimisation materials, Eq. wavetopopt,
+    mass scaled by 1e6): a time step at 0.99 of the per-cell Gershgorin limit runs and
+    matches the oracle, 1.01 of it is refused with FD_E_CFL, and a global
+    dt sqrt(d max b / min m) <= dx rule would have refused both."""
+    rng = np.random.default_rng(71)
+    shape, nt = (40, 66), 200
+    blocks = rng.random((5, 11)) < 0.4
+    solid = np.kron(blocks, np.ones((8, 6), dtype=bool))
+    m = np.where(solid, 1.46e-9, 7.05e-6) * 1e6
+    b = np.where(solid, 3.78e-4, 0.83)
+    dt_lim = 2.0 / np.sqrt(gershgorin_rows(m, b).max())
+    assert 0.99 * dt_lim * np.sqrt(2 * b.max() / m.min()) > 10.0
+    n = m.size
+    src = rng.integers(0, n, 2).astype(np.int64)
+    rec = rng.integers(0, n, 11).astype(np.int64)
+    w = rng.standard_normal((nt, 2))
+    f64 = torch.float64
+    say("vd per-cell stability bound")
+    tr = fdw.fd_vd_forward(to_dev(m, f64), to_dev(b, f64), 1.0, src, to_dev(w, f64), rec, 0.99 * dt_lim, nt)
+    otr, _, _ = oracle.vd_forward(m, b, 1.0, 0.99 * dt_lim, nt, src, w, rec)
+    assert rel(tr.cpu().numpy(), otr) < 1e-12
+    with pytest.raises(fdw.FdError) as e:
+        fdw.fd_vd_forward(to_dev(m, f64), to_dev(b, f64), 1.0, src, to_dev(w, f64), rec, 1.01 * dt_lim, nt)
+    assert e.value.code == fdw.FD_E_CFL

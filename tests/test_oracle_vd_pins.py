@@ -14,12 +14,17 @@ harmonic-mean faces) against facts fixed independently of its code:
   every cell of tiny grids;
 * Alg. 1 differs from the exact gradient by the closed forms -(k/2) sum (dmu)^2
   (mass) and (dt^2/dx^2)(k/2) sum_faces dh/db (dmu)^2 (stiffness); the +/-k average
-  is exact.
+  is exact;
+* the per-cell stability bound (Gershgorin row sums of M^-1/2 K M^-1/2) covers the
+  largest eigenvalue of M^-1 K from a dense eigen-solve, reaches the closed-form
+  Neumann eigenvalue's bound in a homogeneous medium, and leapfrog runs are bounded
+  just below 2/sqrt(lambda_max) and blow up just above it.
 """
 import numpy as np
 import pytest
 
 import oracle
+from helpers import gershgorin_rows
 
 
 def _medium(shape, seed):
@@ -161,3 +166,70 @@ def test_superposition_gap_closed_form(shape, dx):
     assert np.abs((ab - gb) - 0.5 * k * dt ** 2 / dx ** 2 * s2b).max() <= 1e-10 * np.abs(gb).max()
     assert np.abs(0.5 * (am + bm) - gm).max() <= 1e-10 * np.abs(gm).max()
     assert np.abs(0.5 * (ab + bb) - gb).max() <= 1e-10 * np.abs(gb).max()
+
+
+def _stiffness_matrix(b, dx):
+    """K = -L_b as a dense matrix, column by column from the oracle's operator."""
+    n = b.size
+    K = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        K[:, j] = -oracle.vd_operator(b, e.reshape(b.shape), dx).reshape(-1)
+    return K
+
+
+def test_stability_bound_homogeneous_closed_form():
+    """Homogeneous medium: lambda_max(M^-1 K) is the cell-centred Neumann eigenvalue
+    (b/m)(4/dx^2) sum_ax sin^2(pi (n_ax - 1) / (2 n_ax)), below the row-sum bound
+    4 d b / (m dx^2), which the interior rows reach."""
+    import scipy.linalg
+    shape, dx, mv, bv = (7, 5), 0.5, 1.7, 2.3
+    K = _stiffness_matrix(np.full(shape, bv), dx)
+    lam = scipy.linalg.eigh(K, np.eye(K.shape[0]) * mv, eigvals_only=True)
+    want = bv / mv * 4 / dx ** 2 * sum(np.sin(np.pi * (n - 1) / (2 * n)) ** 2 for n in shape)
+    assert abs(lam.max() - want) < 1e-12 * want
+    s = gershgorin_rows(np.full(shape, mv), np.full(shape, bv))
+    assert abs(s.max() / dx ** 2 - 4 * len(shape) * bv / mv / dx ** 2) < 1e-12 * s.max()
+
+
+@pytest.mark.parametrize("shape,seed", [((6, 5), 1), ((4, 3, 5), 2)])
+def test_stability_bound_covers_lambda_max(shape, seed):
+    """Air/solid-like mixtures (Eq. wavetopopt materials scaled to unit order): the
+    per-cell bound is at least lambda_max, and well below the global
+    4 d max b / (min m dx^2), which pairs one material's stiffness with the other's mass."""
+    import scipy.linalg
+    rng = np.random.default_rng(seed)
+    solid = rng.random(shape) < 0.5
+    m = np.where(solid, 1.46e-9, 7.05e-6) * 1e6
+    b = np.where(solid, 3.78e-4, 0.83)
+    dx = 1.0
+    K = _stiffness_matrix(b, dx)
+    lam = scipy.linalg.eigh(K, np.diag(m.reshape(-1)), eigvals_only=True).max()
+    s = gershgorin_rows(m, b).max() / dx ** 2
+    assert lam <= s * (1 + 1e-12)
+    assert s < 0.05 * 4 * len(shape) * b.max() / m.min() / dx ** 2
+
+
+def test_leapfrog_limit_is_lambda_max():
+    """Oracle runs driven by a +/- impulse pair (no net force, so the Neumann zero mode
+    stays at rest) stay bounded at dt = 0.999 * 2/sqrt(lambda_max) and grow without
+    bound at 1.02 times it: the limit the bound guards is the right one."""
+    import scipy.linalg
+    rng = np.random.default_rng(4)
+    shape = (6, 7)
+    m = 0.5 + rng.random(shape)
+    b = 0.5 + rng.random(shape)
+    K = _stiffness_matrix(b, 1.0)
+    lam = scipy.linalg.eigh(K, np.diag(m.reshape(-1)), eigvals_only=True).max()
+    nt = 3000
+    w = np.zeros((nt, 2))
+    w[0] = (1.0, -1.0)
+    src = np.array([9, 30], dtype=np.int64)
+    rec = np.arange(m.size, dtype=np.int64)
+    tr, _, _ = oracle.vd_forward(m, b, 1.0, 0.999 * 2 / np.sqrt(lam), nt, src, w, rec)
+    assert np.abs(tr[nt // 2:]).max() < 2.0 * np.abs(tr[:nt // 2]).max()
+    with np.errstate(all="ignore"):
+        tr, _, _ = oracle.vd_forward(m, b, 1.0, 1.02 * 2 / np.sqrt(lam), nt, src, w, rec)
+        grown = np.abs(tr[nt // 2:]).max() / np.abs(tr[:nt // 2]).max()
+    assert not np.isfinite(tr).all() or grown > 1e6
