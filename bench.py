@@ -386,6 +386,91 @@ def run_vd(args, np, torch, fdw, wl):
     return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, per_cell / (2 * nt - 1)), None, None, None
 
 
+def cpu_baseline_vd2d(q, m_dev, b_dev, wl, crop=(1024, 2048), nt_s=100):
+    """The FP64 oracle of the variable-material scheme on a bounded sample of the 2D
+    design workload: a crop around the source (design box and region cells inside it
+    keep their material and receivers), nt_s steps forward + superposed backward."""
+    import numpy as np
+    import oracle
+    shape = q["shape"]
+    crop = (min(crop[0], shape[0]), min(crop[1], shape[1]))
+    sx = [int(v) for v in np.unravel_index(int(q["src"][0]), shape)]
+    lo = [max(0, min(sx[a] - crop[a] // 2, shape[a] - crop[a])) for a in range(2)]
+    sl = tuple(slice(lo[a], lo[a] + crop[a]) for a in range(2))
+    m = m_dev[sl].double().cpu().numpy()
+    b = b_dev[sl].double().cpu().numpy()
+    rc = np.array(np.unravel_index(q["rec"], shape)).T
+    inside = np.all([(rc[:, a] >= lo[a]) & (rc[:, a] < lo[a] + crop[a]) for a in range(2)], axis=0)
+    rec = wl.flat(crop, rc[inside] - np.array(lo)) if inside.any() else wl.flat(crop, [[0, 0]])
+    src = wl.flat(crop, [[sx[a] - lo[a] for a in range(2)]])
+    obs = np.zeros((nt_s, len(rec)))
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.vd_superposition_gradient(m, b, q["dx"], q["dt"], nt_s, src, q["wavelet"][:nt_s], rec, obs, 1e-3)
+    el = time.perf_counter() - t0
+    upd = int(np.prod(crop)) * (2 * nt_s - 1)
+    return {"value": upd / el / 1e9, "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle (variable material), crop {'x'.join(map(str, crop))} around the source of "
+                      f"the same material, {len(rec)} receivers, nt={nt_s}, the two sweeps only "
+                      f"({upd:.3g} cell-updates in {el:.1f} s)"}
+
+
+def run_tato(args, np, torch, fdw, wl):
+    """One iteration of the two-dimensional acoustic black-hole design at the paper's
+    size: design map (filter r_f = 1.5, projection beta = 1, eta = 0.5, clip, the
+    air/solid map), forward sweep with the region objective, superposed backward sweep,
+    chain rule, Adam step (lr 0.1) with clip; everything on the device."""
+    from paper_2509_15744_amd import design as dz
+    q = wl.tato_2d(nt=args.nt or 17184)
+    nt = q["nt"]
+    shape = q["shape"]
+    mats = q["materials"]
+    material = fdw.two_material(mats["rho1"], mats["rho2"], mats["kappa1"], mats["kappa2"])
+    d = fdw.make_design(shape, q["design_origin"], q["design_extent"], fdw.FD_F32, material, 1.5, 1.0, 0.5,
+                        0.0, 1.0)
+    f32 = torch.float32
+    m = torch.full(shape, 1.0 / mats["kappa1"], dtype=f32, device="cuda")
+    b = torch.full(shape, 1.0 / mats["rho1"], dtype=f32, device="cuda")
+    rec = dz.region_receivers(shape, q["region_origin"], q["region_extent"])
+    obs = torch.zeros((nt, len(rec)), dtype=f32, device="cuda")
+    w = torch.as_tensor(q["wavelet"], dtype=f32, device="cuda")
+    variant = args.variant   # 0: the library's choice
+    prob = dz.DesignProblem(design=d, m=m, b=b, dx=q["dx"], src=q["src"], wavelet=w, rec=rec, observed=obs,
+                            dt=q["dt"], nt=nt, scale=dz.region_scale(len(rec)), acc_dtype=args.acc,
+                            variant=variant, chunk=args.chunk)
+    gamma0 = torch.full(q["design_extent"], 0.5, dtype=f32, device="cuda")
+    loop = dz.AdamDesign(prob, gamma0, lr=0.1)
+    desc = (f"tato2d {shape[0]}x{shape[1]} f32 order-2 air/solid design iteration nt={nt}, "
+            f"design box {q['design_extent'][0]}x{q['design_extent'][1]}, {len(rec)} region receivers")
+    log("workload:", desc, f"dt={q['dt']:.5g}")
+    timings, holder = [], {}
+
+    def one_step(record):
+        t = fdw.fd_timing()
+        loop.sweep_opts = {"timing": t}
+        holder["C"] = loop.step()
+        if record:
+            timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
+
+    elapsed = timed(args, torch, one_step)
+    ncell = shape[0] * shape[1]
+    upd = ncell * (2 * nt - 1)
+    launches = sum(t[1] + t[3] for t in timings)
+    kern_ms = sum(t[0] + t[2] for t in timings)
+    per_cell = gradient_bytes(nt, vd_step_bytes(args.acc), vd_step_bytes(args.acc))
+    bytes_all = ncell * per_cell * args.steps
+    cfg = {"workload": desc, "grid": list(shape), "nt": nt, "order": 2, "shots": 1, "receivers": len(rec),
+           "design_cells": int(np.prod(q["design_extent"])), "accumulator": args.acc,
+           "method": "superposition", "k": loop.k, "objective": holder["C"], "objective_history": loop.history,
+           "sweep_kernel_ms_per_step": kern_ms / args.steps,
+           "launch_shape": {"variant": variant, "chunk": args.chunk}, "cell_updates_per_step": upd}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, variable material, 2D crop) ...")
+        cfg["_cpu_baseline"] = cpu_baseline_vd2d({**q, "rec": rec}, m, b, wl)
+    return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, per_cell / (2 * nt - 1)), None, None, None
+
+
 def run_problems(args, np, torch, fdw, wl):
     """16 independent layered problems with sides drawn uniformly from 256..2048 (seeded),
     each with its own medium, dt, source at the top centre and receivers every 4 cells."""
@@ -482,7 +567,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="layered3d",
-                    choices=["layered3d", "layered2d", "shots3d", "shots2d", "problems2d", "vd3d"])
+                    choices=["layered3d", "layered2d", "shots3d", "shots2d", "problems2d", "vd3d", "tato2d"])
     ap.add_argument("--n", type=int, default=0, help="grid side (default: 1024 in 3D, 2048 in 2D)")
     ap.add_argument("--nt", type=int, default=0, help="time steps (default: 3000 in 3D, 4000 in 2D)")
     ap.add_argument("--acc", default="f64", choices=["f64", "f32"])
@@ -513,7 +598,7 @@ def main():
 
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    runner = {"problems2d": run_problems, "vd3d": run_vd}.get(args.workload, run_single)
+    runner = {"problems2d": run_problems, "vd3d": run_vd, "tato2d": run_tato}.get(args.workload, run_single)
     upd, elapsed, cfg, (bytes_launch, avg_ms, bpu), p0, c0, accuracy = runner(args, np, torch, fdw, wl)
     if accuracy is not None:
         log("accuracy: 256^3 gradients against the oracle references ...")
@@ -545,7 +630,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args),
-            "kernel": {"problems2d": "fdw::step_multi_kernel", "vd3d": "fdw::vd_step_kernel"}.get(
+            "kernel": {"problems2d": "fdw::step_multi_kernel", "vd3d": "fdw::vd_step_kernel",
+                       "tato2d": "fdw::vd_step_kernel"}.get(
                 args.workload, "fdw::step_kernel"),
             "avg_launch_ms": round(avg_ms, 4),
             "bytes_per_launch": bytes_launch,

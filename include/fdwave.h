@@ -230,7 +230,7 @@ int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, doub
  * of h_f (1/m_i + 1/sqrt(m_i m_j)): the Gershgorin bound of the leapfrog limit
  * dt^2 lambda_max(M^-1 K) < 4, equal to dt sqrt(d b/m) <= dx in a homogeneous medium
  * and local where materials mix.  Time axis, sources, receivers, shots
- * and misfit as for the constant-density calls.  fd_opts.variant: 0, 1 or 2;
+ * and misfit as for the constant-density calls.  fd_opts.variant: 0, 1 or 2 (2D also 4 or 5);
  * max_group is ignored (one wavefield per launch). */
 int fd_vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
                   int32_t nt, void* traces, const fd_opts* opts, void* stream);

@@ -792,11 +792,16 @@ int vd_setup(const fd_grid* grid, const fd_opts* opts, Geo* G)
     if (G->auto_variant) {
         G->variant = 1;   // one cell per lane: fits every extent and measured fastest
         G->auto_variant = false;
-    } else if (G->variant != 1 && G->variant != 2) {
-        return fail(FD_E_ARG, "the variable-material scheme runs tile variants 1 and 2");
+    } else if (G->variant != 1 && G->variant != 2 &&
+               !(G->ndim == 2 && (G->variant == 4 || G->variant == 5))) {
+        return fail(FD_E_ARG, "the variable-material scheme runs tile variants 1 and 2 (2D also 4 and 5)");
     }
     G->max_group = 1;
     G->variant_plain = 0;   // one launch shape for every launch
+    // In 2D a block's march along axis 0 reuses only two neighbour rows from
+    // registers while serialising its rows; two-row chunks keep the most blocks in
+    // flight and measured fastest (one row ties, longer chunks lose steadily).
+    if (G->ndim == 2 && G->chunk == 0) G->chunk = 2;
     return FD_OK;
 }
 

@@ -270,8 +270,10 @@ static hipError_t launch_vd_one(int nblk, const StepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-// The tile shapes of step variants 1 and 2 (one or two cells per lane), so the
-// block decomposition and event lists of a plan serve both kernels.
+// The tile shapes of the step variants (3D: 1 and 2, one or two cells per lane; 2D
+// also 4 and 5, rows of 128 x 2 and 256 cells, which keep more waves resident per
+// block than one 64-lane wavefront), so the block decomposition and event lists of a
+// plan serve both kernels.
 template <typename T, typename AT>
 static hipError_t launch_vd_rt(int ndim, int variant, int nblk, const StepArgs& a, hipStream_t s)
 {
@@ -281,6 +283,8 @@ static hipError_t launch_vd_rt(int ndim, int variant, int nblk, const StepArgs& 
     } else {
         if (variant == 1) return launch_vd_one<T, AT, 2, 64, 1, 1>(nblk, a, s);
         if (variant == 2) return launch_vd_one<T, AT, 2, 64, 1, 2>(nblk, a, s);
+        if (variant == 4) return launch_vd_one<T, AT, 2, 128, 1, 2>(nblk, a, s);
+        if (variant == 5) return launch_vd_one<T, AT, 2, 256, 1, 1>(nblk, a, s);
     }
     return hipErrorInvalidValue;
 }

@@ -107,10 +107,11 @@ class AdamDesign:
         self.grad_m = torch.empty_like(prob.m)
         self.grad_b = torch.empty_like(prob.m)
         self.history: list[float] = []
+        self.sweep_opts: dict = {}   # extra fd_opts fields for the two sweeps (e.g. timing)
 
     def _opts(self):
         p = self.prob
-        return dict(acc_dtype=p.acc_dtype, variant=p.variant, chunk=p.chunk)
+        return dict(acc_dtype=p.acc_dtype, variant=p.variant, chunk=p.chunk, **self.sweep_opts)
 
     def evaluate(self) -> float:
         """C at the current gamma and dC/dgamma into ``self.grad`` (no update)."""

@@ -326,3 +326,40 @@ def small_random(shape, order: int = 8, nt: int = 60, dtype: str = "f32", seed: 
     wavelet = rng.standard_normal((nt, nsrc))
     return Problem("random", tuple(shape), order, dtype, 1.0, dt, nt, c, c_ref, src, rec,
                    wavelet, meta={"courant": courant, "seed": seed})
+
+
+def sine_burst(nt: int, dt: float, freq: float, cycles: int, amp: float) -> np.ndarray:
+    """The sine burst of Eq. source2: amp sin(w t) sin^2(w t / (2 cycles)) for
+    0 <= t <= 2 pi cycles / w, zero after; w = 2 pi freq, t = n dt.  [nt]."""
+    t = np.arange(nt) * dt
+    w = 2.0 * np.pi * freq
+    s = amp * np.sin(w * t) * np.sin(w * t / (2 * cycles)) ** 2
+    s[t > 2.0 * np.pi * cycles / w] = 0.0
+    return s
+
+
+# Air and the solid of the topology-optimisation example (Sec. 2.3): densities and
+# bulk moduli (the solid's modulus as reduced in the paper for larger time steps).
+TATO_MATERIALS = dict(rho1=1.204, rho2=2643.0, kappa1=1.419e5, kappa2=6.87e8)
+
+
+def tato_2d(n0: int = 2703, n1: int = 5403, nt: int = 17184, dx: float = 1.0 / 300.0,
+            dt: float = 4.58e-6) -> dict:
+    """The two-dimensional acoustic black-hole problem at the paper's size (Tab.
+    problemsetupTopOpt: 18 m x 9 m, 5403 x 2703 grid points, N = 17184 steps,
+    dt ~ 4.58e-6 s, 5 kHz two-cycle sine burst of amplitude 1e2 s^-2).  The paper gives
+    the layout only as a figure; here: axis 1 (contiguous) is the 18 m side, the
+    source sits at mid-depth 3 m from the left wall, the design box covers 6..12 m by
+    1.5..7.5 m, and the objective region is a 0.5 m x 0.5 m box centred 14.75 m from the
+    left wall at mid-depth.  Returns host data: shape, dx, dt, nt, src, wavelet [nt, 1],
+    design box (origin, extent), region box (origin, extent), materials."""
+    shape = (n0, n1)
+    cells = lambda metres: int(round(metres / dx))   # noqa: E731
+    src = flat(shape, [[n0 // 2, cells(3.0)]])
+    origin = (cells(1.5), cells(6.0))
+    extent = (min(cells(6.0), n0 - origin[0]), min(cells(6.0), n1 - origin[1]))
+    r_ext = (cells(0.5), cells(0.5))
+    r_org = (n0 // 2 - r_ext[0] // 2, cells(14.75) - r_ext[1] // 2)
+    wavelet = sine_burst(nt, dt, 5000.0, 2, 1e2).reshape(nt, 1)
+    return dict(shape=shape, dx=dx, dt=dt, nt=nt, src=src, wavelet=wavelet, design_origin=origin,
+                design_extent=extent, region_origin=r_org, region_extent=r_ext, materials=dict(TATO_MATERIALS))

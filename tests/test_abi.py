@@ -127,8 +127,8 @@ def test_exact_validation(fdw):
 
 
 def test_vd_rejects_other_orders_and_variants(fdw):
-    """The variable-material scheme is second order and runs tile variants 1 and 2; both
-    are checked before any device work."""
+    """The variable-material scheme is second order and runs tile variants 1 and 2 (2D
+    also 4 and 5); both are checked before any device work."""
     a = fdw.fd_acq()
     J = ctypes.c_double()
     f = fdw.lib().fd_vd_adjoint_sensitivity
