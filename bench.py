@@ -548,6 +548,25 @@ def measured_traffic(args):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def copy_probe(torch, nbytes=1 << 30, reps=5):
+    """HBM rate of a plain device-to-device copy (read + write bytes counted) on the
+    current stream, timed with HIP events: what a streaming kernel with no reuse
+    reaches on this device, next to the 8 TB/s peak."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    del src, dst
+    return round(2.0 * nbytes * reps / (ms * 1e-3) / 1e9, 1)
+
+
 def timed(args, torch, one_step):
     for i in range(args.warmup):
         one_step(False)
@@ -636,6 +655,7 @@ def main():
             "avg_launch_ms": round(avg_ms, 4),
             "bytes_per_launch": bytes_launch,
             "bytes_per_shot_cell_update": bpu,
+            "copy_probe_gbs": copy_probe(torch),
         },
     }
     if accuracy is not None:

@@ -1621,6 +1621,34 @@ const char* fd_last_error(void) { return g_err.c_str(); }
 
 double fd_cfl_limit(int32_t ndim, int32_t order) { return cfl_limit(ndim, order); }
 
+size_t fd_workspace_bytes(const fd_grid* grid, const fd_acq* acq, int32_t nt, int32_t nshots)
+{
+    g_err.clear();
+    Geo G;
+    if (check_grid(grid, nullptr, &G)) return 0;
+    if (nt < 0) {
+        fail(FD_E_ARG, "nt is negative");
+        return 0;
+    }
+    const size_t es = dsize(G.dtype);
+    const size_t ns = nshots > 1 ? (size_t)nshots : 1;
+    const size_t nsrc = acq && acq->nsrc > 0 ? (size_t)acq->nsrc : 0;
+    const size_t nrec = acq && acq->nrec > 0 ? (size_t)acq->nrec : 0;
+    size_t bytes = 2 * ns * (size_t)G.ncell * es + (size_t)G.ncell * 8 + (size_t)nt * nrec * es;
+    // the largest block count of any tile variant with one plane per block
+    int64_t per_plane = 1;
+    for (int v = 1; v <= fdw::variant_count(G.ndim); ++v) {
+        const fdw::Variant w = fdw::variant_shape(G.ndim, v);
+        per_plane = std::max<int64_t>(per_plane, (int64_t)((G.n2 + w.tz - 1) / w.tz) * ((G.n1 + w.ty - 1) / w.ty));
+    }
+    const size_t nblk = (size_t)(per_plane * G.n0);
+    const size_t events = nsrc + nrec;
+    const size_t plan = (nblk + 1) * sizeof(int32_t) + events * (sizeof(fdw::Event) + sizeof(fdw::EvPlane)) +
+                        nrec * (sizeof(int64_t) + 3 * sizeof(int32_t)) + sizeof(int32_t) + 4096;
+    bytes += 2 * plan + sizeof(double) * (3 * fdw::kReduceBlocks + 16);
+    return bytes;
+}
+
 int32_t fd_variant_count(int32_t ndim)
 {
     return (ndim == 2 || ndim == 3) ? fdw::variant_count(ndim) : 0;

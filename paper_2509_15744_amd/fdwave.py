@@ -95,6 +95,7 @@ def _load():
     sig = {
         "fd_last_error": ([], ctypes.c_char_p),
         "fd_cfl_limit": ([I, I], D),
+        "fd_workspace_bytes": ([G, A, I, I], ctypes.c_size_t),
         "fd_variant_count": ([I], I),
         "fd_variant_info": ([I, I, _I32P, _I32P, _I32P, _I32P, _I32P], ctypes.c_int),
         "fd_forward": ([G, P, A, D, I, P, O, P], ctypes.c_int),
@@ -523,6 +524,19 @@ def fd_propagate(coef, u_prev, u_cur, nsteps, dx, order, **opts):
     _raise(_lib.fd_propagate(ctypes.byref(g), _dev(coef, "coef"), _dev(u_prev, "u_prev"),
                              _dev(u_cur, "u_cur"), int(nsteps), ctypes.byref(o), _stream()))
     return u_prev, u_cur
+
+
+def fd_workspace_bytes(shape, order, dtype_code, nt, nsrc=0, nrec=0, nshots=1, dx=1.0) -> int:
+    """Upper bound of the device bytes one fd_adjoint_sensitivity call takes from the
+    stream-ordered pool (see the header)."""
+    g = make_grid(shape, dx, order, dtype_code)
+    a = fd_acq()
+    a.nsrc = int(nsrc)
+    a.nrec = int(nrec)
+    n = _lib.fd_workspace_bytes(ctypes.byref(g), ctypes.byref(a), int(nt), int(nshots))
+    if n == 0:
+        raise FdError(FD_E_ARG, _lib.fd_last_error().decode())
+    return int(n)
 
 
 # ---- gradient-based design ---------------------------------------------------------

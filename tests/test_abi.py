@@ -209,3 +209,19 @@ def test_stable_dt_reduces_to_the_homogeneous_limit():
     from paper_2509_15744_amd import design as dz
     dt = dz.stable_dt((2.0, 0.0, 8.0, 0.0), 0.0, 1.0, 0.5, 2, frac=1.0)
     assert abs(dt - 0.5 / np.sqrt(2 * 8.0 / 2.0)) < 1e-15
+
+
+def test_workspace_bytes(fdw):
+    """fd_workspace_bytes covers the state arrays (two wavefields per shot, an f64
+    accumulator, the residual rows) plus small tables, grows with each input, and
+    rejects a bad grid."""
+    shape, nt, nrec = (64, 48, 80), 500, 300
+    n = 64 * 48 * 80
+    w = fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, nt, nsrc=2, nrec=nrec)
+    state = 2 * n * 4 + n * 8 + nt * nrec * 4
+    assert state < w < state * 1.1
+    assert fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, nt, nsrc=2, nrec=nrec, nshots=4) - w == 6 * n * 4
+    assert fdw.fd_workspace_bytes(shape, 8, fdw.FD_F64, nt, nsrc=2, nrec=nrec) > w
+    assert fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, 2 * nt, nsrc=2, nrec=nrec) - w == nt * nrec * 4
+    with pytest.raises(fdw.FdError):
+        fdw.fd_workspace_bytes((2, 2), 8, fdw.FD_F32, nt)
