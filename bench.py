@@ -529,21 +529,26 @@ def step_kernel_sha():
     return h.hexdigest()
 
 
-def measured_traffic(args):
-    """HBM bytes per accumulating step launch from the committed rocprofv3 counter record
-    of the default workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), or
-    None when this run is another workload or the kernel source changed since."""
+def measured_traffic(args, shape):
+    """HBM bytes per step launch from the committed rocprofv3 counter record of the
+    default workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), or None
+    when this run is another workload, runs other launch shapes than the record, or
+    the kernel source changed since."""
     if (args.workload != "layered3d" or args.n not in (0, 1024) or args.acc != "f64"
-            or args.method != "superposition"):
+            or args.method != "superposition" or not shape):
         return None
     rec = os.path.join(ROOT, "profiles", "step_kernel_layered3d_1024_traffic.md")
     try:
         fields = dict(ln.split(": ", 1) for ln in open(rec).read().splitlines()
-                      if ln.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+                      if ln.startswith(("traffic_bytes_per_launch:", "source_sha256:", "launch_shapes")))
         sha = step_kernel_sha()
     except (OSError, ValueError):
         return None
     if fields.get("source_sha256", "").strip() != sha:
+        return None
+    ran = [shape.get(k) for k in ("variant", "chunk", "variant_plain", "chunk_plain")]
+    recorded = [int(v) for v in fields.get("launch_shapes (variant chunk variant_plain chunk_plain)", "").split()]
+    if ran != recorded:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -648,7 +653,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args),
+            "traffic": measured_traffic(args, cfg.get("launch_shape")),
             "kernel": {"problems2d": "fdw::step_multi_kernel", "vd3d": "fdw::vd_step_kernel",
                        "tato2d": "fdw::vd_step_kernel"}.get(
                 args.workload, "fdw::step_kernel"),

@@ -297,10 +297,11 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
     } else {
         // split axis 0 so that the launch holds ~4M threads (several rounds of resident
         // blocks: a short last round leaves the chip idle), keeping chunks >= 16 r
-        // planes in 3D (each chunk re-reads 2r planes to fill its queue)
+        // planes in 3D (each chunk re-reads 2r planes to fill its queue); in 2D short
+        // chunks win (a block's march serialises its rows), down to 4 rows
         const int64_t want_blocks = ((int64_t)4 << 20) / v.threads;
         const int64_t want = (want_blocks + tiles - 1) / tiles;
-        const int min_chunk = G.ndim == 3 ? 16 * G.r : 2 * G.r;
+        const int min_chunk = G.ndim == 3 ? 16 * G.r : std::min(2 * G.r, 4);
         const int64_t maxch = std::max<int64_t>(1, G.n0 / min_chunk);
         const int64_t nch = std::max<int64_t>(1, std::min(want, maxch));
         P->chunk = (int)((G.n0 + nch - 1) / nch);
@@ -1185,6 +1186,8 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
     if (rc) return rc;
     if (!best) return fail(FD_E_ARG, "best is null");
     if (steps < 1) return fail(FD_E_ARG, "steps must be >= 1");
+    // small grids give launches of tens of microseconds: time more of them
+    steps *= (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 24) / std::max<int64_t>(G.ncell, 1)));
     nshot = std::max(nshot, 1);
     // candidate shapes: variants that fit, shot groups, chunk lengths
     std::vector<int> groups = {1};
@@ -1213,7 +1216,7 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
     // per shot-group size: the fastest shape of the launches that add kernel terms and,
     // separately, of the launches that touch no accumulator (the sweeps alternate them)
     struct Best { double ms = 1e300; int variant = 0, chunk = 0; };
-    std::map<int, Best> best_acc, best_plain;
+    std::map<int, Best> best_acc, best_plain, best_same;
     auto time_launches = [&](const Geo& T, const Plan& P, const Group& gr, fdw::StepArgs a, int terms,
                              double* ms_out) -> int {
         void *prev = ua, *cur = ub;
@@ -1265,6 +1268,8 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
                 if (ms_acc < ba.ms) ba = Best{ms_acc, variant, resolved};
                 Best& bp = best_plain[group];
                 if (ms_plain < bp.ms) bp = Best{ms_plain, variant, resolved};
+                Best& bs = best_same[group];
+                if (ms_acc + ms_plain < bs.ms) bs = Best{ms_acc + ms_plain, variant, resolved};
             }
         }
     }
@@ -1272,9 +1277,13 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
     double best_per_shot = 1e300;
     for (int group : groups) {
         if (!best_acc.count(group) || !best_plain.count(group)) continue;
-        const Best& ba = best_acc[group];
-        const Best& bp = best_plain[group];
-        const double per_pair = ba.ms + bp.ms;
+        // 2D: one shape for both launch kinds.  Separately timed shapes mispredict 2D
+        // sweeps (small grids whose launches share cache-resident data): real sweeps
+        // with a second shape for the plain launches ran up to 30% slower than with
+        // the accumulating launches' own shape.
+        const Best& ba = G.ndim == 3 ? best_acc[group] : best_same[group];
+        const Best& bp = G.ndim == 3 ? best_plain[group] : best_same[group];
+        const double per_pair = G.ndim == 3 ? ba.ms + bp.ms : ba.ms;
         if (per_pair / group < best_per_shot) {
             best_per_shot = per_pair / group;
             bestv.variant = ba.variant;

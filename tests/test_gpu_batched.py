@@ -193,3 +193,10 @@ def test_batched_rejects_mixed_orders(fdw):
     with pytest.raises(fdw.FdError) as e:
         fdw.fd_adjoint_sensitivity_batched(items)
     assert "same ndim, order and dtype" in str(e.value)
+
+
+def test_autotune_2d_keeps_one_shape(fdw):
+    """In 2D the tuner gives both launch kinds one shape (chosen by their summed time)."""
+    best, ms = fdw.fd_autotune((96, 130), 1.0, 8, torch.float32, nshot=1, steps=2)
+    assert best["variant_plain"] == best["variant"] and best["chunk_plain"] == best["chunk"]
+    assert ms > 0
