@@ -39,6 +39,7 @@ CASES = [
     ((14, 11, 70), (2, 3, 5), (9, 6, 41), 2.2, 1.0, 0.5, 0.0, 1.0, "two"),
     ((20, 33), (4, 1), (7, 31), 0.0, 0.0, 0.5, 1e-5, 1.0, "rho"),        # FWI form: no filter, no projection
     ((6, 5, 9), (1, 0, 2), (5, 5, 1), 1.5, 3.0, 0.5, 0.0, 1.0, "two"),   # one-cell-thin box
+    ((40, 50), (3, 4), (30, 40), 12.0, 2.0, 0.5, 0.0, 1.0, "two"),       # the appendix's radius 12
 ]
 
 
@@ -246,3 +247,23 @@ def test_design_error_paths(fdw):
         with pytest.raises(fdw.FdError):
             fdw.fd_adam_step(x, x, x.clone(), x.clone(), args["step"], args["lr"], args["beta1"], args["beta2"],
                              args["eps"])
+
+
+def test_design_loop_amplifies_with_negative_scale(fdw):
+    """The amplifying design (the paper's second example, signs of Eqs. cost2 and
+    adjointSource2 inverted): a negative scale makes the loop raise the region energy."""
+    from paper_2509_15744_amd import design as dz
+    p = _tato(fdw)
+    f64 = torch.float64
+    m = torch.full(p["shape"], p["background"][0], dtype=f64, device="cuda")
+    b = torch.full(p["shape"], p["background"][1], dtype=f64, device="cuda")
+    d = fdw.make_design(p["shape"], p["origin"], p["extent"], fdw.FD_F64, p["dmat"], p["rf"], p["beta"],
+                        p["eta"], p["lo"], p["hi"])
+    prob = dz.DesignProblem(design=d, m=m, b=b, dx=p["dx"], src=p["src"], wavelet=to_dev(p["w"], f64),
+                            rec=p["rec"], observed=torch.zeros((p["nt"], len(p["rec"])), dtype=f64, device="cuda"),
+                            dt=p["dt"], nt=p["nt"], scale=dz.region_scale(len(p["rec"]), maximize=True))
+    loop = dz.AdamDesign(prob, torch.full(p["extent"], 0.5, dtype=f64, device="cuda"), lr=0.1)
+    say("design loop ascent")
+    hist = [loop.step() for _ in range(5)]
+    assert all(h < 0 for h in hist)
+    assert hist[-1] < hist[0], hist        # -C decreases: the region energy grows
