@@ -159,8 +159,8 @@ double fd_cfl_limit(int32_t ndim, int32_t order);
  * caller's inputs and outputs (host-side arithmetic, no device work):
  *   wavefields 2 * nshots * ncell * sizeof(T), accumulator ncell * 8 (f64, the larger
  *   choice), residual rows nt * nrec * sizeof(T), event tables of two launch plans
- *   (bounded with the smallest tile and one plane per block) and the reduction
- *   partials.  acq may be NULL (no sources or receivers); nshots < 1 counts as 1.
+ *   (per-block offsets for every shot group, bounded with the smallest tile and one
+ *   plane per block) and the reduction partials.  acq may be NULL (no sources or receivers); nshots < 1 counts as 1.
  * Returns 0 and sets fd_last_error on an invalid grid or a negative nt.  The split
  * halves take the same amount less the caller-owned fd_state arrays. */
 size_t fd_workspace_bytes(const fd_grid* grid, const fd_acq* acq, int32_t nt, int32_t nshots);

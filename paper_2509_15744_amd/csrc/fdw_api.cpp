@@ -1652,7 +1652,9 @@ size_t fd_workspace_bytes(const fd_grid* grid, const fd_acq* acq, int32_t nt, in
     }
     const size_t nblk = (size_t)(per_plane * G.n0);
     const size_t events = nsrc + nrec;
-    const size_t plan = (nblk + 1) * sizeof(int32_t) + events * (sizeof(fdw::Event) + sizeof(fdw::EvPlane)) +
+    // each shot group of a plan has its own block offsets (at most one group per shot)
+    const size_t plan = ns * ((nblk + 1) * sizeof(int32_t) + 256) +
+                        events * (sizeof(fdw::Event) + sizeof(fdw::EvPlane)) +
                         nrec * (sizeof(int64_t) + 3 * sizeof(int32_t)) + sizeof(int32_t) + 4096;
     bytes += 2 * plan + sizeof(double) * (3 * fdw::kReduceBlocks + 16);
     return bytes;
