@@ -471,6 +471,70 @@ def run_tato(args, np, torch, fdw, wl):
     return upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, per_cell / (2 * nt - 1)), None, None, None
 
 
+def run_autograd(args, np, torch, fdw, wl):
+    """The differentiation workload (smooth speed in [1, 3], 256^3, order 8, nt 2000,
+    f32): one timed step = J(c) through the autograd Function and .backward() (the
+    forward sweep, then the superposed backward sweep as the hand-written backward),
+    next to fd_adjoint_sensitivity on the same problem (the plain single-shot call) and
+    the two gradients' relative difference."""
+    from paper_2509_15744_amd import autograd, calibrate
+    n = args.n or 256
+    nt = args.nt or 2000
+    p = wl.smooth_3d(n=n, nt=nt)
+    f32 = torch.float32
+    c = torch.as_tensor(p.c, dtype=f32, device="cuda")
+    w = torch.as_tensor(p.wavelet, dtype=f32, device="cuda")
+    obs = torch.as_tensor(p.observed, dtype=f32, device="cuda")
+    tr = fdw.fd_forward(c, p.dx, p.order, p.src, w, p.rec, p.dt, nt)
+    J0 = fdw.fd_misfit(tr, obs, p.dt)
+    k = calibrate.auto_k(J0, p.dt, float(np.linalg.norm(p.wavelet)), p.dx, 3, args.beta)
+    shape = None
+    if not args.variant:   # tune once; both paths then take the tuned shape (variant 0)
+        shape, _ = fdw.fd_autotune(p.shape, p.dx, p.order, torch.float32, steps=4, acc_dtype=args.acc)
+        log("launch shape:", shape)
+    prob = autograd.SensProblem(dx=p.dx, order=p.order, src=p.src, rec=p.rec, wavelet=w, observed=obs, dt=p.dt,
+                                nt=nt, acc_dtype=args.acc, variant=args.variant, chunk=args.chunk)
+    desc = f"autograd3d {n}^3 f32 order-{p.order} nt={nt}, smooth speed in [1, 3], {len(p.rec)} receivers"
+    log("workload:", desc, f"dt={p.dt:.5g}")
+    holder = {}
+
+    def one_step(record):
+        cg = c.clone().requires_grad_(True)
+        J = autograd.misfit(cg, prob, k)
+        J.backward()
+        holder["grad"] = cg.grad
+        holder["J"] = float(J.item())
+
+    elapsed = timed(args, torch, one_step)
+    ncell = n ** 3
+    upd = ncell * (2 * nt - 1)
+    # the plain call on the same problem: wall time and the step kernel's launch record
+    grad = torch.empty_like(c)
+    timings = []
+    for rec in (False, True):
+        t = fdw.fd_timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fdw.fd_adjoint_sensitivity(c, p.dx, p.order, p.src, w, p.rec, p.dt, nt, obs, k, grad=grad, timing=t,
+                                   acc_dtype=args.acc, variant=args.variant, chunk=args.chunk)
+        torch.cuda.synchronize()
+        if rec:
+            plain_s = time.perf_counter() - t0
+            timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
+    g_ag = holder["grad"].double()
+    diff = float(torch.linalg.vector_norm(g_ag - grad.double()) / torch.linalg.vector_norm(grad.double()))
+    launches = sum(t[1] + t[3] for t in timings)
+    kern_ms = sum(t[0] + t[2] for t in timings)
+    per_cell = gradient_bytes(nt, step_bytes(1, args.acc), step_bytes(1, args.acc))
+    cfg = {"workload": desc, "grid": [n, n, n], "nt": nt, "order": p.order, "shots": 1, "receivers": len(p.rec),
+           "accumulator": args.acc, "k": k, "J": holder["J"],
+           "plain_call_gcell_updates_per_s": upd / plain_s / 1e9,
+           "autograd_over_plain_time": (elapsed / args.steps) / plain_s,
+           "grad_rel_diff_autograd_vs_plain": diff, "launch_shape": shape, "cell_updates_per_step": upd}
+    return upd, elapsed, cfg, (ncell * per_cell / launches, kern_ms / launches, per_cell / (2 * nt - 1)), \
+        None, None, None
+
+
 def run_problems(args, np, torch, fdw, wl):
     """16 independent layered problems with sides drawn uniformly from 256..2048 (seeded),
     each with its own medium, dt, source at the top centre and receivers every 4 cells."""
@@ -591,7 +655,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="layered3d",
-                    choices=["layered3d", "layered2d", "shots3d", "shots2d", "problems2d", "vd3d", "tato2d"])
+                    choices=["layered3d", "layered2d", "shots3d", "shots2d", "problems2d", "vd3d", "tato2d",
+                             "autograd3d"])
     ap.add_argument("--n", type=int, default=0, help="grid side (default: 1024 in 3D, 2048 in 2D)")
     ap.add_argument("--nt", type=int, default=0, help="time steps (default: 3000 in 3D, 4000 in 2D)")
     ap.add_argument("--acc", default="f64", choices=["f64", "f32"])
@@ -622,7 +687,8 @@ def main():
 
     torch.cuda.set_device(0)
     t_setup = time.perf_counter()
-    runner = {"problems2d": run_problems, "vd3d": run_vd, "tato2d": run_tato}.get(args.workload, run_single)
+    runner = {"problems2d": run_problems, "vd3d": run_vd, "tato2d": run_tato,
+              "autograd3d": run_autograd}.get(args.workload, run_single)
     upd, elapsed, cfg, (bytes_launch, avg_ms, bpu), p0, c0, accuracy = runner(args, np, torch, fdw, wl)
     if accuracy is not None:
         log("accuracy: 256^3 gradients against the oracle references ...")
