@@ -363,3 +363,45 @@ def tato_2d(n0: int = 2703, n1: int = 5403, nt: int = 17184, dx: float = 1.0 / 3
     wavelet = sine_burst(nt, dt, 5000.0, 2, 1e2).reshape(nt, 1)
     return dict(shape=shape, dx=dx, dt=dt, nt=nt, src=src, wavelet=wavelet, design_origin=origin,
                 design_extent=extent, region_origin=r_org, region_extent=r_ext, materials=dict(TATO_MATERIALS))
+
+
+def fwi_3d(n0: int = 976, n1: int = 503, n2: int = 503, nt: int = 7200, dt: float = 9e-9, seed: int = 11,
+           n_voids: int = 24, rec_every: int = 8, device=None) -> dict:
+    """A stand-in for the paper's three-dimensional FWI specimen at its size (Tab.
+    problemsetupFWI: 0.05 m x 0.05 m x 0.0973 m, 503 x 503 x 976 grid points, N = 7200,
+    dt = 9e-9 s, 2 MHz two-cycle sine burst of 1e12, rho-scaling with rho0 = 2700,
+    c0 = 6000).  The CT scan is not available: the true indicator is a solid cylinder
+    along axis 0 (radius 0.45 of the side, gamma = 1, void gamma = 1e-5 outside) holding
+    ``n_voids`` seeded spherical voids (radius 6..20 cells, less on small grids) and the paper's added
+    16 x 16 x 16 cubical void at the centre; the starting design is the cylinder without
+    voids.  Source at the centre of the top face (x0 = 0), receivers on the top and
+    bottom faces every ``rec_every`` cells.  gamma fields are float32 on ``device``."""
+    import torch
+    shape = (n0, n1, n2)
+    dx = 0.05 / n1
+    rng = np.random.default_rng(seed)
+    y = torch.arange(n1, device=device, dtype=torch.float32).view(1, n1, 1) - (n1 - 1) / 2
+    z = torch.arange(n2, device=device, dtype=torch.float32).view(1, 1, n2) - (n2 - 1) / 2
+    inside = (y * y + z * z) <= (0.45 * n1) ** 2
+    eps = 1e-5
+    start = torch.where(inside, 1.0, eps).expand(shape).contiguous()
+    true = start.clone()
+    x = torch.arange(n0, device=device, dtype=torch.float32).view(n0, 1, 1)
+    r_hi = min(20.0, 0.15 * n1)
+    for _ in range(n_voids):
+        r = float(rng.uniform(min(6.0, r_hi / 2), r_hi))
+        cx = float(rng.uniform(r, n0 - r))
+        ang, rad = rng.uniform(0, 2 * np.pi), rng.uniform(0, 0.45 * n1 - r)
+        cy, cz = rad * np.cos(ang), rad * np.sin(ang)
+        ball = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= r * r
+        true = torch.where(ball, eps, true)
+    c0, c1, c2 = n0 // 2, n1 // 2, n2 // 2
+    true[c0 - 8:c0 + 8, c1 - 8:c1 + 8, c2 - 8:c2 + 8] = eps
+    src = flat(shape, [[0, c1, c2]])
+    h = rec_every // 2
+    face = [[a, rec_every * i + h, rec_every * j + h] for a in (0, n0 - 1)
+            for i in range(n1 // rec_every) for j in range(n2 // rec_every)]
+    rec = flat(shape, face)
+    wavelet = sine_burst(nt, dt, 2e6, 2, 1e12).reshape(nt, 1)
+    return dict(shape=shape, dx=dx, dt=dt, nt=nt, src=src, rec=rec, wavelet=wavelet, gamma_true=true.contiguous(),
+                gamma_start=start, rho0=2700.0, c0=6000.0, eps=eps)

@@ -152,6 +152,29 @@ def _fwi(fdw):
                 background=(0.0, 0.0))
 
 
+def _fwi3d(fdw):
+    """The 3D FWI form on a small grid: rho-scaling on the whole grid, a void ball in the
+    true medium, receivers on the top and bottom faces."""
+    from paper_2509_15744_amd import design as dz
+    shape, dx = (16, 14, 20), 1e-4
+    mat = od.rho_scaling(2700.0, 6000.0)
+    dmat = fdw.rho_scaling(2700.0, 6000.0)
+    dt = dz.stable_dt(dmat, 1e-5, 1.0, dx, 3)
+    nt = 120
+    src = np.array([7 * shape[2] + 10], dtype=np.int64)
+    w = _sine_burst(nt, dt, 6000.0 / (12 * dx), 2, 1e12)
+    face = [(a * shape[1] + i) * shape[2] + j for a in (0, shape[0] - 1)
+            for i in range(0, shape[1], 2) for j in range(0, shape[2], 2)]
+    rec = np.array(face, dtype=np.int64)
+    x, y, z = np.indices(shape)
+    true = np.ones(shape)
+    true[(x - 9) ** 2 + (y - 6) ** 2 + (z - 9) ** 2 <= 9] = 1e-5
+    tr, _, _ = oracle.vd_forward(true * 2700.0, true * 2700.0 * 6000.0 ** 2, dx, dt, nt, src, w, rec)
+    return dict(shape=shape, dx=dx, origin=(0, 0, 0), extent=shape, mat=mat, dmat=dmat, dt=dt, nt=nt, src=src,
+                w=w, rec=rec, scale=1.0, oscale=1.0, rf=0.0, beta=0.0, eta=0.5, lo=1e-5, hi=1.0, obs=tr,
+                background=(0.0, 0.0))
+
+
 def _oracle_loop(p, gamma0, k, iters, lr):
     shape, box = p["shape"], _box(p["origin"], p["extent"])
     obs = p["obs"] if p["obs"] is not None else np.zeros((p["nt"], len(p["rec"])))
@@ -172,12 +195,12 @@ def _oracle_loop(p, gamma0, k, iters, lr):
     return out
 
 
-@pytest.mark.parametrize("setup", ["tato", "fwi"])
+@pytest.mark.parametrize("setup", ["tato", "fwi", "fwi3d"])
 def test_design_loop_matches_oracle_loop(fdw, setup):
     """Three Adam iterations of the device loop equal the same loop built from the
     oracle's pieces at the same k (f64): objective and design field after each."""
     from paper_2509_15744_amd import design as dz
-    p = _tato(fdw) if setup == "tato" else _fwi(fdw)
+    p = {"tato": _tato, "fwi": _fwi, "fwi3d": _fwi3d}[setup](fdw)
     rng = np.random.default_rng(30)
     gamma0 = (0.5 + 0.1 * rng.standard_normal(p["extent"])).clip(0, 1) if setup == "tato" else np.ones(p["extent"])
     f64 = torch.float64
