@@ -478,9 +478,11 @@ def run_fwi(args, np, torch, fdw, wl):
     sweep against traces of the voided specimen, superposed backward sweep, chain rule,
     Adam step (lr 0.2, the paper's alpha)."""
     from paper_2509_15744_amd import design as dz
-    q = wl.fwi_3d(nt=args.nt or 7200, device="cuda")
+    q = wl.fwi_3d(nt=args.nt or 7200, device="cuda", **({"n1": args.n, "n2": args.n} if args.n else {}))
     shape, nt = q["shape"], q["nt"]
     material = fdw.rho_scaling(q["rho0"], q["c0"])
+    # the paper's dt unless a design could break the per-cell stability bound at it
+    q["dt"] = min(q["dt"], dz.stable_dt(material, q["eps"], 1.0, q["dx"], 3))
     d = fdw.make_design(shape, (0, 0, 0), shape, fdw.FD_F32, material, 0.0, 0.0, 0.5, q["eps"], 1.0)
     f32 = torch.float32
     m = torch.empty(shape, dtype=f32, device="cuda")

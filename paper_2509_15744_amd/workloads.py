@@ -366,7 +366,7 @@ def tato_2d(n0: int = 2703, n1: int = 5403, nt: int = 17184, dx: float = 1.0 / 3
 
 
 def fwi_3d(n0: int = 976, n1: int = 503, n2: int = 503, nt: int = 7200, dt: float = 9e-9, seed: int = 11,
-           n_voids: int = 24, rec_every: int = 8, device=None) -> dict:
+           n_voids: int = 24, rec_every: int = 8, dx: float = 0.05 / 503, device=None) -> dict:
     """A stand-in for the paper's three-dimensional FWI specimen at its size (Tab.
     problemsetupFWI: 0.05 m x 0.05 m x 0.0973 m, 503 x 503 x 976 grid points, N = 7200,
     dt = 9e-9 s, 2 MHz two-cycle sine burst of 1e12, rho-scaling with rho0 = 2700,
@@ -375,10 +375,10 @@ def fwi_3d(n0: int = 976, n1: int = 503, n2: int = 503, nt: int = 7200, dt: floa
     ``n_voids`` seeded spherical voids (radius 6..20 cells, less on small grids) and the paper's added
     16 x 16 x 16 cubical void at the centre; the starting design is the cylinder without
     voids.  Source at the centre of the top face (x0 = 0), receivers on the top and
-    bottom faces every ``rec_every`` cells.  gamma fields are float32 on ``device``."""
+    bottom faces every ``rec_every`` cells; cells of the paper's size (0.05 m / 503)
+    whatever the extents.  gamma fields are float32 on ``device``."""
     import torch
     shape = (n0, n1, n2)
-    dx = 0.05 / n1
     rng = np.random.default_rng(seed)
     y = torch.arange(n1, device=device, dtype=torch.float32).view(1, n1, 1) - (n1 - 1) / 2
     z = torch.arange(n2, device=device, dtype=torch.float32).view(1, 1, n2) - (n2 - 1) / 2
