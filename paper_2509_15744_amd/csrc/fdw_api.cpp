@@ -84,6 +84,8 @@ struct Geo {
     int chunk_plain = 0;        //   and planes per block (0: library choice)
     int n0, n1, n2;      // internal extents (2D: n1 = 1)
     int64_t ncell;
+    int pitch = 0;       // row stride of the library's own arrays (>= n2; see vd_setup)
+    int64_t ncell_pad = 0;   // n0 * n1 * pitch: elements of one such array
     double dx, inv_vol;
 };
 
@@ -138,6 +140,8 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
     if (g->ndim == 3) { G.n1 = (int)n[1]; G.n2 = (int)n[2]; }
     else { G.n1 = 1; G.n2 = (int)n[1]; }
     G.ncell = n[0] * n[1] * n[2];
+    G.pitch = G.n2;
+    G.ncell_pad = G.ncell;
     G.dx = g->dx;
     G.inv_vol = 1.0 / std::pow(g->dx, (double)g->ndim);
     *out = G;
@@ -410,7 +414,8 @@ int make_plan(Geo& G, const fd_acq* acq, bool want_uniq, hipStream_t s, Scratch&
         for (int i = 0; i < nrec; ++i) {
             if (i == 0 || rc[i].cell != rc[i - 1].cell) {
                 if (i) uoff.push_back(i);
-                ucell.push_back(rc[i].cell);
+                // index into the library's arrays, whose rows may be padded
+                ucell.push_back(rc[i].cell / G.n2 * G.pitch + rc[i].cell % G.n2);
             }
             uidx.push_back(rc[i].idx);
             ushot.push_back(rc[i].shot);
@@ -461,6 +466,7 @@ fdw::StepArgs base_args(const Geo& G, const Plan& P, const void* c, double dt)
     a.c = c;
     a.shot_stride = G.ncell;
     a.n0 = G.n0; a.n1 = G.n1; a.n2 = G.n2;
+    a.pitch = G.pitch;
     const double* w = weights(2 * G.r);
     for (int j = 0; j < G.r; ++j) a.w[j] = w[j] / (G.dx * G.dx);
     a.dt2 = dt * dt;
@@ -577,11 +583,11 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
                   const void* obs, void* ua, void* ub, void* acc, void* resid, void* traces,
                   hipStream_t s, const VdFields& vd = VdFields())
 {
-    const size_t fb = G.ncell * dsize(G.dtype) * nshots(acq);
+    const size_t fb = G.ncell_pad * dsize(G.dtype) * nshots(acq);
     HIPCHK(hipMemsetAsync(ua, 0, fb, s));
     HIPCHK(hipMemsetAsync(ub, 0, fb, s));
-    if (acc) HIPCHK(hipMemsetAsync(acc, 0, G.ncell * dsize(G.acc_dtype), s));
-    if (vd.acc_b) HIPCHK(hipMemsetAsync(vd.acc_b, 0, G.ncell * dsize(G.acc_dtype), s));
+    if (acc) HIPCHK(hipMemsetAsync(acc, 0, G.ncell_pad * dsize(G.acc_dtype), s));
+    if (vd.acc_b) HIPCHK(hipMemsetAsync(vd.acc_b, 0, G.ncell_pad * dsize(G.acc_dtype), s));
     fdw::StepArgs a = base_args(G, P, c, dt);
     a.acc = acc;
     a.stiff = vd.stiff;
@@ -599,8 +605,8 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
     tm.start();
     for (int gi = 0; gi < (int)P.groups.size(); ++gi) {
         const Group& gr = P.groups[gi];
-        char* prev = (char*)ua + (size_t)gr.g0 * G.ncell * es;   // level n-1
-        char* cur = (char*)ub + (size_t)gr.g0 * G.ncell * es;    // level n
+        char* prev = (char*)ua + (size_t)gr.g0 * G.ncell_pad * es;   // level n-1
+        char* cur = (char*)ub + (size_t)gr.g0 * G.ncell_pad * es;    // level n
         for (int n = 0; n < nt; ++n) {
             a.ucur = cur;
             a.unew = prev;
@@ -651,11 +657,11 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
     SweepTimer tm(G.timing != nullptr && nt > 1, s);
     for (size_t gi = 0; gi < P.groups.size(); ++gi) {
         const Group& gr = P.groups[gi];
-        char* vj = (char*)up + (size_t)gr.g0 * G.ncell * es;   // v^j
-        char* vn = (char*)ul + (size_t)gr.g0 * G.ncell * es;   // v^{j+1}, overwritten by v^{j-1}
+        char* vj = (char*)up + (size_t)gr.g0 * G.ncell_pad * es;   // v^j
+        char* vn = (char*)ul + (size_t)gr.g0 * G.ncell_pad * es;   // v^{j+1}, overwritten by v^{j-1}
         if (acq->nrec > 0)
             HIPCHK(fdw::launch_terminal(G.dtype, G.acc_dtype, P.nuniq, P.d_ucell, P.d_uoff, P.d_uidx,
-                                        P.d_ushot, gr.g0, gr.size, G.ncell, c, vd.stiff ? 1 : 0,
+                                        P.d_ushot, gr.g0, gr.size, G.ncell_pad, c, vd.stiff ? 1 : 0,
                                         dt * dt, vn, vj, acc,
                                         (const char*)resid + (size_t)(nt - 1) * acq->nrec * es,
                                         rec_scale, s));
@@ -803,6 +809,45 @@ int vd_setup(const fd_grid* grid, const fd_opts* opts, Geo* G)
     // registers while serialising its rows; two-row chunks keep the most blocks in
     // flight and measured fastest (one row ties, longer chunks lose steadily).
     if (G->ndim == 2 && G->chunk == 0) G->chunk = 2;
+    // Rows that do not start on 256-byte boundaries cost about a third of the
+    // throughput (each 64-lane row load touches three cache lines instead of two):
+    // the sweeps run on copies whose rows are padded to 64 elements.
+    const int pitch = (G->n2 + 63) / 64 * 64;
+    if (pitch != G->n2 && (int64_t)G->n1 * pitch < ((int64_t)1 << 31)) {
+        G->pitch = pitch;
+        G->ncell_pad = (int64_t)G->n0 * G->n1 * pitch;
+    }
+    return FD_OK;
+}
+
+// Copy `rows` rows of n2 elements between arrays with row strides dpitch and spitch.
+int copy_rows(void* dst, int64_t dpitch, const void* src, int64_t spitch, size_t es, int64_t rows, int64_t n2,
+              hipStream_t s)
+{
+    if (rows == 0) return FD_OK;
+    HIPCHK(hipMemcpy2DAsync(dst, (size_t)dpitch * es, src, (size_t)spitch * es, (size_t)n2 * es, (size_t)rows,
+                            hipMemcpyDeviceToDevice, s));
+    return FD_OK;
+}
+
+// The material of a sweep in the library's row layout: the caller's arrays when rows
+// are not padded, else padded copies.
+int padded_material(const Geo& G, const void* m, const void* b, Scratch& sc, hipStream_t s, const void** mp,
+                    const void** bp)
+{
+    *mp = m;
+    *bp = b;
+    if (G.pitch == G.n2) return FD_OK;
+    const size_t es = dsize(G.dtype);
+    const int64_t rows = (int64_t)G.n0 * G.n1;
+    void *pm = nullptr, *pb = nullptr;
+    HIPCHK(sc.get(&pm, G.ncell_pad * es));
+    HIPCHK(sc.get(&pb, G.ncell_pad * es));
+    int rc;
+    if ((rc = copy_rows(pm, G.pitch, m, G.n2, es, rows, G.n2, s))) return rc;
+    if ((rc = copy_rows(pb, G.pitch, b, G.n2, es, rows, G.n2, s))) return rc;
+    *mp = pm;
+    *bp = pb;
     return FD_OK;
 }
 
@@ -828,6 +873,37 @@ int check_vd_state(const fd_state* st, const void* acc_b, const Geo& G, int nt, 
     return check_dev(acc_b, G.ncell * dsize(G.acc_dtype), "acc_b");
 }
 
+// The sweep state in the library's row layout.  With padded rows and a caller-owned
+// (dense) state, the sweeps work on padded copies: the forward half hands the final
+// levels and both accumulators back to the caller's arrays, the backward half starts
+// by copying them in.  Internal states (own_state) are allocated padded.
+struct VdWork {
+    fd_state st{};
+    void* acc_b = nullptr;
+    bool copied = false;
+};
+
+int vd_work(const Geo& G, const fd_state* st, void* acc_b, int ns, bool own_state, bool copy_in, Scratch& sc,
+            hipStream_t s, VdWork* w)
+{
+    w->st = *st;
+    w->acc_b = acc_b;
+    if (G.pitch == G.n2 || own_state) return FD_OK;
+    const size_t es = dsize(G.dtype), aes = dsize(G.acc_dtype);
+    HIPCHK(sc.get(&w->st.u_a, G.ncell_pad * es * ns));
+    HIPCHK(sc.get(&w->st.u_b, G.ncell_pad * es * ns));
+    HIPCHK(sc.get(&w->st.acc, G.ncell_pad * aes));
+    HIPCHK(sc.get(&w->acc_b, G.ncell_pad * aes));
+    w->copied = true;
+    if (!copy_in) return FD_OK;
+    const int64_t rows = (int64_t)G.n0 * G.n1;
+    int rc;
+    if ((rc = copy_rows(w->st.u_a, G.pitch, st->u_a, G.n2, es, rows * ns, G.n2, s))) return rc;
+    if ((rc = copy_rows(w->st.u_b, G.pitch, st->u_b, G.n2, es, rows * ns, G.n2, s))) return rc;
+    if ((rc = copy_rows(w->st.acc, G.pitch, st->acc, G.n2, aes, rows, G.n2, s))) return rc;
+    return copy_rows(w->acc_b, G.pitch, acc_b, G.n2, aes, rows, G.n2, s);
+}
+
 // First half: forward sweep with cost, adjoint force and both kernel terms of u.
 int vd_sens_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt, int nt,
                     const void* observed, const fd_state* st, void* acc_b, void* traces, double* J_host,
@@ -842,14 +918,27 @@ int vd_sens_forward(const fd_grid* grid, const void* m, const void* b, const fd_
     if (traces && (rc = check_dev(traces, tb, "traces"))) return rc;
     Scratch sc(s);
     if ((rc = check_material(G, m, b, dt, s, sc))) return rc;
+    const void *mp = nullptr, *bp = nullptr;
+    if ((rc = padded_material(G, m, b, sc, s, &mp, &bp))) return rc;
     Plan P;
     if ((rc = make_plan(G, acq, false, s, sc, &P))) return rc;
+    const int ns = nshots(acq);
+    VdWork w;
+    if ((rc = vd_work(G, st, acc_b, ns, own_state, false, sc, s, &w))) return rc;
     VdFields vd;
-    vd.stiff = b;
-    vd.acc_b = acc_b;
-    if ((rc = forward_sweep(G, P, m, acq, dt, nt, observed, st->u_a, st->u_b, st->acc, st->residual, traces,
+    vd.stiff = bp;
+    vd.acc_b = w.acc_b;
+    if ((rc = forward_sweep(G, P, mp, acq, dt, nt, observed, w.st.u_a, w.st.u_b, w.st.acc, st->residual, traces,
                             s, vd)))
         return rc;
+    if (w.copied) {   // hand the state back in the caller's dense layout
+        const size_t es = dsize(G.dtype), aes = dsize(G.acc_dtype);
+        const int64_t rows = (int64_t)G.n0 * G.n1;
+        if ((rc = copy_rows(st->u_a, G.n2, w.st.u_a, G.pitch, es, rows * ns, G.n2, s))) return rc;
+        if ((rc = copy_rows(st->u_b, G.n2, w.st.u_b, G.pitch, es, rows * ns, G.n2, s))) return rc;
+        if ((rc = copy_rows(st->acc, G.n2, w.st.acc, G.pitch, aes, rows, G.n2, s))) return rc;
+        if ((rc = copy_rows(acc_b, G.n2, w.acc_b, G.pitch, aes, rows, G.n2, s))) return rc;
+    }
     if (J_host) {
         double ss = 0.0;
         if ((rc = misfit_sum(G.dtype, st->residual, nullptr, nullptr, (int64_t)nt * acq->nrec, s, sc, &ss)))
@@ -877,16 +966,32 @@ int vd_sens_backward(const fd_grid* grid, const void* m, const void* b, const fd
     if ((rc = check_dev(grad_m, G.ncell * es, "grad_m"))) return rc;
     if ((rc = check_dev(grad_b, G.ncell * es, "grad_b"))) return rc;
     Scratch sc(s);
+    const void *mp = nullptr, *bp = nullptr;
+    if ((rc = padded_material(G, m, b, sc, s, &mp, &bp))) return rc;
     Plan P;
     if ((rc = make_plan(G, acq, true, s, sc, &P))) return rc;
+    VdWork w;
+    if ((rc = vd_work(G, st, acc_b, nshots(acq), own_state, true, sc, s, &w))) return rc;
     VdFields vd;
-    vd.stiff = b;
-    vd.acc_b = acc_b;
-    if ((rc = backward_sweep(G, P, m, acq, dt, nt, k, st->u_a, st->u_b, st->acc, st->residual, s, vd)))
+    vd.stiff = bp;
+    vd.acc_b = w.acc_b;
+    if ((rc = backward_sweep(G, P, mp, acq, dt, nt, k, w.st.u_a, w.st.u_b, w.st.acc, st->residual, s, vd)))
         return rc;
-    HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, st->acc, grad_scale * 0.5 / k, grad_m, s));
-    HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, acc_b, -grad_scale * dt * dt / (G.dx * G.dx) * 0.5 / k,
-                             grad_b, s));
+    const double sm = grad_scale * 0.5 / k;
+    const double sb = -grad_scale * dt * dt / (G.dx * G.dx) * 0.5 / k;
+    if (G.pitch == G.n2) {
+        HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, w.st.acc, sm, grad_m, s));
+        HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell, w.acc_b, sb, grad_b, s));
+    } else {   // scale in the padded layout, then copy the rows out
+        void *tm = nullptr, *tbuf = nullptr;
+        HIPCHK(sc.get(&tm, G.ncell_pad * es));
+        HIPCHK(sc.get(&tbuf, G.ncell_pad * es));
+        HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell_pad, w.st.acc, sm, tm, s));
+        HIPCHK(fdw::launch_scale(G.dtype, G.acc_dtype, G.ncell_pad, w.acc_b, sb, tbuf, s));
+        const int64_t rows = (int64_t)G.n0 * G.n1;
+        if ((rc = copy_rows(grad_m, G.n2, tm, G.pitch, es, rows, G.n2, s))) return rc;
+        if ((rc = copy_rows(grad_b, G.n2, tbuf, G.pitch, es, rows, G.n2, s))) return rc;
+    }
     HIPCHK(hipStreamSynchronize(s));
     return FD_OK;
 }
@@ -904,10 +1009,10 @@ int vd_gradient(const fd_grid* grid, const void* m, const void* b, const fd_acq*
     const int ns = nshots(acq);
     fd_state st;
     void* accb = nullptr;
-    HIPCHK(sc.get(&st.u_a, G.ncell * es * ns));
-    HIPCHK(sc.get(&st.u_b, G.ncell * es * ns));
-    HIPCHK(sc.get(&st.acc, G.ncell * dsize(G.acc_dtype)));
-    HIPCHK(sc.get(&accb, G.ncell * dsize(G.acc_dtype)));
+    HIPCHK(sc.get(&st.u_a, G.ncell_pad * es * ns));
+    HIPCHK(sc.get(&st.u_b, G.ncell_pad * es * ns));
+    HIPCHK(sc.get(&st.acc, G.ncell_pad * dsize(G.acc_dtype)));
+    HIPCHK(sc.get(&accb, G.ncell_pad * dsize(G.acc_dtype)));
     HIPCHK(sc.get(&st.residual, std::max<size_t>((size_t)nt * acq->nrec * es, es)));
     if ((rc = vd_sens_forward(grid, m, b, acq, dt, nt, observed, &st, accb, traces, J_host, opts, s, true)))
         return rc;
@@ -929,15 +1034,17 @@ int vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* 
     if ((rc = check_dev(traces, (size_t)nt * acq->nrec * es, "traces"))) return rc;
     Scratch sc(s);
     if ((rc = check_material(G, m, b, dt, s, sc))) return rc;
+    const void *mp = nullptr, *bp = nullptr;
+    if ((rc = padded_material(G, m, b, sc, s, &mp, &bp))) return rc;
     const int ns = nshots(acq);
     void *ua = nullptr, *ub = nullptr;
-    HIPCHK(sc.get(&ua, G.ncell * es * ns));
-    HIPCHK(sc.get(&ub, G.ncell * es * ns));
+    HIPCHK(sc.get(&ua, G.ncell_pad * es * ns));
+    HIPCHK(sc.get(&ub, G.ncell_pad * es * ns));
     Plan P;
     if ((rc = make_plan(G, acq, false, s, sc, &P))) return rc;
     VdFields vd;
-    vd.stiff = b;
-    if ((rc = forward_sweep(G, P, m, acq, dt, nt, nullptr, ua, ub, nullptr, nullptr, traces, s, vd)))
+    vd.stiff = bp;
+    if ((rc = forward_sweep(G, P, mp, acq, dt, nt, nullptr, ua, ub, nullptr, nullptr, traces, s, vd)))
         return rc;
     HIPCHK(hipStreamSynchronize(s));
     return FD_OK;

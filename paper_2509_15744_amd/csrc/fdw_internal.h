@@ -40,6 +40,8 @@ struct StepArgs {
     void* acc_b;         // variable-material step: stiffness-term accumulator
     int64_t shot_stride; // elements between the wavefields of consecutive shots
     int32_t n0, n1, n2;  // extents; 2D grids run with n1 = 1
+    int32_t pitch;       // elements between consecutive rows (>= n2; the variable-material
+                         // step pads rows to 256-byte alignment, the others use n2)
     double w[8];         // a_j / dx^2, j = 1..r
     double dt2;          // dt^2
     int32_t coef_direct; // 1: c already holds dt^2 c^2

@@ -60,8 +60,9 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
     const int z = z0 + lz * VZ;
     const int y = y0 + ly;
     const bool live = z < n2 && y < n1;
-    const int64_t ps = (int64_t)n1 * n2;
-    const int roff = ghost(y, n1) * n2;
+    const int pitch = a.pitch;                  // row stride (rows may be padded)
+    const int64_t ps = (int64_t)n1 * pitch;
+    const int roff = ghost(y, n1) * pitch;
     const int lofs = (ly + RYH) * LZ + PADL + lz * VZ;
     const int lane0 = ly * WZ + lz * VZ;
 
@@ -85,7 +86,7 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
         const int sy = row < 1 ? 0 : TY + 1;
         const int cz = (h % TZ) * VZ;
         hyl[i] = h < HYV ? sy * LZ + PADL + cz : -1;
-        hyr[i] = ghost(y0 + sy - 1, n1) * n2;
+        hyr[i] = ghost(y0 + sy - 1, n1) * pitch;
         hyz[i] = z0 + cz;
     }
     int hzl[NHZ], hzg[NHZ];
@@ -95,7 +96,7 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
         const int row = h / 2;
         const int sz = (h % 2) == 0 ? PADL - 1 : PADL + WZ;
         hzl[i] = h < HZ ? (RYH + row) * LZ + sz : -1;
-        hzg[i] = ghost(y0 + (h < HZ ? row : 0), n1) * n2 + ghost(z0 + sz - PADL, n2);
+        hzg[i] = ghost(y0 + (h < HZ ? row : 0), n1) * pitch + ghost(z0 + sz - PADL, n2);
     }
 
     // register queues along axis 0: planes x-1, x, x+1 of u^n and of b
