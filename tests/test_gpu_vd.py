@@ -91,13 +91,13 @@ def test_vd_gap_matches_closed_forms(fdw):
     assert rel(gb - eb, 0.5 * k * dt * dt * s2b) < 1e-6
 
 
-@pytest.mark.parametrize("acc", ["f64", "f32"])
-def test_vd_f32(fdw, acc):
-    shape, nt = (40, 24, 128), 300
+@pytest.mark.parametrize("acc,shape", [("f64", (40, 24, 128)), ("f32", (40, 24, 128)), ("f64", (40, 24, 100))])
+def test_vd_f32(fdw, acc, shape):
+    nt = 300
     m, b, dt, src, rec, w, obs = _medium(shape, 9, nt, nrec=16, layered=True)
     k = 0.05
     om, ob, oJ, otr = oracle.vd_superposition_gradient(m, b, 1.0, dt, nt, src, w, rec, obs, k)
-    say("vd f32, acc", acc)
+    say("vd f32, acc", acc, shape)
     gm, gb, J, tr = _run(fdw, m, b, dt, nt, src, w, rec, obs, k, torch.float32, acc_dtype=acc)
     assert rel(tr, otr) < 1e-4
     assert abs(J - oJ) < 1e-4 * oJ
@@ -255,3 +255,41 @@ def test_vd_stability_bound_is_per_cell(fdw):
     with pytest.raises(fdw.FdError) as e:
         fdw.fd_vd_forward(to_dev(m, f64), to_dev(b, f64), 1.0, src, to_dev(w, f64), rec, 1.01 * dt_lim, nt)
     assert e.value.code == fdw.FD_E_CFL
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_vd_shots_with_padded_rows(fdw, split):
+    """Three shots on a grid whose contiguous extent (70) is padded to 128 inside the
+    library: the fused call and the split halves (whose caller-owned dense state is
+    copied in and out of the padded layout) equal the sum of per-shot oracle runs."""
+    shape, nt = (12, 9, 70), 30
+    m, b, dt, _, _, _, _ = _medium(shape, 81, nt)
+    rng = np.random.default_rng(82)
+    n = int(np.prod(shape))
+    src = rng.integers(0, n, 3).astype(np.int64)
+    rec = rng.integers(0, n, 9).astype(np.int64)
+    src_shot = np.arange(3, dtype=np.int32)
+    rec_shot = np.repeat(np.arange(3, dtype=np.int32), 3)
+    w = rng.standard_normal((nt, 3))
+    obs = 0.05 * rng.standard_normal((nt, 9))
+    k = 0.02
+    om, ob, oJ = np.zeros(shape), np.zeros(shape), 0.0
+    for sh in range(3):
+        ri = np.where(rec_shot == sh)[0]
+        a, bb, J, _ = oracle.vd_superposition_gradient(m, b, 1.0, dt, nt, src[sh:sh + 1], w[:, sh:sh + 1],
+                                                       rec[ri], obs[:, ri], k)
+        om += a
+        ob += bb
+        oJ += J
+    f64 = torch.float64
+    md, bd, wd, od = to_dev(m, f64), to_dev(b, f64), to_dev(w, f64), to_dev(obs, f64)
+    shots = (src_shot, rec_shot, 3)
+    say("vd shots padded, split", split)
+    if split:
+        st = fdw.VdSweepState(md, nt, len(rec), nshot=3)
+        J = fdw.fd_vd_sens_forward(md, bd, 1.0, src, wd, rec, dt, nt, od, st, shots=shots)
+        gm, gb = fdw.fd_vd_sens_backward(md, bd, 1.0, src, wd, rec, dt, nt, k, st, shots=shots)
+    else:
+        gm, gb, J = fdw.fd_vd_adjoint_sensitivity(md, bd, 1.0, src, wd, rec, dt, nt, od, k, shots=shots)
+    assert abs(J - oJ) <= 1e-12 * oJ
+    assert rel(gm.cpu().numpy(), om) < 1e-9 and rel(gb.cpu().numpy(), ob) < 1e-9
