@@ -240,7 +240,11 @@ int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, doub
  * dt^2 max_i s_i <= 4 dx^2 (else FD_E_CFL), s_i = sum over the interior faces of cell i
  * of h_f (1/m_i + 1/sqrt(m_i m_j)): the Gershgorin bound of the leapfrog limit
  * dt^2 lambda_max(M^-1 K) < 4, equal to dt sqrt(d b/m) <= dx in a homogeneous medium
- * and local where materials mix.  Time axis, sources, receivers, shots
+ * and local where materials mix.  When the contiguous extent is not a multiple of
+ * 64 the sweeps run on copies with rows padded to 64 elements (m and b, the
+ * wavefields and both accumulators; stream-ordered scratch of up to about six grid
+ * arrays beyond the unpadded case), which keeps every row load on 256-byte
+ * boundaries; callers' arrays stay dense.  Time axis, sources, receivers, shots
  * and misfit as for the constant-density calls.  fd_opts.variant: 0, 1 or 2 (2D also 4 or 5);
  * max_group is ignored (one wavefield per launch). */
 int fd_vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
