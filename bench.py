@@ -429,6 +429,8 @@ def run_tato(args, np, torch, fdw, wl):
     material = fdw.two_material(mats["rho1"], mats["rho2"], mats["kappa1"], mats["kappa2"])
     d = fdw.make_design(shape, q["design_origin"], q["design_extent"], fdw.FD_F32, material, 1.5, 1.0, 0.5,
                         0.0, 1.0)
+    # the paper's dt unless a design could break the per-cell stability bound at it
+    q["dt"] = min(q["dt"], dz.stable_dt(material, 0.0, 1.0, q["dx"], 2))
     f32 = torch.float32
     m = torch.full(shape, 1.0 / mats["kappa1"], dtype=f32, device="cuda")
     b = torch.full(shape, 1.0 / mats["rho1"], dtype=f32, device="cuda")
