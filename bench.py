@@ -141,11 +141,24 @@ def cpu_baseline(p, c_dev, wl):
     oracle.superposition_gradient(c, p.dx, p.order, p.dt, nt_s, src, w, rec, obs, 1e-3)
     el = time.perf_counter() - t0
     upd = ncell * (2 * nt_s - 1)
-    return {"value": upd / el / 1e9, "unit": "Gcell-updates/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same crop on one thread, for a few steps
+    nt_1 = max(2, nt_s // 10)
+    prev = oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.superposition_gradient(c, p.dx, p.order, p.dt, nt_1, src, w[:nt_1], rec, obs[:nt_1], 1e-3)
+        el1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(prev)
+    upd1 = ncell * (2 * nt_1 - 1)
+    return {"value": upd / el / 1e9, "unit": "Gcell-updates/s", "cores": cores,
             "kind": "oracle",
+            "single_thread_value": upd1 / el1 / 1e9,
             "sample": f"FP64 oracle, crop {'x'.join(map(str, crop))} of the same medium around the "
                       f"first source, {len(rec)} receivers, nt={nt_s}, one shot "
-                      f"({upd:.3g} cell-updates in {el:.1f} s)"}
+                      f"({upd:.3g} cell-updates in {el:.1f} s on {cores} threads; the same crop for "
+                      f"nt={nt_1} on one thread: {upd1:.3g} in {el1:.1f} s)"}
 
 
 def rel_dev(a, b):

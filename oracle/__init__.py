@@ -144,6 +144,8 @@ def _load():
         lib.orc_exact_gradient_ckpt.restype = I
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = I
+        lib.orc_set_threads.argtypes = [I]
+        lib.orc_set_threads.restype = I
         vgrid = [I, P, D]
         lib.orc_vd_operator.argtypes = vgrid + [P, P, P]
         lib.orc_vd_operator.restype = None
@@ -343,6 +345,11 @@ def fd_gradient(c, dx, order, dt, nt, src, wavelet, rec, observed, cells, eps=1e
 def num_threads() -> int:
     """Threads used by the oracle's parallel cell loops."""
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """Set the threads of the oracle's parallel loops; returns the previous count."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def cfl_limit(ndim: int, order: int) -> float:

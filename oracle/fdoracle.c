@@ -49,6 +49,18 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Set that number (timing the oracle single-threaded); returns the previous one. */
+int orc_set_threads(int n)
+{
+    const int prev = orc_num_threads();
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return prev;
+}
+
 typedef struct {
     int ndim;      /* 1, 2 or 3 */
     long n[3];     /* extents, axis 0 slowest; unused trailing axes have extent 1 */
