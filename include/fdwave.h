@@ -158,11 +158,14 @@ double fd_cfl_limit(int32_t ndim, int32_t order);
  * acquisition takes from the stream-ordered pool of `stream`'s device, beyond the
  * caller's inputs and outputs (host-side arithmetic, no device work):
  *   wavefields 2 * nshots * ncell * sizeof(T), accumulator ncell * 8 (f64, the larger
- *   choice), residual rows nt * nrec * sizeof(T), event tables of two launch plans
+ *   choice), residual rows nt * nrec * sizeof(T) — with ncell counted in rows padded to
+ *   64 elements when the contiguous extent is not a multiple of 64, plus then a padded
+ *   copy of c and a padded finalisation buffer — event tables of two launch plans
  *   (per-block offsets for every shot group, bounded with the smallest tile and one
  *   plane per block) and the reduction partials.  acq may be NULL (no sources or receivers); nshots < 1 counts as 1.
  * Returns 0 and sets fd_last_error on an invalid grid or a negative nt.  The split
- * halves take the same amount less the caller-owned fd_state arrays. */
+ * halves take the same amount less the caller-owned fd_state arrays (plus padded
+ * working copies of those arrays when rows are padded). */
 size_t fd_workspace_bytes(const fd_grid* grid, const fd_acq* acq, int32_t nt, int32_t nshots);
 
 /* Number of kernel tile variants for `ndim` (valid fd_opts.variant values are 1..count). */
@@ -283,7 +286,10 @@ int fd_vd_sens_backward(const fd_grid* grid, const void* m, const void* b, const
 
 /* First half of fd_adjoint_sensitivity: the forward sweep with cost, adjoint force and
  * K(u,u) accumulation; leaves u^{nt-1}, u^nt, the accumulator and the residuals in
- * `state` (all four arrays overwritten).  J_host may be NULL. */
+ * `state` (all four arrays overwritten).  J_host may be NULL.  When the contiguous
+ * extent is not a multiple of 64 this call, its second half, fd_forward and
+ * fd_adjoint_sensitivity sweep on copies with rows padded to 64 elements (256-byte
+ * aligned row loads); `state` stays in the caller's dense layout. */
 int fd_sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
                     int32_t nt, const void* observed, const fd_state* state,
                     void* traces_or_null, double* J_host, const fd_opts* opts, void* stream);

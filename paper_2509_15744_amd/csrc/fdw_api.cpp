@@ -464,7 +464,7 @@ fdw::StepArgs base_args(const Geo& G, const Plan& P, const void* c, double dt)
     fdw::StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.c = c;
-    a.shot_stride = G.ncell;
+    a.shot_stride = G.ncell_pad;
     a.n0 = G.n0; a.n1 = G.n1; a.n2 = G.n2;
     a.pitch = G.pitch;
     const double* w = weights(2 * G.r);
@@ -576,7 +576,7 @@ int prepare(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, in
 }
 
 // Forward sweep of every shot group (Alg. 1 forward loop); the wavefields of shot s
-// live at ua/ub + s * ncell.  `acc` null: no kernel accumulation (plain forward).  With
+// live at ua/ub + s * ncell_pad (rows possibly padded to G.pitch).  `acc` null: no kernel accumulation (plain forward).  With
 // vd.stiff the variable-material step runs (c is then the mass coefficient) and, with
 // vd.acc_b, every launch adds the stiffness term of its current level.
 int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
@@ -698,6 +698,110 @@ int misfit_sum(int dtype, const void* x, const void* y, void* diff, int64_t n, h
     return FD_OK;
 }
 
+// Rows that do not start on 256-byte boundaries cost about a third of a sweep's
+// throughput (each 64-lane row load touches three cache lines instead of two): the
+// sweeps of the calls that use this run on copies whose rows are padded to 64
+// elements.  The caller's arrays stay dense.
+void pad_rows(Geo* G)
+{
+    const int pitch = (G->n2 + 63) / 64 * 64;
+    if (pitch != G->n2 && (int64_t)G->n1 * pitch < ((int64_t)1 << 31)) {
+        G->pitch = pitch;
+        G->ncell_pad = (int64_t)G->n0 * G->n1 * pitch;
+    }
+}
+
+// Copy `rows` rows of n2 elements between arrays with row strides dpitch and spitch.
+int copy_rows(void* dst, int64_t dpitch, const void* src, int64_t spitch, size_t es, int64_t rows, int64_t n2,
+              hipStream_t s)
+{
+    if (rows == 0) return FD_OK;
+    HIPCHK(hipMemcpy2DAsync(dst, (size_t)dpitch * es, src, (size_t)spitch * es, (size_t)n2 * es, (size_t)rows,
+                            hipMemcpyDeviceToDevice, s));
+    return FD_OK;
+}
+
+// One field in the library's row layout: the caller's array when rows are not padded,
+// else a padded copy.
+int padded_field(const Geo& G, const void* f, Scratch& sc, hipStream_t s, const void** fp)
+{
+    *fp = f;
+    if (G.pitch == G.n2) return FD_OK;
+    const size_t es = dsize(G.dtype);
+    void* p = nullptr;
+    HIPCHK(sc.get(&p, G.ncell_pad * es));
+    int rc = copy_rows(p, G.pitch, f, G.n2, es, (int64_t)G.n0 * G.n1, G.n2, s);
+    if (rc) return rc;
+    *fp = p;
+    return FD_OK;
+}
+
+// The material of a sweep in the library's row layout: the caller's arrays when rows
+// are not padded, else padded copies.
+int padded_material(const Geo& G, const void* m, const void* b, Scratch& sc, hipStream_t s, const void** mp,
+                    const void** bp)
+{
+    *mp = m;
+    *bp = b;
+    if (G.pitch == G.n2) return FD_OK;
+    const size_t es = dsize(G.dtype);
+    const int64_t rows = (int64_t)G.n0 * G.n1;
+    void *pm = nullptr, *pb = nullptr;
+    HIPCHK(sc.get(&pm, G.ncell_pad * es));
+    HIPCHK(sc.get(&pb, G.ncell_pad * es));
+    int rc;
+    if ((rc = copy_rows(pm, G.pitch, m, G.n2, es, rows, G.n2, s))) return rc;
+    if ((rc = copy_rows(pb, G.pitch, b, G.n2, es, rows, G.n2, s))) return rc;
+    *mp = pm;
+    *bp = pb;
+    return FD_OK;
+}
+
+// The sweep state in the library's row layout (stiffness accumulator only for the
+// variable-material scheme).  With padded rows and a caller-owned
+// (dense) state, the sweeps work on padded copies: the forward half hands the final
+// levels and both accumulators back to the caller's arrays, the backward half starts
+// by copying them in.  Internal states (own_state) are allocated padded.
+struct VdWork {
+    fd_state st{};
+    void* acc_b = nullptr;
+    bool copied = false;
+};
+
+int vd_work(const Geo& G, const fd_state* st, void* acc_b, int ns, bool own_state, bool copy_in, Scratch& sc,
+            hipStream_t s, VdWork* w)
+{
+    w->st = *st;
+    w->acc_b = acc_b;
+    if (G.pitch == G.n2 || own_state) return FD_OK;
+    const size_t es = dsize(G.dtype), aes = dsize(G.acc_dtype);
+    HIPCHK(sc.get(&w->st.u_a, G.ncell_pad * es * ns));
+    HIPCHK(sc.get(&w->st.u_b, G.ncell_pad * es * ns));
+    HIPCHK(sc.get(&w->st.acc, G.ncell_pad * aes));
+    if (acc_b) HIPCHK(sc.get(&w->acc_b, G.ncell_pad * aes));
+    w->copied = true;
+    if (!copy_in) return FD_OK;
+    const int64_t rows = (int64_t)G.n0 * G.n1;
+    int rc;
+    if ((rc = copy_rows(w->st.u_a, G.pitch, st->u_a, G.n2, es, rows * ns, G.n2, s))) return rc;
+    if ((rc = copy_rows(w->st.u_b, G.pitch, st->u_b, G.n2, es, rows * ns, G.n2, s))) return rc;
+    if ((rc = copy_rows(w->st.acc, G.pitch, st->acc, G.n2, aes, rows, G.n2, s))) return rc;
+    return acc_b ? copy_rows(w->acc_b, G.pitch, acc_b, G.n2, aes, rows, G.n2, s) : FD_OK;
+}
+
+// Hand a padded working state back to the caller's dense arrays.
+int work_out(const Geo& G, const VdWork& w, const fd_state* st, void* acc_b, int ns, hipStream_t s)
+{
+    if (!w.copied) return FD_OK;
+    const size_t es = dsize(G.dtype), aes = dsize(G.acc_dtype);
+    const int64_t rows = (int64_t)G.n0 * G.n1;
+    int rc;
+    if ((rc = copy_rows(st->u_a, G.n2, w.st.u_a, G.pitch, es, rows * ns, G.n2, s))) return rc;
+    if ((rc = copy_rows(st->u_b, G.n2, w.st.u_b, G.pitch, es, rows * ns, G.n2, s))) return rc;
+    if ((rc = copy_rows(st->acc, G.n2, w.st.acc, G.pitch, aes, rows, G.n2, s))) return rc;
+    return acc_b ? copy_rows(acc_b, G.n2, w.acc_b, G.pitch, aes, rows, G.n2, s) : FD_OK;
+}
+
 int check_state(const fd_state* st, const Geo& G, int nt, const fd_acq* acq)
 {
     if (!st) return fail(FD_E_ARG, "state is null");
@@ -723,11 +827,18 @@ int sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double d
     const size_t tb = (size_t)nt * acq->nrec * dsize(G.dtype);
     if ((rc = check_dev(observed, tb, "observed"))) return rc;
     if (traces && (rc = check_dev(traces, tb, "traces"))) return rc;
+    pad_rows(&G);
+    const void* cp = nullptr;
+    if ((rc = padded_field(G, c, sc, s, &cp))) return rc;
     Plan P;
     if ((rc = make_plan(G, acq, false, s, sc, &P))) return rc;
-    if ((rc = forward_sweep(G, P, c, acq, dt, nt, observed, st->u_a, st->u_b, st->acc, st->residual,
+    const int ns = nshots(acq);
+    VdWork w;
+    if ((rc = vd_work(G, st, nullptr, ns, own_state, false, sc, s, &w))) return rc;
+    if ((rc = forward_sweep(G, P, cp, acq, dt, nt, observed, w.st.u_a, w.st.u_b, w.st.acc, st->residual,
                             traces, s)))
         return rc;
+    if ((rc = work_out(G, w, st, nullptr, ns, s))) return rc;   // back to the caller's dense layout
     if (J_host) {
         double ss = 0.0;
         if ((rc = misfit_sum(G.dtype, st->residual, nullptr, nullptr, (int64_t)nt * acq->nrec, s, sc, &ss)))
@@ -750,11 +861,24 @@ int sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double 
     if (!std::isfinite(grad_scale)) return fail(FD_E_ARG, "grad_scale must be finite");
     if (!own_state && (rc = check_state(st, G, nt, acq))) return rc;
     if ((rc = check_dev(grad, G.ncell * dsize(G.dtype), "grad_c"))) return rc;
+    pad_rows(&G);
+    const void* cp = nullptr;
+    if ((rc = padded_field(G, c, sc, s, &cp))) return rc;
     Plan P;
     if ((rc = make_plan(G, acq, true, s, sc, &P))) return rc;
-    if ((rc = backward_sweep(G, P, c, acq, dt, nt, k, st->u_a, st->u_b, st->acc, st->residual, s)))
+    VdWork w;
+    if ((rc = vd_work(G, st, nullptr, nshots(acq), own_state, true, sc, s, &w))) return rc;
+    if ((rc = backward_sweep(G, P, cp, acq, dt, nt, k, w.st.u_a, w.st.u_b, w.st.acc, st->residual, s)))
         return rc;
-    HIPCHK(fdw::launch_finalize(G.dtype, G.acc_dtype, G.ncell, st->acc, c, grad_scale / k, grad, s));
+    if (G.pitch == G.n2) {
+        HIPCHK(fdw::launch_finalize(G.dtype, G.acc_dtype, G.ncell, w.st.acc, c, grad_scale / k, grad, s));
+    } else {   // finalise in the padded layout, then copy the rows out
+        const size_t es = dsize(G.dtype);
+        void* t = nullptr;
+        HIPCHK(sc.get(&t, G.ncell_pad * es));
+        HIPCHK(fdw::launch_finalize(G.dtype, G.acc_dtype, G.ncell_pad, w.st.acc, cp, grad_scale / k, t, s));
+        if ((rc = copy_rows(grad, G.n2, t, G.pitch, es, (int64_t)G.n0 * G.n1, G.n2, s))) return rc;
+    }
     return FD_OK;
 }
 
@@ -809,45 +933,7 @@ int vd_setup(const fd_grid* grid, const fd_opts* opts, Geo* G)
     // registers while serialising its rows; two-row chunks keep the most blocks in
     // flight and measured fastest (one row ties, longer chunks lose steadily).
     if (G->ndim == 2 && G->chunk == 0) G->chunk = 2;
-    // Rows that do not start on 256-byte boundaries cost about a third of the
-    // throughput (each 64-lane row load touches three cache lines instead of two):
-    // the sweeps run on copies whose rows are padded to 64 elements.
-    const int pitch = (G->n2 + 63) / 64 * 64;
-    if (pitch != G->n2 && (int64_t)G->n1 * pitch < ((int64_t)1 << 31)) {
-        G->pitch = pitch;
-        G->ncell_pad = (int64_t)G->n0 * G->n1 * pitch;
-    }
-    return FD_OK;
-}
-
-// Copy `rows` rows of n2 elements between arrays with row strides dpitch and spitch.
-int copy_rows(void* dst, int64_t dpitch, const void* src, int64_t spitch, size_t es, int64_t rows, int64_t n2,
-              hipStream_t s)
-{
-    if (rows == 0) return FD_OK;
-    HIPCHK(hipMemcpy2DAsync(dst, (size_t)dpitch * es, src, (size_t)spitch * es, (size_t)n2 * es, (size_t)rows,
-                            hipMemcpyDeviceToDevice, s));
-    return FD_OK;
-}
-
-// The material of a sweep in the library's row layout: the caller's arrays when rows
-// are not padded, else padded copies.
-int padded_material(const Geo& G, const void* m, const void* b, Scratch& sc, hipStream_t s, const void** mp,
-                    const void** bp)
-{
-    *mp = m;
-    *bp = b;
-    if (G.pitch == G.n2) return FD_OK;
-    const size_t es = dsize(G.dtype);
-    const int64_t rows = (int64_t)G.n0 * G.n1;
-    void *pm = nullptr, *pb = nullptr;
-    HIPCHK(sc.get(&pm, G.ncell_pad * es));
-    HIPCHK(sc.get(&pb, G.ncell_pad * es));
-    int rc;
-    if ((rc = copy_rows(pm, G.pitch, m, G.n2, es, rows, G.n2, s))) return rc;
-    if ((rc = copy_rows(pb, G.pitch, b, G.n2, es, rows, G.n2, s))) return rc;
-    *mp = pm;
-    *bp = pb;
+    pad_rows(G);
     return FD_OK;
 }
 
@@ -871,37 +957,6 @@ int check_vd_state(const fd_state* st, const void* acc_b, const Geo& G, int nt, 
     int rc = check_state(st, G, nt, acq);
     if (rc) return rc;
     return check_dev(acc_b, G.ncell * dsize(G.acc_dtype), "acc_b");
-}
-
-// The sweep state in the library's row layout.  With padded rows and a caller-owned
-// (dense) state, the sweeps work on padded copies: the forward half hands the final
-// levels and both accumulators back to the caller's arrays, the backward half starts
-// by copying them in.  Internal states (own_state) are allocated padded.
-struct VdWork {
-    fd_state st{};
-    void* acc_b = nullptr;
-    bool copied = false;
-};
-
-int vd_work(const Geo& G, const fd_state* st, void* acc_b, int ns, bool own_state, bool copy_in, Scratch& sc,
-            hipStream_t s, VdWork* w)
-{
-    w->st = *st;
-    w->acc_b = acc_b;
-    if (G.pitch == G.n2 || own_state) return FD_OK;
-    const size_t es = dsize(G.dtype), aes = dsize(G.acc_dtype);
-    HIPCHK(sc.get(&w->st.u_a, G.ncell_pad * es * ns));
-    HIPCHK(sc.get(&w->st.u_b, G.ncell_pad * es * ns));
-    HIPCHK(sc.get(&w->st.acc, G.ncell_pad * aes));
-    HIPCHK(sc.get(&w->acc_b, G.ncell_pad * aes));
-    w->copied = true;
-    if (!copy_in) return FD_OK;
-    const int64_t rows = (int64_t)G.n0 * G.n1;
-    int rc;
-    if ((rc = copy_rows(w->st.u_a, G.pitch, st->u_a, G.n2, es, rows * ns, G.n2, s))) return rc;
-    if ((rc = copy_rows(w->st.u_b, G.pitch, st->u_b, G.n2, es, rows * ns, G.n2, s))) return rc;
-    if ((rc = copy_rows(w->st.acc, G.pitch, st->acc, G.n2, aes, rows, G.n2, s))) return rc;
-    return copy_rows(w->acc_b, G.pitch, acc_b, G.n2, aes, rows, G.n2, s);
 }
 
 // First half: forward sweep with cost, adjoint force and both kernel terms of u.
@@ -931,14 +986,7 @@ int vd_sens_forward(const fd_grid* grid, const void* m, const void* b, const fd_
     if ((rc = forward_sweep(G, P, mp, acq, dt, nt, observed, w.st.u_a, w.st.u_b, w.st.acc, st->residual, traces,
                             s, vd)))
         return rc;
-    if (w.copied) {   // hand the state back in the caller's dense layout
-        const size_t es = dsize(G.dtype), aes = dsize(G.acc_dtype);
-        const int64_t rows = (int64_t)G.n0 * G.n1;
-        if ((rc = copy_rows(st->u_a, G.n2, w.st.u_a, G.pitch, es, rows * ns, G.n2, s))) return rc;
-        if ((rc = copy_rows(st->u_b, G.n2, w.st.u_b, G.pitch, es, rows * ns, G.n2, s))) return rc;
-        if ((rc = copy_rows(st->acc, G.n2, w.st.acc, G.pitch, aes, rows, G.n2, s))) return rc;
-        if ((rc = copy_rows(acc_b, G.n2, w.acc_b, G.pitch, aes, rows, G.n2, s))) return rc;
-    }
+    if ((rc = work_out(G, w, st, acc_b, ns, s))) return rc;   // back to the caller's dense layout
     if (J_host) {
         double ss = 0.0;
         if ((rc = misfit_sum(G.dtype, st->residual, nullptr, nullptr, (int64_t)nt * acq->nrec, s, sc, &ss)))
@@ -1127,7 +1175,7 @@ int exact_gradient(const fd_grid* grid, const void* c, const fd_acq* acq, double
                                           ul, up, acc, (const char*)resid + (size_t)(nt - 1) * acq->nrec * es,
                                           rec_scale, s));
     fdw::StepArgs a = base_args(Gb, Pb, c, dt);
-    a.shot_stride = (int64_t)G.ncell * ns;   // slot 1 (mu) of shot s sits nshot fields after its u
+    a.shot_stride = (int64_t)G.ncell_pad * ns;   // slot 1 (mu) of shot s sits nshot fields after its u
     a.acc = acc;
     a.acc_cross = 1;
     a.wavelet = acq->wavelet;
@@ -1750,7 +1798,10 @@ size_t fd_workspace_bytes(const fd_grid* grid, const fd_acq* acq, int32_t nt, in
     const size_t ns = nshots > 1 ? (size_t)nshots : 1;
     const size_t nsrc = acq && acq->nsrc > 0 ? (size_t)acq->nsrc : 0;
     const size_t nrec = acq && acq->nrec > 0 ? (size_t)acq->nrec : 0;
-    size_t bytes = 2 * ns * (size_t)G.ncell * es + (size_t)G.ncell * 8 + (size_t)nt * nrec * es;
+    pad_rows(&G);   // the call's own arrays use the padded row layout
+    const size_t np = (size_t)G.ncell_pad;
+    size_t bytes = 2 * ns * np * es + np * 8 + (size_t)nt * nrec * es;
+    if (G.pitch != G.n2) bytes += 2 * np * es;   // padded copy of c, finalisation rows
     // the largest block count of any tile variant with one plane per block
     int64_t per_plane = 1;
     for (int v = 1; v <= fdw::variant_count(G.ndim); ++v) {
@@ -1797,12 +1848,15 @@ int fd_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
     int rc = prepare(grid, c, acq, dt, nt, opts, s, sc, &G, true);
     if (rc) return rc;
     if ((rc = check_dev(traces, (size_t)nt * acq->nrec * dsize(G.dtype), "traces"))) return rc;
+    pad_rows(&G);
+    const void* cp = nullptr;
+    if ((rc = padded_field(G, c, sc, s, &cp))) return rc;
     Plan P;
     if ((rc = make_plan(G, acq, false, s, sc, &P))) return rc;
     void *ua = nullptr, *ub = nullptr;
-    HIPCHK(sc.get(&ua, G.ncell * dsize(G.dtype) * nshots(acq)));
-    HIPCHK(sc.get(&ub, G.ncell * dsize(G.dtype) * nshots(acq)));
-    return forward_sweep(G, P, c, acq, dt, nt, nullptr, ua, ub, nullptr, nullptr, traces, s);
+    HIPCHK(sc.get(&ua, G.ncell_pad * dsize(G.dtype) * nshots(acq)));
+    HIPCHK(sc.get(&ub, G.ncell_pad * dsize(G.dtype) * nshots(acq)));
+    return forward_sweep(G, P, cp, acq, dt, nt, nullptr, ua, ub, nullptr, nullptr, traces, s);
 }
 
 int fd_misfit(int32_t nt, int32_t nrec, int32_t dtype, double dt, const void* traces,
@@ -1861,10 +1915,11 @@ int fd_adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq
     if (acq->nshot < 0) return fail(FD_E_ARG, "nshot is negative");
     if (!(k != 0.0) || !std::isfinite(k)) return fail(FD_E_ARG, "k must be finite and non-zero");
     Scratch sc(s);
+    pad_rows(&G);   // the halves' own state is in the (possibly padded) row layout
     fd_state st;
-    HIPCHK(sc.get(&st.u_a, G.ncell * dsize(G.dtype) * nshots(acq)));
-    HIPCHK(sc.get(&st.u_b, G.ncell * dsize(G.dtype) * nshots(acq)));
-    HIPCHK(sc.get(&st.acc, G.ncell * dsize(G.acc_dtype)));
+    HIPCHK(sc.get(&st.u_a, G.ncell_pad * dsize(G.dtype) * nshots(acq)));
+    HIPCHK(sc.get(&st.u_b, G.ncell_pad * dsize(G.dtype) * nshots(acq)));
+    HIPCHK(sc.get(&st.acc, G.ncell_pad * dsize(G.acc_dtype)));
     HIPCHK(sc.get(&st.residual, (size_t)nt * acq->nrec * dsize(G.dtype)));
     if ((rc = sens_forward(grid, c, acq, dt, nt, observed, &st, traces_or_null, J_host, opts, s, true)))
         return rc;

@@ -260,7 +260,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
     const int lyt = tid / TZ;
     const int z = z0 + lz * VZ;              // first cell of this lane
     const bool zlive = z < n2;
-    const int64_t ps = (int64_t)n1 * n2;
+    const int pitch = a.pitch;                  // row stride (rows may be padded)
+    const int64_t ps = (int64_t)n1 * pitch;
     const int64_t sst = a.shot_stride;
 
     const T* __restrict__ ucur = (const T*)a.ucur;
@@ -280,7 +281,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
     for (int k = 0; k < RY; ++k) {
         const int ly = lyt + k * TYT;
         const int y = y0 + ly;
-        roff[k] = ghost(y, n1) * n2;
+        roff[k] = ghost(y, n1) * pitch;
         live[k] = zlive && (y < n1);
         lofs[k] = (ly + RYH) * LZ + PADL + lz * VZ;
         lane0[k] = ly * WZ + lz * VZ;
@@ -294,7 +295,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
         const int sy = row < R ? row : row + TY;
         const int cz = (h % TZ) * VZ;
         hyl[i] = h < HYV ? sy * LZ + PADL + cz : -1;
-        hyr[i] = ghost(y0 + sy - R, n1) * n2;
+        hyr[i] = ghost(y0 + sy - R, n1) * pitch;
         hyz[i] = z0 + cz;
     }
     // halo columns: LDS slot and in-plane offset of single cells
@@ -307,7 +308,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
         const int sz = col < R ? PADL - R + col : PADL + WZ + (col - R);
         hzl[i] = h < HZ ? (RYH + row) * LZ + sz : -1;
         const int gy = ghost(y0 + (h < HZ ? row : 0), n1);
-        hzg[i] = gy * n2 + ghost(z0 + sz - PADL, n2);
+        hzg[i] = gy * pitch + ghost(z0 + sz - PADL, n2);
     }
 
     // register queue along axis 0: q[s][k][R + d] = u^n(x + d) of shot s, d in [-R, R]

@@ -215,12 +215,15 @@ def test_workspace_bytes(fdw):
     """fd_workspace_bytes covers the state arrays (two wavefields per shot, an f64
     accumulator, the residual rows) plus small tables, grows with each input, and
     rejects a bad grid."""
-    shape, nt, nrec = (64, 48, 80), 500, 300
-    n = 64 * 48 * 80
+    shape, nt, nrec = (64, 48, 128), 500, 300
+    n = 64 * 48 * 128
     w = fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, nt, nsrc=2, nrec=nrec)
     state = 2 * n * 4 + n * 8 + nt * nrec * 4
     assert state < w < state * 1.1
     assert fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, nt, nsrc=2, nrec=nrec, nshots=4) - w >= 6 * n * 4
+    # rows of 80 are padded to 128: the bound covers the padded arrays
+    wp = fdw.fd_workspace_bytes((64, 48, 80), 8, fdw.FD_F32, nt, nsrc=2, nrec=nrec)
+    assert wp > 2 * n * 4 + n * 8 + nt * nrec * 4
     assert fdw.fd_workspace_bytes(shape, 8, fdw.FD_F64, nt, nsrc=2, nrec=nrec) > w
     assert fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, 2 * nt, nsrc=2, nrec=nrec) - w == nt * nrec * 4
     with pytest.raises(fdw.FdError):
