@@ -1342,7 +1342,7 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
     if (!best) return fail(FD_E_ARG, "best is null");
     if (steps < 1) return fail(FD_E_ARG, "steps must be >= 1");
     // small grids give launches of tens of microseconds: time more of them
-    steps *= (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 24) / std::max<int64_t>(G.ncell, 1)));
+    steps *= (int)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)1 << 26) / std::max<int64_t>(G.ncell, 1)));
     nshot = std::max(nshot, 1);
     // candidate shapes: variants that fit, shot groups, chunk lengths
     std::vector<int> groups = {1};
