@@ -1508,19 +1508,25 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         }
         if ((rc = check_speeds(gs, cs, dts, s, sc))) return rc;
     }
+    // each problem sweeps on rows padded to 64 elements when its extent needs it
+    std::vector<const void*> cp(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        pad_rows(&G[p]);
+        if ((rc = padded_field(G[p], probs[p].c, sc, s, &cp[p]))) return rc;
+    }
     int nt_max = 0;
     std::vector<fd_state> st(nprob);
     std::vector<int32_t> bstart(nprob + 1, 0);
     for (int p = 0; p < nprob; ++p) {
         if ((rc = make_plan(G[p], &probs[p].acq, true, s, sc, &P[p]))) return rc;
-        const size_t fb = G[p].ncell * dsize(G[p].dtype);
+        const size_t fb = G[p].ncell_pad * dsize(G[p].dtype);
         HIPCHK(sc.get(&st[p].u_a, fb));
         HIPCHK(sc.get(&st[p].u_b, fb));
-        HIPCHK(sc.get(&st[p].acc, G[p].ncell * dsize(G[p].acc_dtype)));
+        HIPCHK(sc.get(&st[p].acc, G[p].ncell_pad * dsize(G[p].acc_dtype)));
         HIPCHK(sc.get(&st[p].residual, (size_t)probs[p].nt * probs[p].acq.nrec * dsize(G[p].dtype)));
         HIPCHK(hipMemsetAsync(st[p].u_a, 0, fb, s));
         HIPCHK(hipMemsetAsync(st[p].u_b, 0, fb, s));
-        HIPCHK(hipMemsetAsync(st[p].acc, 0, G[p].ncell * dsize(G[p].acc_dtype), s));
+        HIPCHK(hipMemsetAsync(st[p].acc, 0, G[p].ncell_pad * dsize(G[p].acc_dtype), s));
         bstart[p + 1] = bstart[p] + P[p].nblk;
         nt_max = std::max(nt_max, probs[p].nt);
     }
@@ -1533,7 +1539,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         const fd_problem& q = probs[p];
         void *prev = st[p].u_a, *cur = st[p].u_b;
         for (int n = 0; n < nfw; ++n) {
-            fdw::StepArgs a = base_args(G[p], P[p], q.c, q.dt);
+            fdw::StepArgs a = base_args(G[p], P[p], cp[p], q.dt);
             a.blk_off = P[p].groups[0].d_off;
             a.grp = P[p].groups[0].d_grp;
             a.ev = P[p].groups[0].d_ev;
@@ -1558,7 +1564,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         void *vj = up, *vn = ul;
         for (int i = 0; i < nbw; ++i) {
             const int j = q.nt - 1 - i;
-            fdw::StepArgs a = base_args(G[p], P[p], q.c, q.dt);
+            fdw::StepArgs a = base_args(G[p], P[p], cp[p], q.dt);
             a.blk_off = P[p].groups[0].d_off;
             a.grp = P[p].groups[0].d_grp;
             a.ev = P[p].groups[0].d_ev;
@@ -1687,7 +1693,7 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         void *up = nullptr, *ul = nullptr;
         final_levels(st[p].u_a, st[p].u_b, q.nt, &up, &ul);
         HIPCHK(fdw::launch_terminal(G[p].dtype, G[p].acc_dtype, P[p].nuniq, P[p].d_ucell, P[p].d_uoff,
-                                    P[p].d_uidx, P[p].d_ushot, 0, 1, G[p].ncell, q.c, 0, q.dt * q.dt,
+                                    P[p].d_uidx, P[p].d_ushot, 0, 1, G[p].ncell_pad, cp[p], 0, q.dt * q.dt,
                                     ul, up, st[p].acc,
                                     (const char*)st[p].residual +
                                         (size_t)(q.nt - 1) * q.acq.nrec * dsize(G[p].dtype),
@@ -1703,8 +1709,18 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
     }
     for (int p = 0; p < nprob; ++p) {
         const fd_problem& q = probs[p];
-        HIPCHK(fdw::launch_finalize(G[p].dtype, G[p].acc_dtype, G[p].ncell, st[p].acc, q.c, 1.0 / q.k,
-                                    q.grad_c, s));
+        if (G[p].pitch == G[p].n2) {
+            HIPCHK(fdw::launch_finalize(G[p].dtype, G[p].acc_dtype, G[p].ncell, st[p].acc, q.c, 1.0 / q.k,
+                                        q.grad_c, s));
+        } else {   // finalise in the padded layout, then copy the rows out
+            const size_t es = dsize(G[p].dtype);
+            void* t = nullptr;
+            HIPCHK(sc.get(&t, G[p].ncell_pad * es));
+            HIPCHK(fdw::launch_finalize(G[p].dtype, G[p].acc_dtype, G[p].ncell_pad, st[p].acc, cp[p], 1.0 / q.k,
+                                        t, s));
+            if ((rc = copy_rows(q.grad_c, G[p].n2, t, G[p].pitch, es, (int64_t)G[p].n0 * G[p].n1, G[p].n2, s)))
+                return rc;
+        }
         double ss = 0.0;
         if ((rc = misfit_sum(G[p].dtype, st[p].residual, nullptr, nullptr, (int64_t)q.nt * q.acq.nrec, s,
                              sc, &ss)))
