@@ -715,23 +715,51 @@ def copy_probe(torch, nbytes=1 << 30, reps=5):
 
 
 def timed(args, torch, one_step):
+    """Runs the warm-up steps, then times the steps, within wall budgets: warm-up stops
+    once its time passes --warmup-budget-s (at least one step runs), and no timed step
+    starts once the elapsed time plus the slowest step so far would pass --budget-s (at
+    least one step is timed).  args.steps and args.warmup are set to the counts actually
+    run (the requested ones stay in args.steps_requested / args.warmup_requested), so
+    every figure derived from args.steps counts the steps that were timed."""
+    args.steps_requested, args.warmup_requested = args.steps, args.warmup
+    w0 = time.perf_counter()
+    done = 0
     for i in range(args.warmup):
         one_step(False)
+        done += 1
         log(f"warmup step {i + 1}/{args.warmup} done")
+        if time.perf_counter() - w0 > args.warmup_budget_s:
+            break
+    args.warmup = done
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    done, slowest = 0, 0.0
     for i in range(args.steps):
+        s0 = time.perf_counter()
         one_step(True)
+        torch.cuda.synchronize()
+        slowest = max(slowest, time.perf_counter() - s0)
+        done += 1
         log(f"timed step {i + 1}/{args.steps} done")
+        if time.perf_counter() - t0 + slowest > args.budget_s:
+            break
     torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    elapsed = time.perf_counter() - t0
+    if done < args.steps:
+        log(f"time budget {args.budget_s:.0f} s reached: {done} of {args.steps} steps timed")
+    args.steps = done
+    return elapsed
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--budget-s", type=float, default=120.0,
+                    help="wall budget of the timed steps: no step starts that would pass it")
+    ap.add_argument("--warmup-budget-s", type=float, default=20.0,
+                    help="warm-up stops once it has taken this long (at least one step runs)")
     ap.add_argument("--workload", default="layered3d",
                     choices=["layered3d", "layered2d", "shots3d", "shots2d", "problems2d", "vd3d", "tato2d",
                              "autograd3d", "fwi3d"])
@@ -784,11 +812,12 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "steps_requested": args.steps_requested,
+        "warmup_requested": args.warmup_requested,
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": (round(value / PAPER_SAME_WORKLOAD[args.workload], 3)
-                        if args.workload in PAPER_SAME_WORKLOAD and not args.nt and not args.n else None),
+        "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": cfg,
@@ -808,6 +837,9 @@ def main():
             "copy_probe_gbs": copy_probe(torch),
         },
     }
+    if args.workload in PAPER_SAME_WORKLOAD and not args.nt and not args.n:
+        out["context"] = {"paper_a100_gcell_updates_per_s": PAPER_SAME_WORKLOAD[args.workload],
+                          "note": "another machine and the paper's own code: context, not a baseline"}
     if accuracy is not None:
         out["accuracy"] = accuracy
     if "_cpu_baseline" in cfg:

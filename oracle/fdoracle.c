@@ -176,6 +176,49 @@ static double* coef_from_speed(const grid_t* g, const double* c, double dt)
     return coef;
 }
 
+/* Mass-term kernel of one time interval (Eq. kernel2 in the parameter m = 1/c^2, its
+ * time derivatives as differences of consecutive levels): for a level pair
+ * (a^{n+1}, a^n) of one field, K(a,a)_i gains -(a^{n+1} - a^n)_i^2. */
+static void kernel_interval(long N, const double* a_next, const double* a_cur, double* K)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < N; ++i) {
+        const double d = a_next[i] - a_cur[i];
+        K[i] -= d * d;
+    }
+}
+
+/* The forward problem solved forward in time from two zero levels.  traces
+ * [nt][nrec], hist [(nt+1)][ncell] (levels 0..nt), last2 [2][ncell] (u^{nt-1}, u^nt)
+ * and Kuu [ncell] (K(u,u) over the nt intervals [n, n+1], added to what it holds)
+ * may each be NULL. */
+static int forward_solve(const grid_t* g, const double* coef, int nt, int nsrc, const long* src,
+                         const double* wavelet, int nrec, const long* rec, double* traces,
+                         double* hist, double* last2, double* Kuu)
+{
+    double* um = calloc(g->ncell, sizeof(double));   /* u^{n-1} */
+    double* u0 = calloc(g->ncell, sizeof(double));   /* u^n     */
+    double* up = calloc(g->ncell, sizeof(double));   /* u^{n+1} */
+    if (!um || !u0 || !up) { free(um); free(u0); free(up); return -2; }
+    const double vol = inv_cell_volume(g);
+    if (hist) memset(hist, 0, sizeof(double) * g->ncell);   /* level 0 */
+    for (int n = 0; n < nt; ++n) {
+        propagate_step(g, coef, um, u0, up);
+        add_point_forces(coef, up, nsrc, src, wavelet + (long)n * nsrc, vol);
+        if (traces)
+            for (int q = 0; q < nrec; ++q) traces[(long)n * nrec + q] = up[rec[q]];
+        if (hist) memcpy(hist + (long)(n + 1) * g->ncell, up, sizeof(double) * g->ncell);
+        if (Kuu) kernel_interval(g->ncell, up, u0, Kuu);
+        double* t = um; um = u0; u0 = up; up = t;
+    }
+    if (last2) {
+        memcpy(last2, um, sizeof(double) * g->ncell);
+        memcpy(last2 + g->ncell, u0, sizeof(double) * g->ncell);
+    }
+    free(um); free(u0); free(up);
+    return 0;
+}
+
 /* Forward solve.  traces [nt][nrec] (may be NULL); hist [(nt+1)][ncell] holds
  * levels 0..nt (may be NULL); last2 [2][ncell] receives u^{nt-1}, u^nt (may be
  * NULL). */
@@ -188,26 +231,10 @@ int orc_forward(int ndim, const long* shape, double dx, int r, const double* a,
     grid_t g;
     if (make_grid(&g, ndim, shape, dx, r, a) || nt < 1) return -1;
     double* coef = coef_from_speed(&g, c, dt);
-    double* um = calloc(g.ncell, sizeof(double));   /* u^{n-1} */
-    double* u0 = calloc(g.ncell, sizeof(double));   /* u^n     */
-    double* up = calloc(g.ncell, sizeof(double));   /* u^{n+1} */
-    if (!coef || !um || !u0 || !up) { free(coef); free(um); free(u0); free(up); return -2; }
-    const double vol = inv_cell_volume(&g);
-    if (hist) memset(hist, 0, sizeof(double) * g.ncell);   /* level 0 */
-    for (int n = 0; n < nt; ++n) {
-        propagate_step(&g, coef, um, u0, up);
-        add_point_forces(coef, up, nsrc, src, wavelet + (long)n * nsrc, vol);
-        if (traces)
-            for (int q = 0; q < nrec; ++q) traces[(long)n * nrec + q] = up[rec[q]];
-        if (hist) memcpy(hist + (long)(n + 1) * g.ncell, up, sizeof(double) * g.ncell);
-        double* t = um; um = u0; u0 = up; up = t;   /* delete u^{n-1} */
-    }
-    if (last2) {
-        memcpy(last2, um, sizeof(double) * g.ncell);
-        memcpy(last2 + g.ncell, u0, sizeof(double) * g.ncell);
-    }
-    free(coef); free(um); free(u0); free(up);
-    return 0;
+    if (!coef) return -2;
+    const int rc = forward_solve(&g, coef, nt, nsrc, src, wavelet, nrec, rec, traces, hist, last2, NULL);
+    free(coef);
+    return rc;
 }
 
 /* J = dt/2 sum (traces - obs)^2 in index order; resid (may be NULL) = traces - obs. */
@@ -394,20 +421,57 @@ int orc_exact_gradient_ckpt(int ndim, const long* shape, double dx, int r, const
     return isnan(Jv) ? -2 : 0;
 }
 
-/* Memory-efficient mixed-kernel computation, paper Alg. 1, in the paper's
- * order: forward solve with adjoint force, cost and kernel increments; scale
- * the stored adjoint forces by k; superposed solve backwards in time with
- * kernel increments; return the cost and the approximate gradient.
+/* The superposed problem solved backward in time (Sec. 4, Eq. superposedPDE: the
+ * same operator as the forward problem, driven by the superposed force of Eq.
+ * superposedforce, f^s = f + k fdag, with fdag of Eq. adjointSource1):
+ *   v^{j-1} = 2 v^j - v^{j+1} + coef (L v^j + f^j + k fdag^j),  j = nt-1..1,
+ * from the end levels v^nt (v_hi) and v^{nt-1} (v_lo), which the call overwrites.
+ * f^j is the source term of level j (wavelet row j over the cell volume), fdag^j the
+ * adjoint force of level j (row j-1 of fdag [nt][nrec], injected without a volume
+ * factor).  Kvv [ncell] gains K(v,v) over all nt intervals [j-1, j], j = nt..1. */
+static int superposed_solve(const grid_t* g, const double* coef, int nt, int nsrc, const long* src,
+                            const double* wavelet, int nrec, const long* rec, const double* fdag,
+                            double k, double* v_hi, double* v_lo, double* Kvv)
+{
+    double* buf = malloc(sizeof(double) * g->ncell);
+    if (!buf) return -2;
+    const double vol = inv_cell_volume(g);
+    double* vp = v_hi;   /* v^{j+1} */
+    double* v0 = v_lo;   /* v^j     */
+    double* vm = buf;    /* v^{j-1} */
+    kernel_interval(g->ncell, vp, v0, Kvv);   /* [nt-1, nt] */
+    for (int j = nt - 1; j >= 1; --j) {
+        propagate_step(g, coef, vp, v0, vm);
+        add_point_forces(coef, vm, nsrc, src, wavelet + (long)j * nsrc, vol);
+        add_point_forces(coef, vm, nrec, rec, fdag + (long)(j - 1) * nrec, k);
+        kernel_interval(g->ncell, v0, vm, Kvv);   /* [j-1, j] */
+        double* t = vp; vp = v0; v0 = vm; vm = t;
+    }
+    free(buf);
+    return 0;
+}
+
+/* The memory-efficient sensitivity of Sec. 4 (Alg. 1) at factor k, assembled from
+ * its equations:
+ *   1. the forward problem with K(u,u), the kernel of the forward field with itself
+ *      (it needs no stored history: each interval is added as the solve passes it);
+ *   2. the cost (Eq. cost1) and the adjoint force fdag^n = -(u^n(x_r) - obs^n_r)/dt
+ *      (Eq. adjointSource1);
+ *   3. the superposed field v = u + k mu (mu the adjoint field), which obeys the
+ *      forward operator with the force f + k fdag (Eqs. superposedPDE,
+ *      superposedforce) and is solved backward in time from its end levels with
+ *      K(v,v) accumulated on the way;
+ *   4. the mixed kernel of Eq. superposedkernel, K~ = (K(v,v) - K(u,u)) / (2k), which
+ *      approximates K(u,mu) = dJ/dm (Eq. superposedkernel1 without its k^2 term),
+ *      and dJ/dc = -(2/c^3) dJ/dm (m = 1/c^2).
+ * Kernel of a level sequence a with itself: K(a,a)_i = -sum_{n=0}^{nt-1} (a^{n+1} -
+ * a^n)_i^2 (Eq. kernel2, mass term), over the same nt intervals for u and v.
  *
- * Kernel in the parameter m = 1/c^2 for a pair of level sequences (a, b):
- *   K(a, b)_i = -sum_{n=0}^{nt-1} (a^{n+1} - a^n)_i (b^{n+1} - b^n)_i,
- * and the approximation (paper Eq. superposedkernel)
- *   dJ/dm ~ (K(v, v) - K(u, u)) / (2k),  v = u + k mu (paper Sec. 4).
- *
- * The superposed end levels are v^nt = u^nt and v^{nt-1} = u^{nt-1} +
- * k coef fdag^nt at the receivers: the exact-adjoint end level mu^{nt-1}
- * = coef fdag^nt is kept, so that v = u + k mu holds level by level.
- * traces [nt][nrec] may be NULL. */
+ * End levels of v: the adjoint field's end conditions are homogeneous (Eq.
+ * ICadjoint), so the superposed end state is the forward one (Sec. 4); discretely the
+ * adjoint recursion started from mu^{nt+1} = mu^nt = 0 has mu^{nt-1} = coef fdag^nt at
+ * the receivers, so v^nt = u^nt and v^{nt-1} = u^{nt-1} + k coef fdag^nt, which keeps
+ * v = u + k mu level by level.  traces [nt][nrec] may be NULL. */
 int orc_superposition(int ndim, const long* shape, double dx, int r, const double* a,
                       const double* c, double dt, int nt,
                       int nsrc, const long* src, const double* wavelet,
@@ -417,69 +481,33 @@ int orc_superposition(int ndim, const long* shape, double dx, int r, const doubl
     grid_t g;
     if (make_grid(&g, ndim, shape, dx, r, a) || nt < 1 || k == 0.0) return -1;
     const long N = g.ncell;
-    const double vol = inv_cell_volume(&g);
     double* coef = coef_from_speed(&g, c, dt);
-    double* Kt = calloc(N, sizeof(double));                   /* K~ */
-    double* um = calloc(N, sizeof(double));
-    double* u0 = calloc(N, sizeof(double));
-    double* up = calloc(N, sizeof(double));
-    double* fdag = calloc((size_t)nt * nrec, sizeof(double)); /* row n-1: level n */
-    if (!coef || !Kt || !um || !u0 || !up || !fdag) {
-        free(coef); free(Kt); free(um); free(u0); free(up); free(fdag);
-        return -2;
-    }
-    double cost = 0.0;
+    double* Kuu = calloc(N, sizeof(double));
+    double* Kvv = calloc(N, sizeof(double));
+    double* ends = malloc(sizeof(double) * 2 * N);                 /* u^{nt-1}, u^nt */
+    double* tr = malloc(sizeof(double) * ((size_t)nt * nrec + 1));
+    double* fdag = malloc(sizeof(double) * ((size_t)nt * nrec + 1)); /* row n-1: level n */
+    int rc = (!coef || !Kuu || !Kvv || !ends || !tr || !fdag) ? -2 : 0;
 
-    /* forward in time: solve, adjoint force, cost, -K(u,u) increment */
-    for (int n = 0; n < nt; ++n) {
-        propagate_step(&g, coef, um, u0, up);
-        add_point_forces(coef, up, nsrc, src, wavelet + (long)n * nsrc, vol);
-        double inc = 0.0;
-        for (int q = 0; q < nrec; ++q) {
-            double rho = up[rec[q]] - obs[(long)n * nrec + q];
-            if (traces) traces[(long)n * nrec + q] = up[rec[q]];
-            fdag[(long)n * nrec + q] = -rho / dt;
-            inc += rho * rho;
-        }
-        cost += 0.5 * dt * inc;
+    /* 1. forward problem and K(u,u) */
+    if (!rc) rc = forward_solve(&g, coef, nt, nsrc, src, wavelet, nrec, rec, tr, NULL, ends, Kuu);
+    if (!rc) {
+        /* 2. cost and adjoint force */
+        const double cost = orc_misfit(nt, nrec, dt, tr, obs, fdag);
+        for (long q = 0; q < (long)nt * nrec; ++q) fdag[q] = -fdag[q] / dt;
+        if (J) *J = cost;
+        if (traces) memcpy(traces, tr, sizeof(double) * (size_t)nt * nrec);
+        /* 3. superposed field from v^{nt-1} = u^{nt-1} + k coef fdag^nt, v^nt = u^nt */
+        add_point_forces(coef, ends, nrec, rec, fdag + (long)(nt - 1) * nrec, k);
+        rc = superposed_solve(&g, coef, nt, nsrc, src, wavelet, nrec, rec, fdag, k, ends + N, ends, Kvv);
+    }
+    if (!rc) {
+        /* 4. mixed kernel and the gradient in c */
         for (long i = 0; i < N; ++i) {
-            double du = up[i] - u0[i];
-            Kt[i] -= -du * du;          /* K~ <- K~ - K(u,u) increment */
+            const double dJdm = (Kvv[i] - Kuu[i]) / (2.0 * k);
+            grad_c[i] = -2.0 / (c[i] * c[i] * c[i]) * dJdm;
         }
-        double* t = um; um = u0; u0 = up; up = t;
     }
-    /* now um = u^{nt-1}, u0 = u^nt */
-
-    /* scale the adjoint forces: fdag <- k fdag */
-    for (long i = 0; i < (long)nt * nrec; ++i) fdag[i] *= k;
-
-    /* superposed end levels: v^{nt} = u^{nt}, v^{nt-1} = u^{nt-1} + coef k fdag^{nt} */
-    double* vp = u0;   /* v^{j+1} */
-    double* v0 = um;   /* v^j     */
-    double* vm = up;   /* v^{j-1} */
-    add_point_forces(coef, v0, nrec, rec, fdag + (long)(nt - 1) * nrec, 1.0);
-    for (long i = 0; i < N; ++i) {
-        double dv = vp[i] - v0[i];
-        Kt[i] += -dv * dv;              /* interval [nt-1, nt] of K(v,v) */
-    }
-
-    /* backward in time: superposed solve with f^j + k fdag^j, +K(v,v) increment */
-    for (int j = nt - 1; j >= 1; --j) {
-        propagate_step(&g, coef, vp, v0, vm);
-        add_point_forces(coef, vm, nsrc, src, wavelet + (long)j * nsrc, vol);
-        add_point_forces(coef, vm, nrec, rec, fdag + (long)(j - 1) * nrec, 1.0);
-        for (long i = 0; i < N; ++i) {
-            double dv = v0[i] - vm[i];
-            Kt[i] += -dv * dv;          /* interval [j-1, j] */
-        }
-        double* t = vp; vp = v0; v0 = vm; vm = t;
-    }
-
-    for (long i = 0; i < N; ++i) {
-        double dJdm = Kt[i] / (2.0 * k);
-        grad_c[i] = -2.0 / (c[i] * c[i] * c[i]) * dJdm;
-    }
-    if (J) *J = cost;
-    free(coef); free(Kt); free(um); free(u0); free(up); free(fdag);
-    return 0;
+    free(coef); free(Kuu); free(Kvv); free(ends); free(tr); free(fdag);
+    return rc;
 }

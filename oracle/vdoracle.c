@@ -118,6 +118,56 @@ static double vinv_volume(const vgrid_t* g)
     return 1.0 / v;
 }
 
+/* sum over the faces of cell i of dh/db_i * (a_j - a_i)(c_j - c_i) for two fields a, c. */
+static double face_term(const vgrid_t* g, const double* b, const double* a, const double* c, long i);
+
+/* The two kernel terms of one field with itself (Eqs. kernel1/kernel2 in discrete
+ * form): Km gains the mass term of the interval (a^{n+1}, a^n), sum of squared level
+ * differences; Kb gains the stiffness term of level a^n, sum over the faces of dh/db
+ * times the squared face difference.  Either level may be NULL (that term is skipped). */
+static void vkernel_terms(const vgrid_t* g, const double* b, const double* a_next, const double* a_cur,
+                          const double* a_level, double* Km, double* Kb)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < g->ncell; ++i) {
+        if (a_next) Km[i] += (a_next[i] - a_cur[i]) * (a_next[i] - a_cur[i]);
+        if (a_level) Kb[i] += face_term(g, b, a_level, a_level, i);
+    }
+}
+
+/* The forward problem forward in time from two zero levels.  traces [nt][nrec], hist
+ * [(nt+1)][ncell] (levels 0..nt), last2 [2][ncell] (u^{nt-1}, u^nt) may be NULL; with
+ * Km and Kb (both or neither) the kernel terms of u with itself are added: the mass
+ * term over the nt intervals [n, n+1], the stiffness term over the levels 1..nt-1
+ * (level 0 is zero; level nt is shared with the superposed field, whose end level it
+ * is, so it cancels in their difference). */
+static int vd_forward_solve(const vgrid_t* g, const double* m, const double* b, double dt, int nt,
+                            int nsrc, const long* src, const double* wavelet, int nrec, const long* rec,
+                            double* traces, double* hist, double* last2, double* Km, double* Kb)
+{
+    double* um = calloc(g->ncell, sizeof(double));
+    double* u0 = calloc(g->ncell, sizeof(double));
+    double* up = calloc(g->ncell, sizeof(double));
+    if (!um || !u0 || !up) { free(um); free(u0); free(up); return -2; }
+    const double vol = vinv_volume(g);
+    if (hist) memset(hist, 0, sizeof(double) * g->ncell);
+    for (int n = 0; n < nt; ++n) {
+        vstep(g, m, b, dt, um, u0, up);
+        vforces(m, dt, up, nsrc, src, wavelet + (long)n * nsrc, vol);
+        if (traces)
+            for (int q = 0; q < nrec; ++q) traces[(long)n * nrec + q] = up[rec[q]];
+        if (hist) memcpy(hist + (long)(n + 1) * g->ncell, up, sizeof(double) * g->ncell);
+        if (Km) vkernel_terms(g, b, up, u0, n >= 1 ? u0 : NULL, Km, Kb);
+        double* t = um; um = u0; u0 = up; up = t;
+    }
+    if (last2) {
+        memcpy(last2, um, sizeof(double) * g->ncell);
+        memcpy(last2 + g->ncell, u0, sizeof(double) * g->ncell);
+    }
+    free(um); free(u0); free(up);
+    return 0;
+}
+
 /* Forward solve: traces [nt][nrec] (may be NULL), hist [(nt+1)][ncell] levels 0..nt
  * (may be NULL), last2 [2][ncell] u^{nt-1}, u^nt (may be NULL). */
 int orc_vd_forward(int ndim, const long* shape, double dx, const double* m, const double* b,
@@ -126,26 +176,7 @@ int orc_vd_forward(int ndim, const long* shape, double dx, const double* m, cons
 {
     vgrid_t g;
     if (make_vgrid(&g, ndim, shape, dx) || nt < 1) return -1;
-    double* um = calloc(g.ncell, sizeof(double));
-    double* u0 = calloc(g.ncell, sizeof(double));
-    double* up = calloc(g.ncell, sizeof(double));
-    if (!um || !u0 || !up) { free(um); free(u0); free(up); return -2; }
-    const double vol = vinv_volume(&g);
-    if (hist) memset(hist, 0, sizeof(double) * g.ncell);
-    for (int n = 0; n < nt; ++n) {
-        vstep(&g, m, b, dt, um, u0, up);
-        vforces(m, dt, up, nsrc, src, wavelet + (long)n * nsrc, vol);
-        if (traces)
-            for (int q = 0; q < nrec; ++q) traces[(long)n * nrec + q] = up[rec[q]];
-        if (hist) memcpy(hist + (long)(n + 1) * g.ncell, up, sizeof(double) * g.ncell);
-        double* t = um; um = u0; u0 = up; up = t;
-    }
-    if (last2) {
-        memcpy(last2, um, sizeof(double) * g.ncell);
-        memcpy(last2 + g.ncell, u0, sizeof(double) * g.ncell);
-    }
-    free(um); free(u0); free(up);
-    return 0;
+    return vd_forward_solve(&g, m, b, dt, nt, nsrc, src, wavelet, nrec, rec, traces, hist, last2, NULL, NULL);
 }
 
 /* Adjoint sweep: mu^{nt} = mu^{nt+1} = 0, mu^{j-1} = 2 mu^j - mu^{j+1} +
@@ -238,16 +269,46 @@ int orc_vd_exact_gradient(int ndim, const long* shape, double dx, const double* 
     return rc;
 }
 
-/* Alg. 1 for both fields, step by step in the paper's order: the forward sweep
- * propagates u, records the residual and the adjoint force and accumulates
- * K_m(u,u) = sum_n (u^{n+1} - u^n)^2 over the intervals n = 0..nt-2 and
- * K_b(u,u) = sum_{n=1}^{nt-1} face_term(u, u); the superposed field starts from
- * v^nt = u^nt, v^{nt-1} = u^{nt-1} + k (dt^2/m) fdag^nt and runs backward with the
- * force f + k fdag, accumulating K_m(v,v) over the same intervals and K_b(v,v) over
- * the same levels; the last interval [nt-1, nt] enters both K_m sums through its
- * end levels.  Then
- *   dJ/dm ~ (K_m(u,u) - K_m(v,v)) / (2k),   dJ/db ~ -(dt^2/dx^2)(K_b(u,u) - K_b(v,v)) / (2k).
- */
+/* The superposed field v = u + k mu solved backward in time (Sec. 4, Eqs.
+ * superposedPDE2/superposedforce: the forward operator with the force f + k fdag) from
+ * its end levels v^nt (v_hi) and v^{nt-1} (v_lo), both overwritten:
+ *   v^{j-1} = 2 v^j - v^{j+1} + (dt^2/m)(L_b v^j + f^j + k fdag^j),  j = nt-1..1,
+ * f^j = wavelet row j over the cell volume, fdag^j = row j-1 of fdag at the receivers.
+ * Km, Kb gain the kernel terms of v with itself over the same intervals (all nt) and
+ * levels (1..nt-1) as the forward field's. */
+static int vd_superposed_solve(const vgrid_t* g, const double* m, const double* b, double dt, int nt,
+                               int nsrc, const long* src, const double* wavelet, int nrec, const long* rec,
+                               const double* fdag, double k, double* v_hi, double* v_lo, double* Km,
+                               double* Kb)
+{
+    double* buf = malloc(sizeof(double) * g->ncell);
+    if (!buf) return -2;
+    const double vol = vinv_volume(g);
+    double* vp = v_hi;   /* v^{j+1} */
+    double* v0 = v_lo;   /* v^j */
+    double* vm = buf;    /* v^{j-1} */
+    vkernel_terms(g, b, vp, v0, NULL, Km, Kb);   /* interval [nt-1, nt] */
+    for (int j = nt - 1; j >= 1; --j) {
+        vstep(g, m, b, dt, vp, v0, vm);
+        vforces(m, dt, vm, nsrc, src, wavelet + (long)j * nsrc, vol);
+        vforces(m, dt, vm, nrec, rec, fdag + (long)(j - 1) * nrec, k);
+        vkernel_terms(g, b, v0, vm, v0, Km, Kb);   /* interval [j-1, j], level j */
+        double* t = vp; vp = v0; v0 = vm; vm = t;
+    }
+    free(buf);
+    return 0;
+}
+
+/* The memory-efficient sensitivity of Sec. 4 (Alg. 1) for both material fields,
+ * from its equations: the forward problem with the kernel terms of u with itself,
+ * the cost (Eq. cost1) and adjoint force fdag = -(u - obs)/dt (Eq. adjointSource1),
+ * the superposed field v = u + k mu backward from v^nt = u^nt, v^{nt-1} = u^{nt-1} +
+ * k (dt^2/m) fdag^nt (the discrete adjoint's end levels are mu^nt = 0, mu^{nt-1} =
+ * (dt^2/m) fdag^nt) with the kernel terms of v with itself, and the mixed kernel of Eq.
+ * superposedkernel per term.  With the mass term written as a sum of squares
+ * (Km = -K, so its difference changes sign) and the stiffness term carrying the
+ * scheme's dt^2/dx^2:
+ *   dJ/dm ~ (Km(u,u) - Km(v,v)) / (2k),   dJ/db ~ -(dt^2/dx^2)(Kb(u,u) - Kb(v,v)) / (2k). */
 int orc_vd_superposition(int ndim, const long* shape, double dx, const double* m, const double* b,
                          double dt, int nt, int nsrc, const long* src, const double* wavelet,
                          int nrec, const long* rec, const double* obs, double k, double* grad_m,
@@ -256,65 +317,36 @@ int orc_vd_superposition(int ndim, const long* shape, double dx, const double* m
     vgrid_t g;
     if (make_vgrid(&g, ndim, shape, dx) || nt < 1 || !(k != 0.0)) return -1;
     const long N = g.ncell;
-    double* um = calloc(N, sizeof(double));
-    double* u0 = calloc(N, sizeof(double));
-    double* up = calloc(N, sizeof(double));
-    double* km = calloc(N, sizeof(double));   /* K_m(u,u) - K_m(v,v) */
-    double* kb = calloc(N, sizeof(double));   /* K_b(u,u) - K_b(v,v) */
-    double* fd = malloc(sizeof(double) * (size_t)nt * (nrec > 0 ? nrec : 1));
-    if (!um || !u0 || !up || !km || !kb || !fd) {
-        free(um); free(u0); free(up); free(km); free(kb); free(fd);
-        return -2;
-    }
-    const double vol = vinv_volume(&g);
-    double s = 0.0;
-    /* forward sweep */
-    for (int n = 0; n < nt; ++n) {
-        if (n >= 1)
-            for (long i = 0; i < N; ++i) kb[i] += face_term(&g, b, u0, u0, i);
-        vstep(&g, m, b, dt, um, u0, up);
-        vforces(m, dt, up, nsrc, src, wavelet + (long)n * nsrc, vol);
-        for (int q = 0; q < nrec; ++q) {
-            const double val = up[rec[q]];
-            if (traces_out) traces_out[(long)n * nrec + q] = val;
-            const double rho = val - obs[(long)n * nrec + q];
+    const size_t nq = (size_t)nt * (nrec > 0 ? nrec : 1);
+    double* kmu = calloc(N, sizeof(double));
+    double* kbu = calloc(N, sizeof(double));
+    double* kmv = calloc(N, sizeof(double));
+    double* kbv = calloc(N, sizeof(double));
+    double* ends = malloc(sizeof(double) * 2 * N);   /* u^{nt-1}, u^nt */
+    double* tr = malloc(sizeof(double) * nq);
+    double* fd = malloc(sizeof(double) * nq);
+    int rc = (!kmu || !kbu || !kmv || !kbv || !ends || !tr || !fd) ? -2 : 0;
+    if (!rc) rc = vd_forward_solve(&g, m, b, dt, nt, nsrc, src, wavelet, nrec, rec, tr, NULL, ends, kmu, kbu);
+    if (!rc) {
+        double s = 0.0;
+        for (long q = 0; q < (long)nt * nrec; ++q) {
+            const double rho = tr[q] - obs[q];
             s += rho * rho;
-            fd[(long)n * nrec + q] = -rho / dt;
+            fd[q] = -rho / dt;
         }
-        if (n < nt - 1)
-            for (long i = 0; i < N; ++i) km[i] += (up[i] - u0[i]) * (up[i] - u0[i]);
-        double* t = um; um = u0; u0 = up; up = t;
+        if (J) *J = 0.5 * dt * s;
+        if (traces_out) memcpy(traces_out, tr, sizeof(double) * (size_t)nt * nrec);
+        vforces(m, dt, ends, nrec, rec, fd + (long)(nt - 1) * nrec, k);   /* v^{nt-1} */
+        rc = vd_superposed_solve(&g, m, b, dt, nt, nsrc, src, wavelet, nrec, rec, fd, k, ends + N, ends,
+                                 kmv, kbv);
     }
-    if (J) *J = 0.5 * dt * s;
-    /* um = u^{nt-1}, u0 = u^nt.  Superposed end levels. */
-    double* vn = u0;   /* v^{j+1} */
-    double* vj = um;   /* v^j */
-    double* vm = up;   /* v^{j-1} */
-    {
-        /* the last interval: (u^nt - u^{nt-1})^2 - (v^nt - v^{nt-1})^2 */
-        double* vnm1 = malloc(sizeof(double) * N);
-        if (!vnm1) { free(um); free(u0); free(up); free(km); free(kb); free(fd); return -2; }
-        memcpy(vnm1, vj, sizeof(double) * N);
-        vforces(m, dt, vnm1, nrec, rec, fd + (long)(nt - 1) * nrec, k);
-        for (long i = 0; i < N; ++i)
-            km[i] += (vn[i] - vj[i]) * (vn[i] - vj[i]) - (vn[i] - vnm1[i]) * (vn[i] - vnm1[i]);
-        memcpy(vj, vnm1, sizeof(double) * N);
-        free(vnm1);
+    if (!rc) {
+        const double fac = dt * dt / (dx * dx);
+        for (long i = 0; i < N; ++i) {
+            grad_m[i] = (kmu[i] - kmv[i]) / (2.0 * k);
+            grad_b[i] = -fac * (kbu[i] - kbv[i]) / (2.0 * k);
+        }
     }
-    /* superposed backward sweep, j = nt-1..1 */
-    for (int j = nt - 1; j >= 1; --j) {
-        for (long i = 0; i < N; ++i) kb[i] -= face_term(&g, b, vj, vj, i);
-        vstep(&g, m, b, dt, vn, vj, vm);
-        vforces(m, dt, vm, nsrc, src, wavelet + (long)j * nsrc, vol);
-        vforces(m, dt, vm, nrec, rec, fd + (long)(j - 1) * nrec, k);
-        for (long i = 0; i < N; ++i) km[i] -= (vj[i] - vm[i]) * (vj[i] - vm[i]);
-        double* t = vn; vn = vj; vj = vm; vm = t;
-    }
-    const double fac = dt * dt / (dx * dx);
-    for (long i = 0; i < N; ++i) {
-        grad_m[i] = km[i] / (2.0 * k);
-        grad_b[i] = -fac * kb[i] / (2.0 * k);
-    }
-    free(um); free(u0); free(up); free(km); free(kb); free(fd);
-    return 0;
+    free(kmu); free(kbu); free(kmv); free(kbv); free(ends); free(tr); free(fd);
+    return rc;
 }
