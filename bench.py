@@ -46,12 +46,63 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def step_bytes(group, acc):
+PARTIAL_CYCLE = 16   # accumulating launches per partial-sum cycle (f32 fields, f64 accumulator)
+
+
+def acc_terms(l, count):
+    """Kernel terms of launch l of a sweep accumulating `count` intervals: 0 (none), 1
+    (its own interval, the last launch of an odd count) or 3 (its own and the one before,
+    odd l): the accumulator is touched by every other launch."""
+    if l < 0 or l >= count:
+        return 0
+    if l & 1:
+        return 3
+    return 1 if l == count - 1 else 0
+
+
+def part_mode(l, count):
+    """What accumulating launch l does with its terms when f32 partial sums are kept
+    (f32 fields, f64 accumulator): 'start' (write the partial sum), 'add' (read and write
+    it), 'flush' (read it, read and write the accumulator) or 'direct' (read and write
+    the accumulator only), in cycles of PARTIAL_CYCLE accumulating launches."""
+    i, total = l >> 1, (count + 1) >> 1
+    j = i % PARTIAL_CYCLE
+    if i == total - 1:
+        return "direct" if j == 0 else "flush"
+    if j == 0:
+        return "start"
+    return "flush" if j == PARTIAL_CYCLE - 1 else "add"
+
+
+def launch_bytes(group, acc, mode):
     """Algorithmic HBM bytes per cell of one fused step launch advancing `group` fields:
-    read u^n, u^{n-1} per field and c once, write u^{n+1} per field; a launch that adds
-    kernel terms also reads and writes the accumulator once.  Returns (with, without)."""
+    read u^n, u^{n-1} per field and c once, write u^{n+1} per field, plus what the launch
+    does with the accumulator (mode None: nothing; 'direct': read and write it) or with
+    the f32 partial sums (see part_mode)."""
+    base = 12 * group + 4
     a = 8 if acc == "f64" else 4
-    return 12 * group + 4 + 2 * a, 12 * group + 4
+    extra = {None: 0, "direct": 2 * a, "start": 4, "add": 8, "flush": 4 + 2 * a}[mode]
+    return base + extra
+
+
+def sweep_bytes(nt, group, acc, partials, nlaunch):
+    """Bytes per cell of the `nlaunch` step launches of one sweep accumulating nt - 1
+    intervals (nt launches forward, nt - 1 backward)."""
+    total = 0
+    for l in range(nlaunch):
+        terms = acc_terms(l, nt - 1)
+        mode = None if not terms else (part_mode(l, nt - 1) if partials else "direct")
+        total += launch_bytes(group, acc, mode)
+    return total
+
+
+def gradient_bytes(nt, group, acc, partials=None):
+    """Algorithmic bytes per cell of the step launches of one gradient (forward sweep of
+    nt launches, backward of nt - 1).  Partial sums are kept for f32 fields with an f64
+    accumulator (every workload of this bench runs f32 fields)."""
+    if partials is None:
+        partials = acc == "f64"
+    return sweep_bytes(nt, group, acc, partials, nt) + sweep_bytes(nt, group, acc, partials, nt - 1)
 
 
 def vd_step_bytes(acc):
@@ -62,18 +113,13 @@ def vd_step_bytes(acc):
     return 20 + 4 * a, 20 + 2 * a
 
 
-def accumulating_launches(nt):
-    """Launches of one sweep that touch the accumulator: each sweep accumulates nt - 1
-    intervals, two per launch on every other launch (one alone at the end of an odd
-    count), i.e. ceil((nt - 1) / 2) of them."""
-    return nt // 2
-
-
-def gradient_bytes(nt, fwd, bwd):
-    """Algorithmic bytes per cell of the step launches of one gradient: nt forward and
-    nt - 1 backward launches; fwd and bwd are (with, without) accumulator bytes."""
-    na = accumulating_launches(nt)
-    return (na * fwd[0] + (nt - na) * fwd[1]) + (na * bwd[0] + (nt - 1 - na) * bwd[1])
+def vd_gradient_bytes(nt, acc):
+    """Algorithmic bytes per cell of the variable-material step launches of one gradient:
+    the mass accumulator on every other launch (acc_terms), the stiffness one on all."""
+    w, wo = vd_step_bytes(acc)
+    fwd = sum(w if acc_terms(l, nt - 1) else wo for l in range(nt))
+    bwd = sum(w if acc_terms(l, nt - 1) else wo for l in range(nt - 1))
+    return fwd + bwd
 
 
 def make_single(args, torch, wl):
@@ -301,14 +347,15 @@ def run_single(args, np, torch, fdw, wl):
     if exact:
         # forward: one field per launch, no accumulator; backward: u and mu together with
         # the cross accumulator, one launch per shot and step
-        nof = step_bytes(1, args.acc)[1]
-        per_cell = gradient_bytes(p.nt, (nof, nof), step_bytes(2, args.acc))
+        # forward: one field per launch, no accumulator; backward: u and mu together
+        per_cell = p.nt * launch_bytes(1, args.acc, None) + sweep_bytes(p.nt, 2, args.acc, args.acc == "f64",
+                                                                        p.nt - 1)
         bytes_all = ncell * nshot * per_cell * args.steps
         bpu = per_cell / (2 * p.nt - 1)
     else:
         group = best["max_group"] or 1
         ngroups = math.ceil(nshot / group)
-        per_cell = gradient_bytes(p.nt, step_bytes(group, args.acc), step_bytes(group, args.acc))
+        per_cell = gradient_bytes(p.nt, group, args.acc)
         bytes_all = ncell * ngroups * per_cell * args.steps
         bpu = per_cell / (2 * p.nt - 1) / group
     cfg = {"workload": desc, "grid": list(p.shape), "nt": p.nt, "order": p.order, "shots": nshot,
@@ -388,7 +435,7 @@ def run_vd(args, np, torch, fdw, wl):
     upd = ncell * (2 * nt - 1)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    per_cell = gradient_bytes(nt, vd_step_bytes(args.acc), vd_step_bytes(args.acc))
+    per_cell = vd_gradient_bytes(nt, args.acc)
     bytes_all = ncell * per_cell * args.steps
     cfg = {"workload": desc, "grid": [n, n, n], "nt": nt, "order": 2, "shots": 1, "receivers": len(q["rec"]),
            "accumulator": args.acc, "method": "superposition", "k": k, "J": holder["J"],
@@ -473,7 +520,7 @@ def run_tato(args, np, torch, fdw, wl):
     upd = ncell * (2 * nt - 1)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    per_cell = gradient_bytes(nt, vd_step_bytes(args.acc), vd_step_bytes(args.acc))
+    per_cell = vd_gradient_bytes(nt, args.acc)
     bytes_all = ncell * per_cell * args.steps
     cfg = {"workload": desc, "grid": list(shape), "nt": nt, "order": 2, "shots": 1, "receivers": len(rec),
            "design_cells": int(np.prod(q["design_extent"])), "accumulator": args.acc,
@@ -527,7 +574,7 @@ def run_fwi(args, np, torch, fdw, wl):
     upd = ncell * (2 * nt - 1)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    per_cell = gradient_bytes(nt, vd_step_bytes(args.acc), vd_step_bytes(args.acc))
+    per_cell = vd_gradient_bytes(nt, args.acc)
     cfg = {"workload": desc, "grid": list(shape), "nt": nt, "order": 2, "shots": 1, "receivers": len(q["rec"]),
            "design_cells": ncell, "accumulator": args.acc, "method": "superposition", "k": loop.k,
            "objective": holder["C"], "objective_history": loop.history,
@@ -594,7 +641,7 @@ def run_autograd(args, np, torch, fdw, wl):
     diff = float(torch.linalg.vector_norm(g_ag - grad.double()) / torch.linalg.vector_norm(grad.double()))
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    per_cell = gradient_bytes(nt, step_bytes(1, args.acc), step_bytes(1, args.acc))
+    per_cell = gradient_bytes(nt, 1, args.acc)
     cfg = {"workload": desc, "grid": [n, n, n], "nt": nt, "order": p.order, "shots": 1, "receivers": len(p.rec),
            "accumulator": args.acc, "k": k, "J": holder["J"],
            "plain_call_gcell_updates_per_s": upd / plain_s / 1e9,
@@ -627,24 +674,41 @@ def run_problems(args, np, torch, fdw, wl):
     desc = f"problems2d: 16 layered problems, sides {sides[0]}..{sides[-1]}, f32 order-8 nt={nt}"
     log("workload:", desc)
     timings = []
+    # one batch plan (host work once), run per step on the current stream; with --graph
+    # the run is captured once and each step replays the graph
+    plan = fdw.BatchPlan(items, persistent=args.persistent, timing=fdw.fd_timing(), variant=args.variant or 1,
+                         acc_dtype=args.acc)
+    J = torch.zeros(len(items), dtype=torch.float64, device="cuda")
+    graph = None
+    if args.graph:
+        plan.run(J)   # warm-up outside the capture
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.run(J)
 
     def one_step(record):
-        t = fdw.fd_timing()
-        fdw.fd_adjoint_sensitivity_batched(items, graph=args.graph, persistent=args.persistent, timing=t,
-                                           variant=1, acc_dtype=args.acc)
+        if graph is not None:
+            graph.replay()
+        else:
+            plan.run(J)
         if record:
+            t = plan.timing()
             timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
 
     elapsed = timed(args, torch, one_step)
+    if not bool(torch.isfinite(J).all()):
+        raise RuntimeError("problems2d: a misfit is not finite")
     upd = ncell_all * (2 * nt - 1)
-    b = step_bytes(1, args.acc)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    per_cell = gradient_bytes(nt, b, b)
+    per_cell = gradient_bytes(nt, 1, args.acc)
     bytes_all = ncell_all * per_cell * args.steps
-    cfg = {"workload": desc, "sides": sides, "nt": nt, "order": 8, "problems": 16,
+    cfg = {"workload": desc, "sides": sides, "nt": nt, "order": 8, "problems": 16, "variant": args.variant or 1,
            "accumulator": args.acc, "graph": bool(args.graph), "persistent": bool(args.persistent),
-           "cell_updates_per_step": upd}
+           "cell_updates_per_step": upd, "plan": "one fd_batch_plan; steps run it"
+           + (" as a captured graph replay" if args.graph else " directly")}
+    plan.close()
     return (upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, per_cell / (2 * nt - 1)),
             probs[0], items[0].c, None)
 
@@ -837,6 +901,12 @@ def main():
             "copy_probe_gbs": copy_probe(torch),
         },
     }
+    if args.workload in ("layered3d", "layered2d", "autograd3d") and args.acc == "f64" and args.method == "superposition":
+        # the same throughput priced at the 24 B per cell update of the step without partial
+        # sums (every other launch reading and writing the f64 accumulator): what the
+        # partial sums save shows here, not in `frac`, which uses the bytes actually due
+        out["roofline"]["effective_gbs_at_24B"] = round(value * 24.0, 1)
+        out["roofline"]["effective_frac_at_24B"] = round(value * 24.0 / HBM_PEAK_GBS, 4)
     if args.workload in PAPER_SAME_WORKLOAD and not args.nt and not args.n:
         out["context"] = {"paper_a100_gcell_updates_per_s": PAPER_SAME_WORKLOAD[args.workload],
                           "note": "another machine and the paper's own code: context, not a baseline"}

@@ -158,7 +158,9 @@ double fd_cfl_limit(int32_t ndim, int32_t order);
  * acquisition takes from the stream-ordered pool of `stream`'s device, beyond the
  * caller's inputs and outputs (host-side arithmetic, no device work):
  *   wavefields 2 * nshots * ncell * sizeof(T), accumulator ncell * 8 (f64, the larger
- *   choice), residual rows nt * nrec * sizeof(T) — with ncell counted in rows padded to
+ *   choice), for f32 grids ncell * 4 of f32 partial sums of the kernel terms (which an
+ *   f64 accumulator takes in every 16th accumulating step), residual rows
+ *   nt * nrec * sizeof(T) — with ncell counted in rows padded to
  *   64 elements when the contiguous extent is not a multiple of 64, plus then a padded
  *   copy of c and a padded finalisation buffer — event tables of two launch plans
  *   (per-block offsets for every shot group, bounded with the smallest tile and one
@@ -304,13 +306,59 @@ int fd_sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, doub
 /* Alg. 1 for `nprob` independent problems of uneven sizes in lock-step: every time
  * step of all problems is one launch over the union of their tiles (problems that
  * have no step there skip it), the backward sweeps are aligned at their ends.  With
- * opts->graph each sweep is captured once into a hipGraph and replayed as one
- * launch; with opts->persistent each sweep is one cooperative launch whose resident
- * blocks walk all its steps with a grid barrier per step (captured in a graph too
- * when opts->graph is set and the runtime can capture it, else launched directly).
- * J_host [nprob] receives each problem's J.  Needs opts variant 0, 1 or 2. */
+ * opts->persistent each sweep is one cooperative launch whose resident blocks walk
+ * all its steps with a grid barrier per step.  This is a batch plan (below) created,
+ * run once and destroyed: with opts->graph the run is captured into a hipGraph and
+ * launched as one graph (a persistent run is launched directly if the runtime cannot
+ * capture a cooperative launch).  J_host [nprob] receives each problem's J;
+ * synchronises `stream`.  Needs opts variant 0, 1 or 2 (2D also 4 and 5).  FD_E_DEVICE
+ * if a persistent grid barrier wait timed out. */
 int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, double* J_host,
                                    const fd_opts* opts, void* stream);
+
+/* The batched call as a reusable plan whose run is graph-capturable (Alg. 1 per
+ * problem, as above).  The paper states the time per time step per source (Tab.
+ * timings); a plan amortises everything that needs the host across runs: a run
+ * issues kernel launches only.
+ *
+ * fd_batch_plan_create validates the problems (as fd_adjoint_sensitivity_batched),
+ * checks every speed field against the CFL limit once, builds the block
+ * decompositions, event tables and step-argument tables, allocates the state of
+ * every problem (two wavefields, the accumulator, the residual rows; rows padded to
+ * 64 elements where the contiguous extent needs it) stream-ordered on `stream`, and
+ * synchronises `stream` once.  *plan receives the plan (NULL on error).  The plan
+ * keeps the device pointers of every problem (c, wavelet, observed, grad_c, traces):
+ * they must stay valid, at the same addresses, until the plan is destroyed.  The host
+ * arrays of the acquisitions (cells, shot tags) are read during this call only.
+ * fd_opts: variant 0, 1 or 2, acc_dtype, persistent, barrier_timeout_us, timing (a
+ * run then records HIP events around both sweeps; read them with fd_batch_timing);
+ * graph is ignored (the caller captures runs itself).
+ *
+ * fd_batch_run enqueues one gradient of every problem on `stream`: state zeroed by
+ * kernels, each problem's current c copied into the padded layout where needed, the
+ * forward sweeps, the terminal hand-overs, the backward sweeps, grad_c, and
+ * J DEVICE [nprob] doubles (J[p] = dt_p/2 sum of problem p's squared residuals,
+ * reduced in fixed order).  It allocates nothing, copies nothing to or from the host,
+ * records no memset and does not synchronise, so a stream capture of it is a graph
+ * that may be replayed: each replay reads the values c, wavelet and observed hold
+ * then.  The CFL check of fd_batch_plan_create is not repeated: a c that has become
+ * unstable since gives non-finite values.  With opts.persistent every J of the run
+ * is NaN if a grid barrier wait timed out.  Runs of one plan share its state: they
+ * must not overlap (one stream, or ordered by the caller).  FD_E_ARG for a null plan
+ * or J; a failed launch gives FD_E_DEVICE.
+ *
+ * fd_batch_timing waits for the last run's second sweep and fills *timing with the
+ * device time of its two sweeps (FD_E_ARG if the plan was made without timing).
+ *
+ * fd_batch_plan_destroy releases the plan's device memory stream-ordered on `stream`
+ * (no run of it may be pending on another stream) and the plan itself; NULL is a
+ * no-op. */
+typedef struct fd_batch_plan fd_batch_plan;
+int fd_batch_plan_create(const fd_problem* probs, int32_t nprob, const fd_opts* opts, void* stream,
+                         fd_batch_plan** plan);
+int fd_batch_run(fd_batch_plan* plan, double* J, void* stream);
+int fd_batch_timing(fd_batch_plan* plan, fd_timing* timing);
+int fd_batch_plan_destroy(fd_batch_plan* plan, void* stream);
 
 /* Source-free steps (test hook for closed-form solutions): on entry u_prev, u_cur DEVICE
  * [ncell] hold levels -1 and 0; on return they hold levels nsteps-1 and nsteps.

@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass
+from typing import Optional
 
 import torch
 
@@ -46,6 +47,8 @@ class KPoint:
     k: float
     gap: float        # ||g64(k) - g_exact|| / ||g_exact||
     fp32_err: float   # ||g32(k) - g64(k)|| / ||g64(k)||
+    g64: Optional[torch.Tensor] = None   # with keep=True: the two device gradients at k
+    g32: Optional[torch.Tensor] = None
 
 
 def _rel(a: torch.Tensor, b: torch.Tensor) -> float:
@@ -55,11 +58,12 @@ def _rel(a: torch.Tensor, b: torch.Tensor) -> float:
 
 
 def sweep_k(c: torch.Tensor, dx: float, order: int, src, wavelet: torch.Tensor, rec, dt: float, nt: int,
-            observed: torch.Tensor, ks, tol: float = 1e-4, shots=None, **opts):
+            observed: torch.Tensor, ks, tol: float = 1e-4, shots=None, keep: bool = False, **opts):
     """Decade sweep of k (the paper's calibration rule).  c, wavelet and observed are
     device tensors (any float dtype; they are run in both f32 and f64).  Returns
     (points, k_best): one KPoint per k in ascending order, and the smallest k whose
-    fp32_err <= tol (None if none qualifies)."""
+    fp32_err <= tol (None if none qualifies).  With keep the points also hold the f64
+    and f32 gradients, and the exact gradient is returned third."""
     c64, w64, o64 = c.double(), wavelet.double(), observed.double()
     c32, w32, o32 = c.float(), wavelet.float(), observed.float()
     g_ex, _ = fdw.fd_adjoint_exact(c64, dx, order, src, w64, rec, dt, nt, o64, shots=shots, **opts)
@@ -67,6 +71,6 @@ def sweep_k(c: torch.Tensor, dx: float, order: int, src, wavelet: torch.Tensor, 
     for k in sorted(float(x) for x in ks):
         g64, _ = fdw.fd_adjoint_sensitivity(c64, dx, order, src, w64, rec, dt, nt, o64, k, shots=shots, **opts)
         g32, _ = fdw.fd_adjoint_sensitivity(c32, dx, order, src, w32, rec, dt, nt, o32, k, shots=shots, **opts)
-        points.append(KPoint(k, _rel(g64, g_ex), _rel(g32, g64)))
+        points.append(KPoint(k, _rel(g64, g_ex), _rel(g32, g64), g64 if keep else None, g32 if keep else None))
     best = next((p.k for p in points if p.fp32_err <= tol), None)
-    return points, best
+    return (points, best, g_ex) if keep else (points, best)

@@ -122,16 +122,17 @@ static hipError_t launch_multi_rt(int ndim, int variant, const StepArgs* t, cons
         switch (variant) {
         case 1: return launch_multi_one<R, T, AT, 2, 64, 1, 1, 1>(t, bs, nprob, total, s);
         case 2: return launch_multi_one<R, T, AT, 2, 64, 1, 1, 2>(t, bs, nprob, total, s);
+        case 4: return launch_multi_one<R, T, AT, 2, 128, 1, 1, 2>(t, bs, nprob, total, s);
+        case 5: return launch_multi_one<R, T, AT, 2, 256, 1, 1, 1>(t, bs, nprob, total, s);
         }
     }
     return hipErrorInvalidValue;
 }
 
-// Resident blocks per CU the persistent grid may use: at most what the occupancy
-// calculator reports and never above this cap (the dispatcher's per-CU workgroup
-// limit can be lower than the wave-based occupancy for one-wave blocks).
+// Resident blocks per CU of the persistent grid: the smallest of what the occupancy
+// calculator allows for the kernel's registers and LDS, the device's limit of resident
+// blocks per CU, and kPersistentBlocksPerCU.
 constexpr int kPersistentBlocksPerCU = 8;
-
 template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
 static hipError_t launch_persistent_one(const StepArgs* t, const int32_t* bs, int nprob, int total,
                                         int nsteps, unsigned* bar, long long timeout, hipStream_t s,
@@ -139,12 +140,16 @@ static hipError_t launch_persistent_one(const StepArgs* t, const int32_t* bs, in
 {
     auto kern = step_persistent_kernel<R, T, AT, NDIM, TZ, TY, RY, VZ>;
     const int threads = TZ * (TY / RY);
-    int per_cu = 0, dev = 0, cus = 0;
+    int per_cu = 0, dev = 0, cus = 0, slots = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
     if (e != hipSuccess) return e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    int grid = std::min(per_cu, kPersistentBlocksPerCU) * cus;
+    if ((e = hipDeviceGetAttribute(&slots, hipDeviceAttributeMaxBlocksPerMultiProcessor, dev)) != hipSuccess)
+        return e;
+    if (slots > 0) per_cu = std::min(per_cu, slots);
+    per_cu = std::min(per_cu, kPersistentBlocksPerCU);
+    int grid = per_cu * cus;
     grid = std::min(grid, ((total + 7) / 8) * 8);
     grid = (grid / 8) * 8;
     if (grid < 8) return hipErrorInvalidConfiguration;
@@ -168,6 +173,8 @@ static hipError_t launch_persistent_rt(int ndim, int variant, const StepArgs* t,
         switch (variant) {
         case 1: return launch_persistent_one<R, T, AT, 2, 64, 1, 1, 1>(t, bs, nprob, total, nsteps, bar, to, s, g);
         case 2: return launch_persistent_one<R, T, AT, 2, 64, 1, 1, 2>(t, bs, nprob, total, nsteps, bar, to, s, g);
+        case 4: return launch_persistent_one<R, T, AT, 2, 128, 1, 1, 2>(t, bs, nprob, total, nsteps, bar, to, s, g);
+        case 5: return launch_persistent_one<R, T, AT, 2, 256, 1, 1, 1>(t, bs, nprob, total, nsteps, bar, to, s, g);
         }
     }
     return hipErrorInvalidValue;

@@ -50,6 +50,13 @@ struct StepArgs {
     int32_t acc_prev;    // 1: also add the interval before, d = ucur - unew (on entry)
     int32_t acc_face;    // variable-material step: 0, or the sign of the face terms into acc_b
     int32_t active;      // 0: the problem has no step here (multi-problem launches)
+    // Partial sums of the kernel terms (f32 fields with an f64 accumulator): the
+    // accumulating launches of a sweep add their terms to a per-cell f32 partial sum
+    // and fold it into the f64 accumulator every kPartialCycle-th of them, so most
+    // accumulating launches move 8 bytes of partial sum per cell instead of 16 of
+    // accumulator.  part_mode says what this launch does (PM_*); part is the buffer.
+    void* part;
+    int32_t part_mode;
     // events
     const int32_t* blk_off;  // [nblk + 1] ranges into grp
     const EvPlane* grp;      // per block, its planes that hold events
@@ -69,6 +76,16 @@ struct StepArgs {
     // block decomposition
     int32_t nty, ntz, chunk_len, nblk;
 };
+
+// What an accumulating launch does with the kernel terms it computes (dsum):
+//   PM_DIRECT  acc += sign dsum                 (no partial sum pending)
+//   PM_START   part = dsum
+//   PM_ADD     part += dsum
+//   PM_FLUSH   acc += sign (part + dsum)
+// The partial sum is rounded to f32 when stored; every kPartialCycle-th accumulating
+// launch of a sweep folds it into the accumulator, and the last one always does.
+enum { PM_DIRECT = 0, PM_START = 1, PM_ADD = 2, PM_FLUSH = 3 };
+constexpr int kPartialCycle = 16;
 
 // Tile shape of one kernel variant.
 struct Variant {
@@ -110,8 +127,17 @@ hipError_t launch_vd_step(int ndim, int dtype, int acc_dtype, int variant, int n
 // Misc kernels.  All return hipError_t of the launch.
 hipError_t launch_speed_stats(int dtype, const void* c, int64_t n, double* d_out3, double* d_part,
                               hipStream_t s);
+// d_out[0] = scale * sum (x - y)^2 (x^2 when y is null) in fixed order; diff_out (may be
+// null) receives x - y.  d_part holds kReduceBlocks doubles.
 hipError_t launch_sum_squares(int dtype, const void* x, const void* y, void* diff_out, int64_t n,
-                              double* d_part, double* d_out, hipStream_t s);
+                              double* d_part, double* d_out, hipStream_t s, double scale = 1.0);
+// Zero `bytes` (a multiple of 4) at p (16-byte aligned) with a kernel.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// Copy `rows` rows of n2 elements of size es (4 or 8) between row strides spitch and dpitch.
+hipError_t launch_copy_rows(void* dst, int64_t dpitch, const void* src, int64_t spitch, size_t es,
+                            int64_t rows, int64_t n2, hipStream_t s);
+// J[0..n) = NaN when *flag != 0 (a persistent launch gave up at a grid barrier).
+hipError_t launch_nan_if_flag(const unsigned* flag, double* J, int n, hipStream_t s);
 // Terminal hand-over for the shots [shot0, shot0 + nshots) of a problem: per distinct
 // receiver cell, receivers sorted by (cell, shot); u_last / u_prev point at the
 // group's first shot, shots shot_stride elements apart.  The step coefficient is

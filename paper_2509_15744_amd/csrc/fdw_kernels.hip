@@ -43,17 +43,17 @@ __global__ __launch_bounds__(kReduceThreads) void sumsq_partial(const T* __restr
 }
 
 __global__ __launch_bounds__(kReduceThreads) void sum_final(const double* __restrict__ part,
-                                                            double* __restrict__ out)
+                                                            double scale, double* __restrict__ out)
 {
     __shared__ double sh[kReduceThreads];
     double s = 0.0;
     for (int i = threadIdx.x; i < kReduceBlocks; i += kReduceThreads) s += part[i];
     const double t = block_sum(s, sh);
-    if (threadIdx.x == 0) out[0] = t;
+    if (threadIdx.x == 0) out[0] = scale * t;
 }
 
 hipError_t launch_sum_squares(int dtype, const void* x, const void* y, void* diff_out, int64_t n,
-                              double* d_part, double* d_out, hipStream_t s)
+                              double* d_part, double* d_out, hipStream_t s, double scale)
 {
     if (dtype == 1)
         hipLaunchKernelGGL(sumsq_partial<double>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s,
@@ -61,7 +61,7 @@ hipError_t launch_sum_squares(int dtype, const void* x, const void* y, void* dif
     else
         hipLaunchKernelGGL(sumsq_partial<float>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s,
                            (const float*)x, (const float*)y, (float*)diff_out, n, d_part);
-    hipLaunchKernelGGL(sum_final, dim3(1), dim3(kReduceThreads), 0, s, d_part, d_out);
+    hipLaunchKernelGGL(sum_final, dim3(1), dim3(kReduceThreads), 0, s, d_part, scale, d_out);
     return hipGetLastError();
 }
 
@@ -321,6 +321,77 @@ hipError_t launch_scale(int dtype, int acc_dtype, int64_t n, const void* acc, do
     else
         hipLaunchKernelGGL((scale_kernel<float, float>), dim3(gs), dim3(bs), 0, s, n, (const float*)acc,
                            (float)scale, (float*)out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// plain memory kernels: a launch, unlike a memset or 2D copy node, is what a
+// captured graph of the batched call may hold
+// ---------------------------------------------------------------------------
+
+__global__ void zero_words_kernel(uint4* __restrict__ p, int64_t n16, uint32_t* __restrict__ tail, int ntail)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    if ((bytes & 3) != 0 || ((uintptr_t)p & 15) != 0) return hipErrorInvalidValue;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int ntail = (int)((bytes - (size_t)n16 * 16) / 4);
+    const int bs = 256;
+    const int64_t gs64 = (n16 + bs - 1) / bs;
+    const int gs = (int)(gs64 < 16384 ? (gs64 > 0 ? gs64 : 1) : 16384);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(gs), dim3(bs), 0, s, (uint4*)p, n16,
+                       (uint32_t*)((char*)p + (size_t)n16 * 16), ntail);
+    return hipGetLastError();
+}
+
+template <typename E>
+__global__ void copy_rows_kernel(E* __restrict__ dst, int64_t dpitch, const E* __restrict__ src,
+                                 int64_t spitch, int64_t rows, int64_t n2)
+{
+    const int64_t total = rows * n2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t r = i / n2, z = i - r * n2;
+        dst[r * dpitch + z] = src[r * spitch + z];
+    }
+}
+
+hipError_t launch_copy_rows(void* dst, int64_t dpitch, const void* src, int64_t spitch, size_t es,
+                            int64_t rows, int64_t n2, hipStream_t s)
+{
+    if (rows <= 0 || n2 <= 0) return hipSuccess;
+    const int bs = 256;
+    const int64_t gs64 = (rows * n2 + bs - 1) / bs;
+    const int gs = (int)(gs64 < 16384 ? gs64 : 16384);
+    if (es == 8)
+        hipLaunchKernelGGL(copy_rows_kernel<uint64_t>, dim3(gs), dim3(bs), 0, s, (uint64_t*)dst, dpitch,
+                           (const uint64_t*)src, spitch, rows, n2);
+    else if (es == 4)
+        hipLaunchKernelGGL(copy_rows_kernel<uint32_t>, dim3(gs), dim3(bs), 0, s, (uint32_t*)dst, dpitch,
+                           (const uint32_t*)src, spitch, rows, n2);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// Every J of a batched run becomes NaN when the persistent launch's barrier flag is set.
+__global__ void nan_if_flag_kernel(const unsigned* __restrict__ flag, double* __restrict__ J, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[0] != 0u) J[i] = __builtin_nan("");
+}
+
+hipError_t launch_nan_if_flag(const unsigned* flag, double* J, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nan_if_flag_kernel, dim3((n + 255) / 256), dim3(256), 0, s, flag, J, n);
     return hipGetLastError();
 }
 

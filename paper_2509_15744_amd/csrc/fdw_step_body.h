@@ -31,7 +31,10 @@
 //    stored dt^2 c^2 array, so a step streams four arrays; those streams are read
 //    and written non-temporally, which leaves the cache to the u^n halos;
 //  * block ids are remapped so that consecutive tiles run on the same XCD
-//    (dispatch is round-robin over the 8 XCDs) and share halo rows in its L2.
+//    (dispatch is round-robin over the 8 XCDs) and share halo rows in its L2;
+//  * with f32 fields and an f64 accumulator, most accumulating launches add their
+//    kernel terms to an f32 partial sum per cell instead of the accumulator, which
+//    takes it in every kPartialCycle-th of them (part_mode).
 //
 // Difference form of the Laplacian, sum_j w_j [(u_{+j} - u_0) + (u_{-j} - u_0)]:
 // L applied to a constant is exactly zero in f32 even though the rounded weights
@@ -242,6 +245,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
     typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, S> SH;
     typedef typename Vec<T, VZ>::type vec;
     typedef typename Vec<AT, VZ>::type avec;
+    typedef typename Vec<float, VZ>::type pvec;
     constexpr int TYT = SH::TYT, NT = SH::NT, WZ = SH::WZ, RYH = SH::RYH, PADL = SH::PADL;
     constexpr int LZ = SH::LZ, LSZ = SH::LSZ, HYV = SH::HYV, HZ = SH::HZ;
     constexpr int NHY = SH::NHY, NHZ = SH::NHZ, NHY1 = SH::NHY1;
@@ -269,6 +273,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
     const T* __restrict__ cc = (const T*)a.c;
     AT* __restrict__ acc = (AT*)a.acc;
     const bool use_acc = ACC && a.acc_sign != 0;
+    // f32 partial sums of the kernel terms exist for f32 fields with an f64 accumulator
+    constexpr bool PARTS = ACC && sizeof(T) == 4 && sizeof(AT) == 8;
+    float* __restrict__ part = (float*)a.part;
+    const int pmode = (PARTS && use_acc) ? a.part_mode : PM_DIRECT;
+    const bool rd_acc = use_acc && (pmode == PM_DIRECT || pmode == PM_FLUSH);
+    const bool rd_part = PARTS && use_acc && (pmode == PM_ADD || pmode == PM_FLUSH);
+    const bool wr_part = PARTS && use_acc && (pmode == PM_START || pmode == PM_ADD);
     T w[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) w[j] = (T)a.w[j];
@@ -325,6 +336,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
     // plane-x operands, loaded one plane ahead
     vec cu[S][RY], cv[RY], chy[S][NHY1];
     avec ca[RY];
+    pvec cpt[RY];
     T chz[S][NHZ];
     {
         const int64_t xo = (int64_t)x0 * ps;
@@ -334,7 +346,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
             for (int s = 0; s < S; ++s)
                 cu[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xo + roff[k], z, n2);
             cv[k] = load_row<T, VZ, true, false>(cc + xo + roff[k], z, n2);
-            if (use_acc) ca[k] = load_row<AT, VZ, true, false>(acc + xo + roff[k], z, n2);
+            if (rd_acc) ca[k] = load_row<AT, VZ, true, false>(acc + xo + roff[k], z, n2);
+            if (rd_part) cpt[k] = load_row<float, VZ, true, false>(part + xo + roff[k], z, n2);
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -357,6 +370,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
         // issue the loads of plane x + 1
         vec nq[S][RY], nu[S][RY], nv[RY], nhy[S][NHY1];
         avec na[RY];
+        pvec npt[RY];
         T nhz[S][NHZ];
         const bool more = x + 1 < x1;
         if (more) {
@@ -370,7 +384,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     nu[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xn + roff[k], z, n2);
                 }
                 nv[k] = load_row<T, VZ, true, false>(cc + xn + roff[k], z, n2);
-                if (use_acc) na[k] = load_row<AT, VZ, true, false>(acc + xn + roff[k], z, n2);
+                if (rd_acc) na[k] = load_row<AT, VZ, true, false>(acc + xn + roff[k], z, n2);
+                if (rd_part) npt[k] = load_row<float, VZ, true, false>(part + xn + roff[k], z, n2);
             }
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -404,6 +419,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
             const int s0 = lofs[k];
             vec un[S];
             avec an;
+            pvec pn;
             const T* L0 = lds + (x & 1) * S * LSZ;
 #pragma unroll
             for (int i = 0; i < VZ; ++i) {
@@ -443,15 +459,21 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     }
                     if (a.sample && pe.has) sample_receivers(pe, a, est, lane0[k] + i, s, uni);
                 }
-                if (use_acc) {
+                if (rd_acc) {
+                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cpt[k], i) : dsum;
                     const AT ai = el<AT, VZ>(ca[k], i);
-                    set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + dsum : ai - dsum);
+                    set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + tot : ai - tot);
+                }
+                if (wr_part) {
+                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cpt[k], i) : dsum;
+                    set_el<float, VZ>(pn, i, (float)tot);
                 }
             }
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 __builtin_nontemporal_store(un[s], (vec*)(unew + s * sst + xo + roff[k] + z));
-            if (use_acc) __builtin_nontemporal_store(an, (avec*)(acc + xo + roff[k] + z));
+            if (rd_acc) __builtin_nontemporal_store(an, (avec*)(acc + xo + roff[k] + z));
+            if (wr_part) __builtin_nontemporal_store(pn, (pvec*)(part + xo + roff[k] + z));
         }
 
         // rotate to plane x + 1
@@ -466,7 +488,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     cu[s][k] = nu[s][k];
                 }
                 cv[k] = nv[k];
-                if (use_acc) ca[k] = na[k];
+                if (rd_acc) ca[k] = na[k];
+                if (rd_part) cpt[k] = npt[k];
             }
 #pragma unroll
             for (int s = 0; s < S; ++s) {

@@ -109,6 +109,10 @@ def _load():
         "fd_sens_forward": ([G, P, A, D, I, P, S, P, DP, O, P], ctypes.c_int),
         "fd_sens_backward": ([G, P, A, D, I, D, S, D, P, O, P], ctypes.c_int),
         "fd_adjoint_sensitivity_batched": ([ctypes.POINTER(fd_problem), I, DP, O, P], ctypes.c_int),
+        "fd_batch_plan_create": ([ctypes.POINTER(fd_problem), I, O, P, ctypes.POINTER(P)], ctypes.c_int),
+        "fd_batch_run": ([P, P, P], ctypes.c_int),
+        "fd_batch_timing": ([P, ctypes.POINTER(fd_timing)], ctypes.c_int),
+        "fd_batch_plan_destroy": ([P, P], ctypes.c_int),
         "fd_propagate": ([G, P, P, P, I, O, P], ctypes.c_int),
         "fd_autotune": ([G, I, O, I, O, DP, P], ctypes.c_int),
         "fd_design_map": ([ctypes.POINTER(fd_design), P, P, P, P, P], ctypes.c_int),
@@ -311,9 +315,7 @@ def fd_misfit(traces, observed, dt, residual=None) -> float:
     return J.value
 
 
-def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k, grad=None,
-                           traces=None, shots=None, **opts):
-    """(grad_c, J) of the memory-efficient method at factor ``k``."""
+def _sensitivity(fn, c, dx, order, src, wavelet, rec, dt, nt, observed, k, grad, traces, shots, opts):
     acq = _acq(src, wavelet, rec, shots)
     if grad is None:
         grad = torch.empty_like(c)
@@ -321,11 +323,16 @@ def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k,
     g = make_grid(c.shape, dx, order, _dtype_code(c))
     o = make_opts(**opts)
     J = ctypes.c_double()
-    _raise(_lib.fd_adjoint_sensitivity(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt),
-                                       int(nt), _dev(observed, "observed"), float(k),
-                                       _dev(grad, "grad"), ctypes.byref(J), _dev(traces, "traces"),
-                                       ctypes.byref(o), _stream()))
+    _raise(fn(ctypes.byref(g), _dev(c, "c"), ctypes.byref(acq.c), float(dt), int(nt), _dev(observed, "observed"),
+              float(k), _dev(grad, "grad"), ctypes.byref(J), _dev(traces, "traces"), ctypes.byref(o), _stream()))
     return grad, J.value
+
+
+def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k, grad=None,
+                           traces=None, shots=None, **opts):
+    """(grad_c, J) of the memory-efficient method at factor ``k``."""
+    return _sensitivity(_lib.fd_adjoint_sensitivity, c, dx, order, src, wavelet, rec, dt, nt, observed, k,
+                        grad, traces, shots, opts)
 
 
 def fd_adjoint_exact(c, dx, order, src, wavelet, rec, dt, nt, observed, grad=None, traces=None,
@@ -499,6 +506,47 @@ def fd_adjoint_sensitivity_batched(problems, **opts):
     o = make_opts(**opts)
     _raise(_lib.fd_adjoint_sensitivity_batched(arr, len(problems), J, ctypes.byref(o), _stream()))
     return list(J)
+
+
+class BatchPlan:
+    """A batch plan (fd_batch_plan_create) over a list of ``Problem``s.  ``run(J)``
+    enqueues one gradient of every problem on the current stream with kernel launches
+    only, so it may be captured in a ``torch.cuda.CUDAGraph`` and replayed; ``J`` is a
+    float64 device tensor of one value per problem.  The problems' tensors stay
+    referenced for the plan's life; ``close()`` releases the plan on the current
+    stream."""
+
+    def __init__(self, problems, **opts):
+        self.problems = list(problems)
+        arr = (fd_problem * len(self.problems))(*[p.c_struct for p in self.problems])
+        o = make_opts(**opts)
+        h = ctypes.c_void_p()
+        _raise(_lib.fd_batch_plan_create(arr, len(self.problems), ctypes.byref(o), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, J):
+        if self._h is None:
+            raise FdError(FD_E_ARG, "plan is closed")
+        if not (J.is_cuda and J.dtype == torch.float64 and J.is_contiguous() and J.numel() >= len(self.problems)):
+            raise FdError(FD_E_ARG, "J must be a contiguous float64 device tensor with one value per problem")
+        _raise(_lib.fd_batch_run(self._h, ctypes.c_void_p(J.data_ptr()), _stream()))
+        return J
+
+    def timing(self):
+        t = fd_timing()
+        _raise(_lib.fd_batch_timing(self._h, ctypes.byref(t)))
+        return t
+
+    def close(self):
+        if self._h is not None:
+            _raise(_lib.fd_batch_plan_destroy(self._h, _stream()))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fd_autotune(shape, dx, order, dtype=torch.float32, nshot=1, steps=3, **opts):

@@ -213,12 +213,12 @@ def test_stable_dt_reduces_to_the_homogeneous_limit():
 
 def test_workspace_bytes(fdw):
     """fd_workspace_bytes covers the state arrays (two wavefields per shot, an f64
-    accumulator, the residual rows) plus small tables, grows with each input, and
-    rejects a bad grid."""
+    accumulator, f32 partial sums of the kernel terms, the residual rows) plus small
+    tables, grows with each input, and rejects a bad grid."""
     shape, nt, nrec = (64, 48, 128), 500, 300
     n = 64 * 48 * 128
     w = fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, nt, nsrc=2, nrec=nrec)
-    state = 2 * n * 4 + n * 8 + nt * nrec * 4
+    state = 2 * n * 4 + n * 8 + n * 4 + nt * nrec * 4
     assert state < w < state * 1.1
     assert fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, nt, nsrc=2, nrec=nrec, nshots=4) - w >= 6 * n * 4
     # rows of 80 are padded to 128: the bound covers the padded arrays
@@ -228,3 +228,19 @@ def test_workspace_bytes(fdw):
     assert fdw.fd_workspace_bytes(shape, 8, fdw.FD_F32, 2 * nt, nsrc=2, nrec=nrec) - w == nt * nrec * 4
     with pytest.raises(fdw.FdError):
         fdw.fd_workspace_bytes((2, 2), 8, fdw.FD_F32, nt)
+
+
+def test_batch_plan_argument_checks(fdw):
+    """The plan calls reject null plans and empty batches on the host; destroying a null
+    plan is a no-op."""
+    lib = fdw.lib()
+    h = ctypes.c_void_p(123)
+    assert lib.fd_batch_plan_create(None, 0, None, None, ctypes.byref(h)) == fdw.FD_E_ARG
+    assert h.value is None and "at least one problem" in lib.fd_last_error().decode()
+    assert lib.fd_batch_plan_create(None, 1, None, None, None) == fdw.FD_E_ARG
+    assert lib.fd_batch_run(None, None, None) == fdw.FD_E_ARG
+    assert "plan is null" in lib.fd_last_error().decode()
+    t = fdw.fd_timing()
+    assert lib.fd_batch_timing(None, ctypes.byref(t)) == fdw.FD_E_ARG
+    assert lib.fd_batch_plan_destroy(None, None) == fdw.FD_OK
+

@@ -45,3 +45,45 @@ def test_sweep_k_follows_the_paper_rule():
     assert best is not None
     i = [q.k for q in pts].index(best)
     assert pts[i].fp32_err <= 1e-4 and all(q.fp32_err > 1e-4 for q in pts[:i])
+
+
+@pytest.mark.gpu
+def test_sweep_k_against_the_oracle():
+    """The decade sweep on the device against the FP64 oracle on the same inputs (the
+    inclusion workload, observed data from the oracle's forward solve): the device
+    exact gradient equals the oracle's stored-history adjoint, each f64 gradient the
+    oracle's Alg. 1 at that k (1e-9), the device gap(k) the oracle's gap(k), which is
+    k times the closed-form gap per unit k (sum of squared adjoint increments over c^3),
+    and the paper's rule (smallest k whose f32 gradient is within the tolerance of the
+    double-precision one) picks the same k with the oracle's gradients as the reference."""
+    assert torch.cuda.is_available(), "the gpu tests need a HIP device"
+    import oracle
+    from paper_2509_15744_amd import calibrate
+    from helpers import rel
+    p = wl.inclusion_2d(nt=400)
+    obs, _, _ = oracle.forward(p.c_ref, p.dx, p.order, p.dt, p.nt, p.src, p.wavelet, p.rec)
+    g_ex_o, _, s2, _ = oracle.exact_gradient(p.c, p.dx, p.order, p.dt, p.nt, p.src, p.wavelet, p.rec, obs)
+    gap1 = np.linalg.norm(s2 / p.c ** 3) / np.linalg.norm(g_ex_o)
+    f64 = torch.float64
+    ks = [1e-3, 1e-2, 1e-1, 1.0, 10.0]
+    tol = 1e-4
+    say("k sweep against the oracle")
+    pts, best, g_ex = calibrate.sweep_k(to_dev(p.c, f64), p.dx, p.order, p.src, to_dev(p.wavelet, f64), p.rec,
+                                        p.dt, p.nt, to_dev(obs, f64), ks, tol=tol, keep=True)
+    assert rel(g_ex.cpu().numpy(), g_ex_o) < 1e-9
+    errs_o = []
+    for q in pts:
+        g_ap_o, _, _ = oracle.superposition_gradient(p.c, p.dx, p.order, p.dt, p.nt, p.src, p.wavelet, p.rec,
+                                                     obs, q.k)
+        gap_o = rel(g_ap_o, g_ex_o)
+        g64 = q.g64.cpu().numpy()
+        g32 = q.g32.cpu().numpy()
+        errs_o.append(rel(g32, g_ap_o))
+        say(f"  k {q.k:.0e}: gap {q.gap:.4e} (oracle {gap_o:.4e}, k gap1 {q.k * gap1:.4e}), "
+            f"f32 {q.fp32_err:.3e} (vs oracle {errs_o[-1]:.3e})")
+        assert rel(g64, g_ap_o) < 1e-9
+        assert abs(gap_o - q.k * gap1) <= 1e-9 * q.k * gap1
+        assert abs(q.gap - gap_o) <= 1e-7 * gap_o
+        assert abs(q.fp32_err - errs_o[-1]) <= 1e-3 * errs_o[-1] + 1e-12
+    best_o = next((q.k for q, e in zip(pts, errs_o) if e <= tol), None)
+    assert best is not None and best == best_o

@@ -200,3 +200,93 @@ def test_autotune_2d_keeps_one_shape(fdw):
     best, ms = fdw.fd_autotune((96, 130), 1.0, 8, torch.float32, nshot=1, steps=2)
     assert best["variant_plain"] == best["variant"] and best["chunk_plain"] == best["chunk"]
     assert ms > 0
+
+
+def _oracle_refs(probs, cs, obs):
+    return [oracle.superposition_gradient(c, 1.0, 8, q.dt, q.nt, q.src, q.wavelet, q.rec, o, q.meta["k"])
+            for q, c, o in zip(probs, cs, obs)]
+
+
+def _check_plan_result(items, J, refs):
+    Jh = J.cpu().numpy()
+    for p, (it, (g_o, J_o, _)) in enumerate(zip(items, refs)):
+        assert rel(it.grad.cpu().numpy(), g_o) < 1e-9, p
+        assert abs(Jh[p] - J_o) < 1e-12 * J_o, p
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_batch_plan_graph_replay(fdw, ndim):
+    """A batch plan's run captured once in a graph and replayed three times, with every
+    problem's speed field changed in place between replays (and eager runs of the same
+    plan in between): each replay equals the oracle's Alg. 1 for the speeds it ran with
+    (f64: gradient 1e-9, J 1e-12) and the eager run of the same speeds bitwise."""
+    probs = _uneven_problems(ndim, 5, "f64", seed=10 + ndim)
+    f64 = torch.float64
+    items, obs = [], []
+    for q in probs:
+        o = oracle.forward(q.c_ref, 1.0, 8, q.dt, q.nt, q.src, q.wavelet, q.rec)[0]
+        obs.append(o)
+        items.append(fdw.Problem(to_dev(q.c, f64), 1.0, 8, q.src, to_dev(q.wavelet, f64), q.rec, q.dt, q.nt,
+                                 to_dev(o, f64), q.meta["k"]))
+    say("batch plan", ndim, [q.shape for q in probs])
+    plan = fdw.BatchPlan(items)
+    J = torch.zeros(len(items), dtype=f64, device="cuda")
+    plan.run(J)
+    torch.cuda.synchronize()
+    _check_plan_result(items, J, _oracle_refs(probs, [q.c for q in probs], obs))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(J)
+    rng = np.random.default_rng(7)
+    for rep in range(3):
+        # slower media only: the CFL check of the plan's creation keeps holding
+        cs = [q.c * (1.0 - 0.05 * rng.random(q.shape)) for q in probs]
+        for it, c in zip(items, cs):
+            it.c.copy_(torch.as_tensor(c, dtype=f64))
+        J.fill_(-1.0)
+        say("batch plan replay", rep)
+        graph.replay()
+        torch.cuda.synchronize()
+        grads = [it.grad.clone() for it in items]
+        Jr = J.clone()
+        _check_plan_result(items, J, _oracle_refs(probs, cs, obs))
+        # the eager run of the same plan and speeds gives the replay's result bitwise
+        plan.run(J)
+        torch.cuda.synchronize()
+        assert torch.equal(J, Jr) and all(torch.equal(g, it.grad) for g, it in zip(grads, items))
+    del graph
+    plan.close()
+
+
+def test_batch_plan_persistent_and_timing(fdw):
+    """The persistent form of a plan (one cooperative launch per sweep) gives the per-step
+    form's gradients and J bitwise, run after run with c changed in between; a timed plan
+    reports both sweeps."""
+    probs = _uneven_problems(2, 4, "f64", seed=21)
+    f64 = torch.float64
+    items = []
+    for q in probs:
+        o = oracle.forward(q.c_ref, 1.0, 8, q.dt, q.nt, q.src, q.wavelet, q.rec)[0]
+        items.append(fdw.Problem(to_dev(q.c, f64), 1.0, 8, q.src, to_dev(q.wavelet, f64), q.rec, q.dt, q.nt,
+                                 to_dev(o, f64), q.meta["k"]))
+    t = fdw.fd_timing()
+    say("batch plan persistent")
+    steps = fdw.BatchPlan(items, timing=t)
+    pers = fdw.BatchPlan(items, persistent=True)
+    J1 = torch.zeros(len(items), dtype=f64, device="cuda")
+    J2 = torch.zeros_like(J1)
+    for rep in range(2):
+        if rep:
+            for it in items:
+                it.c.mul_(0.98)
+        steps.run(J1)
+        tm = steps.timing()
+        g1 = [it.grad.clone() for it in items]
+        pers.run(J2)
+        torch.cuda.synchronize()
+        assert torch.equal(J1, J2) and all(torch.equal(g, it.grad) for g, it in zip(g1, items))
+        assert torch.isfinite(J1).all()
+        assert tm.fwd_ms > 0 and tm.bwd_ms > 0
+        assert tm.fwd_launches == max(q.nt for q in probs) and tm.bwd_launches == tm.fwd_launches - 1
+    steps.close()
+    pers.close()
