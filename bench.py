@@ -105,21 +105,37 @@ def gradient_bytes(nt, group, acc, partials=None):
     return sweep_bytes(nt, group, acc, partials, nt) + sweep_bytes(nt, group, acc, partials, nt - 1)
 
 
-def vd_step_bytes(acc):
-    """Algorithmic HBM bytes per cell of one variable-material step launch: read u^n, b,
-    m, u^{n-1}, write u^{n+1}, and read and write the stiffness accumulator; a launch
-    that adds mass terms also reads and writes the mass accumulator.  (with, without)."""
+def cycle_mode(i, total):
+    """Partial-sum mode of the i-th of `total` accumulating launches of a sweep."""
+    j = i % PARTIAL_CYCLE
+    if i == total - 1:
+        return "direct" if j == 0 else "flush"
+    if j == 0:
+        return "start"
+    return "flush" if j == PARTIAL_CYCLE - 1 else "add"
+
+
+def acc_extra(acc, mode):
+    """Bytes per cell an accumulating launch moves for one accumulator in `mode`."""
     a = 8 if acc == "f64" else 4
-    return 20 + 4 * a, 20 + 2 * a
+    return {None: 0, "direct": 2 * a, "start": 4, "add": 8, "flush": 4 + 2 * a}[mode]
 
 
-def vd_gradient_bytes(nt, acc):
+def vd_gradient_bytes(nt, acc, partials=None):
     """Algorithmic bytes per cell of the variable-material step launches of one gradient:
-    the mass accumulator on every other launch (acc_terms), the stiffness one on all."""
-    w, wo = vd_step_bytes(acc)
-    fwd = sum(w if acc_terms(l, nt - 1) else wo for l in range(nt))
-    bwd = sum(w if acc_terms(l, nt - 1) else wo for l in range(nt - 1))
-    return fwd + bwd
+    read u^n, b, m, u^{n-1} and write u^{n+1} (20 B), the mass accumulator on every other
+    launch (acc_terms) and the stiffness accumulator on every launch, each directly or
+    through f32 partial sums in cycles of PARTIAL_CYCLE (f32 fields, f64 accumulators)."""
+    if partials is None:
+        partials = acc == "f64"
+    total = 0
+    for nl in (nt, nt - 1):
+        for l in range(nl):
+            terms = acc_terms(l, nt - 1)
+            mass = None if not terms else (part_mode(l, nt - 1) if partials else "direct")
+            stiff = cycle_mode(l, nl) if partials else "direct"
+            total += 20 + acc_extra(acc, mass) + acc_extra(acc, stiff)
+    return total
 
 
 def make_single(args, torch, wl):
@@ -304,7 +320,7 @@ def run_single(args, np, torch, fdw, wl):
         log("launch shape (given):", best)
     else:
         best, best_ms = fdw.fd_autotune(p.shape, p.dx, p.order, torch.float32, nshot=nshot, steps=4,
-                                        acc_dtype=args.acc)
+                                        acc_dtype=args.acc, no_partials=args.no_partials)
         log("launch shape:", best, f"{best_ms:.3f} ms/step in the tuner")
     obs = fdw.fd_forward(c_ref, p.dx, p.order, src, w, rec, p.dt, p.nt, shots=shots)
     del c_ref
@@ -316,7 +332,7 @@ def run_single(args, np, torch, fdw, wl):
     acq = fdw.Acquisition(src, w, rec, *(shots if shots else (None, None, 0)))
     opts = dict(acc_dtype=args.acc, variant=best["variant"], chunk=best["chunk"],
                 max_group=best["max_group"], variant_plain=best["variant_plain"],
-                chunk_plain=best["chunk_plain"])
+                chunk_plain=best["chunk_plain"], no_partials=args.no_partials)
 
     def exact_step(record):
         t = fdw.fd_timing()
@@ -348,18 +364,19 @@ def run_single(args, np, torch, fdw, wl):
         # forward: one field per launch, no accumulator; backward: u and mu together with
         # the cross accumulator, one launch per shot and step
         # forward: one field per launch, no accumulator; backward: u and mu together
-        per_cell = p.nt * launch_bytes(1, args.acc, None) + sweep_bytes(p.nt, 2, args.acc, args.acc == "f64",
-                                                                        p.nt - 1)
+        per_cell = p.nt * launch_bytes(1, args.acc, None) + sweep_bytes(
+            p.nt, 2, args.acc, args.acc == "f64" and not args.no_partials, p.nt - 1)
         bytes_all = ncell * nshot * per_cell * args.steps
         bpu = per_cell / (2 * p.nt - 1)
     else:
         group = best["max_group"] or 1
         ngroups = math.ceil(nshot / group)
-        per_cell = gradient_bytes(p.nt, group, args.acc)
+        per_cell = gradient_bytes(p.nt, group, args.acc, args.acc == "f64" and not args.no_partials)
         bytes_all = ncell * ngroups * per_cell * args.steps
         bpu = per_cell / (2 * p.nt - 1) / group
     cfg = {"workload": desc, "grid": list(p.shape), "nt": p.nt, "order": p.order, "shots": nshot,
-           "receivers": len(rec), "accumulator": args.acc, "method": args.method, "k": holder["k"],
+           "receivers": len(rec), "accumulator": args.acc, "partial_sums": args.acc == "f64" and not args.no_partials,
+           "method": args.method, "k": holder["k"],
            "J": holder["J"], "launch_shape": best, "cell_updates_per_step": upd}
     acc_info = None
     if not exact and not args.no_accuracy:
@@ -412,7 +429,7 @@ def run_vd(args, np, torch, fdw, wl):
     log("workload:", desc, f"dt={q['dt']:.5g}")
     w = torch.as_tensor(q["wavelet"], dtype=torch.float32, device="cuda")
     variant = args.variant or 1
-    opts = dict(acc_dtype=args.acc, variant=variant, chunk=args.chunk)
+    opts = dict(acc_dtype=args.acc, variant=variant, chunk=args.chunk, no_partials=args.no_partials)
     obs = fdw.fd_vd_forward(q["m_ref"], q["b_ref"], q["dx"], q["src"], w, q["rec"], q["dt"], nt, **opts)
     tr = fdw.fd_vd_forward(q["m"], q["b"], q["dx"], q["src"], w, q["rec"], q["dt"], nt, **opts)
     J0 = fdw.fd_misfit(tr, obs, q["dt"])
@@ -435,7 +452,7 @@ def run_vd(args, np, torch, fdw, wl):
     upd = ncell * (2 * nt - 1)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    per_cell = vd_gradient_bytes(nt, args.acc)
+    per_cell = vd_gradient_bytes(nt, args.acc, args.acc == "f64" and not args.no_partials)
     bytes_all = ncell * per_cell * args.steps
     cfg = {"workload": desc, "grid": [n, n, n], "nt": nt, "order": 2, "shots": 1, "receivers": len(q["rec"]),
            "accumulator": args.acc, "method": "superposition", "k": k, "J": holder["J"],
@@ -510,7 +527,7 @@ def run_tato(args, np, torch, fdw, wl):
 
     def one_step(record):
         t = fdw.fd_timing()
-        loop.sweep_opts = {"timing": t}
+        loop.sweep_opts = {"timing": t, "no_partials": args.no_partials}
         holder["C"] = loop.step()
         if record:
             timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
@@ -520,7 +537,7 @@ def run_tato(args, np, torch, fdw, wl):
     upd = ncell * (2 * nt - 1)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    per_cell = vd_gradient_bytes(nt, args.acc)
+    per_cell = vd_gradient_bytes(nt, args.acc, args.acc == "f64" and not args.no_partials)
     bytes_all = ncell * per_cell * args.steps
     cfg = {"workload": desc, "grid": list(shape), "nt": nt, "order": 2, "shots": 1, "receivers": len(rec),
            "design_cells": int(np.prod(q["design_extent"])), "accumulator": args.acc,
@@ -564,7 +581,7 @@ def run_fwi(args, np, torch, fdw, wl):
 
     def one_step(record):
         t = fdw.fd_timing()
-        loop.sweep_opts = {"timing": t}
+        loop.sweep_opts = {"timing": t, "no_partials": args.no_partials}
         holder["C"] = loop.step()
         if record:
             timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
@@ -574,7 +591,7 @@ def run_fwi(args, np, torch, fdw, wl):
     upd = ncell * (2 * nt - 1)
     launches = sum(t[1] + t[3] for t in timings)
     kern_ms = sum(t[0] + t[2] for t in timings)
-    per_cell = vd_gradient_bytes(nt, args.acc)
+    per_cell = vd_gradient_bytes(nt, args.acc, args.acc == "f64" and not args.no_partials)
     cfg = {"workload": desc, "grid": list(shape), "nt": nt, "order": 2, "shots": 1, "receivers": len(q["rec"]),
            "design_cells": ncell, "accumulator": args.acc, "method": "superposition", "k": loop.k,
            "objective": holder["C"], "objective_history": loop.history,
@@ -843,6 +860,8 @@ def main():
                     help="single-medium workloads: the gradient that is timed")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-partials", action="store_true",
+                    help="every accumulating step reads and writes the f64 accumulator (no f32 partial sums)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

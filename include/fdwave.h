@@ -122,6 +122,11 @@ typedef struct fd_opts {
                            (or the remembered choice when `variant` is 0).  Used only where
                            it groups the shots as `variant` does; results are identical */
     int32_t chunk_plain;   /* planes per block for those launches; 0: library choice */
+    int32_t no_partials;   /* 1: every accumulating step reads and writes the f64
+                           accumulator; 0 (default): f32 fields with an f64 accumulator
+                           keep f32 partial sums of the kernel terms, folded into the
+                           accumulator every 16th accumulating step (4 instead of 8 bytes
+                           of accumulator traffic per cell update on average) */
 } fd_opts;
 
 /* Caller-owned device state that carries one gradient from its forward sweep

@@ -23,11 +23,20 @@ using namespace fdh;
 
 namespace {
 
+// Working arrays the fused call makes once for both halves: c in the sweep's row
+// layout and the partial sums of the kernel terms (null members: the half makes its own).
+struct Shared {
+    const void* cp = nullptr;
+    void* part = nullptr;
+    bool made = false;
+};
+
 // `own_state`: the state arrays were allocated by the library itself in this call.
 // `ext`: take scratch from this (arena) instead of the stream-ordered pool.
 int sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int nt,
                  const void* observed, const fd_state* st, void* traces, double* J_host,
-                 const fd_opts* opts, hipStream_t s, bool own_state, Scratch* ext = nullptr)
+                 const fd_opts* opts, hipStream_t s, bool own_state, Scratch* ext = nullptr,
+                 const Shared* sh = nullptr)
 {
     Scratch local(s);
     Scratch& sc = ext ? *ext : local;
@@ -39,15 +48,15 @@ int sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double d
     if ((rc = check_dev(observed, tb, "observed"))) return rc;
     if (traces && (rc = check_dev(traces, tb, "traces"))) return rc;
     pad_rows(&G);
-    const void* cp = nullptr;
-    if ((rc = padded_field(G, c, sc, s, &cp))) return rc;
+    const void* cp = sh && sh->made ? sh->cp : nullptr;
+    if (!(sh && sh->made) && (rc = padded_field(G, c, sc, s, &cp))) return rc;
     Plan P;
     if ((rc = make_plan(G, acq, false, s, sc, &P))) return rc;
     const int ns = nshots(acq);
     VdWork w;
     if ((rc = vd_work(G, st, nullptr, ns, own_state, false, sc, s, &w))) return rc;
-    void* part = nullptr;
-    if ((rc = partial_buffer(G, sc, &part))) return rc;
+    void* part = sh && sh->made ? sh->part : nullptr;
+    if (!(sh && sh->made) && (rc = partial_buffer(G, sc, &part))) return rc;
     if ((rc = forward_sweep(G, P, cp, acq, dt, nt, observed, w.st.u_a, w.st.u_b, w.st.acc, st->residual,
                             traces, s, VdFields(), part)))
         return rc;
@@ -64,7 +73,7 @@ int sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double d
 
 int sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int nt, double k,
                   const fd_state* st, double grad_scale, void* grad, const fd_opts* opts, hipStream_t s,
-                  bool own_state, Scratch* ext = nullptr)
+                  bool own_state, Scratch* ext = nullptr, const Shared* sh = nullptr)
 {
     Scratch local(s);
     Scratch& sc = ext ? *ext : local;
@@ -76,14 +85,14 @@ int sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double 
     if (!own_state && (rc = check_state(st, G, nt, acq))) return rc;
     if ((rc = check_dev(grad, G.ncell * dsize(G.dtype), "grad_c"))) return rc;
     pad_rows(&G);
-    const void* cp = nullptr;
-    if ((rc = padded_field(G, c, sc, s, &cp))) return rc;
+    const void* cp = sh && sh->made ? sh->cp : nullptr;
+    if (!(sh && sh->made) && (rc = padded_field(G, c, sc, s, &cp))) return rc;
     Plan P;
     if ((rc = make_plan(G, acq, true, s, sc, &P))) return rc;
     VdWork w;
     if ((rc = vd_work(G, st, nullptr, nshots(acq), own_state, true, sc, s, &w))) return rc;
-    void* part = nullptr;
-    if ((rc = partial_buffer(G, sc, &part))) return rc;
+    void* part = sh && sh->made ? sh->part : nullptr;
+    if (!(sh && sh->made) && (rc = partial_buffer(G, sc, &part))) return rc;
     if ((rc = backward_sweep(G, P, cp, acq, dt, nt, k, w.st.u_a, w.st.u_b, w.st.acc, st->residual, s,
                              VdFields(), part)))
         return rc;
@@ -200,8 +209,10 @@ int vd_sens_forward(const fd_grid* grid, const void* m, const void* b, const fd_
     VdFields vd;
     vd.stiff = bp;
     vd.acc_b = w.acc_b;
+    void* part = nullptr;
+    if ((rc = partial_buffer(G, sc, &part)) || (rc = partial_buffer(G, sc, &vd.part_b))) return rc;
     if ((rc = forward_sweep(G, P, mp, acq, dt, nt, observed, w.st.u_a, w.st.u_b, w.st.acc, st->residual, traces,
-                            s, vd)))
+                            s, vd, part)))
         return rc;
     if ((rc = work_out(G, w, st, acc_b, ns, s))) return rc;   // back to the caller's dense layout
     if (J_host) {
@@ -240,7 +251,9 @@ int vd_sens_backward(const fd_grid* grid, const void* m, const void* b, const fd
     VdFields vd;
     vd.stiff = bp;
     vd.acc_b = w.acc_b;
-    if ((rc = backward_sweep(G, P, mp, acq, dt, nt, k, w.st.u_a, w.st.u_b, w.st.acc, st->residual, s, vd)))
+    void* part = nullptr;
+    if ((rc = partial_buffer(G, sc, &part)) || (rc = partial_buffer(G, sc, &vd.part_b))) return rc;
+    if ((rc = backward_sweep(G, P, mp, acq, dt, nt, k, w.st.u_a, w.st.u_b, w.st.acc, st->residual, s, vd, part)))
         return rc;
     const double sm = grad_scale * 0.5 / k;
     const double sb = -grad_scale * dt * dt / (G.dx * G.dx) * 0.5 / k;
@@ -430,7 +443,7 @@ int exact_gradient(const fd_grid* grid, const void* c, const fd_acq* acq, double
 
 
 // Upper bound of the device scratch of one gradient call on grid G (checked, rows not yet
-// padded): `total` as the stream-ordered pool sees it (freed pieces are reused), and
+// padded): `total` as the stream-ordered pool sees it (counting no reuse of freed pieces), and
 // `arena` when every piece is a new one (scratch carved out of one fixed array).
 struct WorkBytes {
     size_t total = 0, arena = 0;
@@ -461,12 +474,11 @@ WorkBytes workspace_bytes(Geo G, const fd_acq* acq, int nt, int nshots)
                         events * (sizeof(fdw::Event) + sizeof(fdw::EvPlane)) +
                         nrec * (sizeof(int64_t) + 3 * sizeof(int32_t)) + sizeof(int32_t) + 4096;
     WorkBytes w;
-    w.total = bytes + 2 * plan + sizeof(double) * (3 * fdw::kReduceBlocks + 16);
-    // without reuse: the backward half's own padded copy of c and partial sums, the
-    // launch plans of both halves with a second launch shape each, the misfit's
-    // reduction partials and the 256-byte alignment of every piece
-    w.arena = w.total + (padded ? np * es : 0) + (G.dtype == FD_F32 ? np * sizeof(float) : 0) + 2 * plan +
-              sizeof(double) * (fdw::kReduceBlocks + 8) + 256 * (8 * ns + 64);
+    // the launch plans of both halves, each with a second launch shape, and the
+    // reduction partials of the speed check and of the misfit, none of them reused
+    w.total = bytes + 4 * plan + sizeof(double) * (4 * fdw::kReduceBlocks + 16);
+    // and the 256-byte alignment of every piece
+    w.arena = w.total + 256 * (8 * ns + 64);
     return w;
 }
 
@@ -491,9 +503,14 @@ int adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq, d
     HIPCHK(sc.get(&st.u_b, G.ncell_pad * dsize(G.dtype) * nshots(acq)));
     HIPCHK(sc.get(&st.acc, G.ncell_pad * dsize(G.acc_dtype)));
     HIPCHK(sc.get(&st.residual, (size_t)nt * acq->nrec * dsize(G.dtype)));
-    if ((rc = sens_forward(grid, c, acq, dt, nt, observed, &st, traces_or_null, J_host, opts, s, true, &sc)))
+    // c in the row layout of the sweeps and the partial sums, once for both halves
+    if ((rc = check_dev(c, G.ncell * dsize(G.dtype), "c"))) return rc;
+    Shared sh;
+    if ((rc = padded_field(G, c, sc, s, &sh.cp)) || (rc = partial_buffer(G, sc, &sh.part))) return rc;
+    sh.made = true;
+    if ((rc = sens_forward(grid, c, acq, dt, nt, observed, &st, traces_or_null, J_host, opts, s, true, &sc, &sh)))
         return rc;
-    return sens_backward(grid, c, acq, dt, nt, k, &st, 1.0, grad_c, opts, s, true, &sc);
+    return sens_backward(grid, c, acq, dt, nt, k, &st, 1.0, grad_c, opts, s, true, &sc, &sh);
 }
 
 }  // namespace

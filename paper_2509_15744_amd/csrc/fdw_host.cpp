@@ -98,6 +98,7 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
         if (o->chunk_plain < 0) return fail(FD_E_ARG, "chunk_plain is negative");
         G.variant_plain = o->variant_plain;
         G.chunk_plain = o->chunk_plain;
+        G.no_partials = o->no_partials != 0;
     }
     if (G.dtype == FD_F64) G.acc_dtype = FD_F64;
     G.n0 = (int)n[0];
@@ -442,17 +443,20 @@ void set_acc(fdw::StepArgs& a, int terms, int sign)
 // order; each cycle of kPartialCycle of them starts the partial sum, adds to it and
 // folds it into the accumulator at its end, and the sweep's last accumulating launch
 // folds whatever is pending (or adds directly when nothing is).
-int part_mode(int l, int count)
+int cycle_mode(int i, int total)
 {
-    const int i = l >> 1;
-    const int total = (count + 1) >> 1;   // accumulating launches of the run
     const int j = i % fdw::kPartialCycle;
     if (i == total - 1) return j == 0 ? fdw::PM_DIRECT : fdw::PM_FLUSH;
     if (j == 0) return fdw::PM_START;
     return j == fdw::kPartialCycle - 1 ? fdw::PM_FLUSH : fdw::PM_ADD;
 }
 
-bool use_partials(const Geo& G) { return G.dtype == FD_F32 && G.acc_dtype == FD_F64; }
+int part_mode(int l, int count)
+{
+    return cycle_mode(l >> 1, (count + 1) >> 1);   // the run's accumulating launches
+}
+
+bool use_partials(const Geo& G) { return G.dtype == FD_F32 && G.acc_dtype == FD_F64 && !G.no_partials; }
 
 int partial_buffer(const Geo& G, Scratch& sc, void** part)
 {
@@ -466,6 +470,11 @@ void set_acc_at(fdw::StepArgs& a, int l, int count, int sign)
     const int terms = acc_terms(l, count);
     set_acc(a, terms, sign);
     a.part_mode = (terms && a.part) ? part_mode(l, count) : fdw::PM_DIRECT;
+}
+
+void set_face_at(fdw::StepArgs& a, int l, int nlaunch)
+{
+    a.part_b_mode = (a.acc_face && a.part_b) ? cycle_mode(l, nlaunch) : fdw::PM_DIRECT;
 }
 
 int check_time(double dt, int nt)
@@ -493,7 +502,8 @@ int prepare(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, in
 // Forward sweep of every shot group (Alg. 1 forward loop); the wavefields of shot s
 // live at ua/ub + s * ncell_pad (rows possibly padded to G.pitch).  `acc` null: no kernel accumulation (plain forward).  With
 // vd.stiff the variable-material step runs (c is then the mass coefficient) and, with
-// vd.acc_b, every launch adds the stiffness term of its current level.
+// vd.acc_b, every launch adds the stiffness term of its current level (through the
+// partial sums vd.part_b when given).
 int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
                   const void* obs, void* ua, void* ub, void* acc, void* resid, void* traces,
                   hipStream_t s, const VdFields& vd, void* part)
@@ -505,9 +515,10 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
     if (vd.acc_b) HIPCHK(hipMemsetAsync(vd.acc_b, 0, G.ncell_pad * dsize(G.acc_dtype), s));
     fdw::StepArgs a = base_args(G, P, c, dt);
     a.acc = acc;
-    a.part = vd.stiff ? nullptr : part;
+    a.part = part;
     a.stiff = vd.stiff;
     a.acc_b = vd.acc_b;
+    a.part_b = vd.acc_b ? vd.part_b : nullptr;
     a.acc_face = vd.acc_b ? 1 : 0;   // levels 0..nt-1 (level 0 is zero)
     a.wavelet = acq->wavelet;
     a.nsrc = acq->nsrc;
@@ -529,6 +540,7 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
             // intervals 0..nt-2; the last one is settled at hand-over
             if (acc) set_acc_at(a, n, nt - 1, 1);
             else set_acc(a, 0, 1);
+            set_face_at(a, n, nt);
             a.row_src = n;
             a.row_rec = n;
             int rc = step(G, P, gi, a, s);
@@ -562,9 +574,10 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
     const size_t es = dsize(G.dtype);
     fdw::StepArgs a = base_args(G, P, c, dt);
     a.acc = acc;
-    a.part = vd.stiff ? nullptr : part;
+    a.part = part;
     a.stiff = vd.stiff;
     a.acc_b = vd.acc_b;
+    a.part_b = vd.acc_b ? vd.part_b : nullptr;
     a.acc_face = vd.acc_b ? -1 : 0;   // levels nt-1..1 of the superposed field
     a.wavelet = acq->wavelet;
     a.nsrc = acq->nsrc;
@@ -590,6 +603,7 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
             a.row_src = j;
             a.row_rec = j - 1;
             set_acc_at(a, nt - 1 - j, nt - 1, -1);   // intervals nt-2..0
+            set_face_at(a, nt - 1 - j, nt - 1);
             int rc = step(G, P, (int)gi, a, s);
             if (rc) return rc;
             std::swap(vj, vn);

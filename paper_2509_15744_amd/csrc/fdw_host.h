@@ -49,6 +49,7 @@ struct Geo {
     bool auto_variant = true;   // the caller left the variant to the library
     int variant_plain = 0;      // launches without accumulator access: tile variant (0: variant)
     int chunk_plain = 0;        //   and planes per block (0: library choice)
+    bool no_partials = false;   // the caller asked for no f32 partial sums of the kernel terms
     int n0, n1, n2;      // internal extents (2D: n1 = 1)
     int64_t ncell;
     int pitch = 0;       // row stride of the library's own arrays (>= n2; see vd_setup)
@@ -127,6 +128,7 @@ struct Plan {
 struct VdFields {
     const void* stiff = nullptr;
     void* acc_b = nullptr;
+    void* part_b = nullptr;   // f32 partial sums of the stiffness terms, or null
 };
 
 // HIP events around the step launches of one sweep (only when a timing record is asked for).
@@ -199,10 +201,16 @@ void set_acc(fdw::StepArgs& a, int terms, int sign);
 // accumulator), and a buffer for them (ncell_pad floats, or null when not).
 bool use_partials(const Geo& G);
 int partial_buffer(const Geo& G, Scratch& sc, void** part);
-// Partial-sum mode (fdw::PM_*) of launch l of such a run.
+// Partial-sum mode (fdw::PM_*) of the i-th of `total` accumulating launches of a sweep.
+int cycle_mode(int i, int total);
+// Partial-sum mode of launch l of a run of `count` accumulating steps (the accumulating
+// launches are those acc_terms marks).
 int part_mode(int l, int count);
 // acc_terms and, when a.part is set, part_mode of launch l, with the sign of the sweep.
 void set_acc_at(fdw::StepArgs& a, int l, int count, int sign);
+// Partial-sum mode of the stiffness terms of launch l of a sweep of nlaunch launches
+// (variable material: every launch adds them).
+void set_face_at(fdw::StepArgs& a, int l, int nlaunch);
 
 int prepare(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int nt,
             const fd_opts* opts, hipStream_t s, Scratch& sc, Geo* G, bool stats);

@@ -57,6 +57,10 @@ struct StepArgs {
     // accumulator.  part_mode says what this launch does (PM_*); part is the buffer.
     void* part;
     int32_t part_mode;
+    // the same for the stiffness-term accumulator acc_b of the variable-material step,
+    // whose terms every launch adds (cycles of kPartialCycle launches)
+    void* part_b;
+    int32_t part_b_mode;
     // events
     const int32_t* blk_off;  // [nblk + 1] ranges into grp
     const EvPlane* grp;      // per block, its planes that hold events

@@ -13,7 +13,10 @@
 //   * mass term: (u^{n+1} - u^n)^2 per interval, into acc (two intervals every other
 //     launch, as in the constant-density sweeps);
 //   * stiffness term: sum over the faces of the cell of dh/db_i (u_j - u_i)^2 for the
-//     current level, with dh(p, q)/dp = 2 q^2 / (p + q)^2, into acc_b every launch.
+//     current level, with dh(p, q)/dp = 2 q^2 / (p + q)^2, into acc_b every launch;
+//   * with f32 fields and f64 accumulators both terms go through f32 partial sums per
+//     cell, folded into the accumulators every kPartialCycle-th accumulating launch
+//     (part_mode, part_b_mode), as in the constant-density step.
 //
 // Layout of the work follows the constant-density step (2.5D marching along axis 0,
 // three-plane register queues for u and b, the current planes of u and b staged in
@@ -34,6 +37,7 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
 {
     typedef typename Vec<T, VZ>::type vec;
     typedef typename Vec<AT, VZ>::type avec;
+    typedef typename Vec<float, VZ>::type pvec;
     constexpr int NT = TZ * TY;
     constexpr int WZ = TZ * VZ;
     constexpr int RYH = (NDIM == 3) ? 1 : 0;
@@ -74,6 +78,19 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
     AT* __restrict__ accb = (AT*)a.acc_b;
     const bool use_acc = ACC && a.acc_sign != 0;
     const bool use_accb = ACC && a.acc_face != 0;
+    // f32 partial sums of both kernel terms (f32 fields with f64 accumulators): what each
+    // accumulating launch reads and writes (modes as in the constant-density step)
+    constexpr bool PARTS = ACC && sizeof(T) == 4 && sizeof(AT) == 8;
+    float* __restrict__ part = (float*)a.part;
+    float* __restrict__ partb = (float*)a.part_b;
+    const int pm = (PARTS && use_acc) ? a.part_mode : PM_DIRECT;
+    const int pmb = (PARTS && use_accb) ? a.part_b_mode : PM_DIRECT;
+    const bool rd_acc = use_acc && (pm == PM_DIRECT || pm == PM_FLUSH);
+    const bool rd_part = PARTS && use_acc && (pm == PM_ADD || pm == PM_FLUSH);
+    const bool wr_part = PARTS && use_acc && (pm == PM_START || pm == PM_ADD);
+    const bool rd_accb = use_accb && (pmb == PM_DIRECT || pmb == PM_FLUSH);
+    const bool rd_partb = PARTS && use_accb && (pmb == PM_ADD || pmb == PM_FLUSH);
+    const bool wr_partb = PARTS && use_accb && (pmb == PM_START || pmb == PM_ADD);
     const T inv_dx2 = (T)a.w[0];
     const T dt2 = (T)a.dt2;
 
@@ -110,13 +127,16 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
     // plane-x operands, loaded one plane ahead
     vec cu, cm, chyu[NHY1], chyb[NHY1];
     avec ca, cab;
+    pvec cp, cpb;
     T chzu[NHZ], chzb[NHZ];
     {
         const int64_t xo = (int64_t)x0 * ps;
         cu = load_row<T, VZ, true, false>(unew + xo + roff, z, n2);
         cm = load_row<T, VZ, true, false>(mass + xo + roff, z, n2);
-        if (use_acc) ca = load_row<AT, VZ, true, false>(acc + xo + roff, z, n2);
-        if (use_accb) cab = load_row<AT, VZ, true, false>(accb + xo + roff, z, n2);
+        if (rd_acc) ca = load_row<AT, VZ, true, false>(acc + xo + roff, z, n2);
+        if (rd_accb) cab = load_row<AT, VZ, true, false>(accb + xo + roff, z, n2);
+        if (rd_part) cp = load_row<float, VZ, true, false>(part + xo + roff, z, n2);
+        if (rd_partb) cpb = load_row<float, VZ, true, false>(partb + xo + roff, z, n2);
 #pragma unroll
         for (int i = 0; i < NHY; ++i)
             if (hyl[i] >= 0) {
@@ -139,6 +159,7 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
         // issue the loads of plane x + 1
         vec nqu, nqb, ncu, ncm, nhyu[NHY1], nhyb[NHY1];
         avec nca, ncab;
+        pvec ncp, ncpb;
         T nhzu[NHZ], nhzb[NHZ];
         const bool more = x + 1 < x1;
         if (more) {
@@ -148,8 +169,10 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
             nqb = load_row<T, VZ, false, true>(stiff + xq, z, n2);
             ncu = load_row<T, VZ, true, false>(unew + xn + roff, z, n2);
             ncm = load_row<T, VZ, true, false>(mass + xn + roff, z, n2);
-            if (use_acc) nca = load_row<AT, VZ, true, false>(acc + xn + roff, z, n2);
-            if (use_accb) ncab = load_row<AT, VZ, true, false>(accb + xn + roff, z, n2);
+            if (rd_acc) nca = load_row<AT, VZ, true, false>(acc + xn + roff, z, n2);
+            if (rd_accb) ncab = load_row<AT, VZ, true, false>(accb + xn + roff, z, n2);
+            if (rd_part) ncp = load_row<float, VZ, true, false>(part + xn + roff, z, n2);
+            if (rd_partb) ncpb = load_row<float, VZ, true, false>(partb + xn + roff, z, n2);
 #pragma unroll
             for (int i = 0; i < NHY; ++i)
                 if (hyl[i] >= 0) {
@@ -186,6 +209,7 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
         if (live) {
             vec un;
             avec an, abn;
+            pvec pn, pbn;
 #pragma unroll
             for (int i = 0; i < VZ; ++i) {
                 const T u0 = el<T, VZ>(qu[1], i);
@@ -218,17 +242,27 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
                     const AT d = (AT)(uni - u0);
                     const AT dp = a.acc_prev ? (AT)(u0 - cui) : (AT)0;
                     const AT dsum = d * d + dp * dp;
-                    const AT ai = el<AT, VZ>(ca, i);
-                    set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + dsum : ai - dsum);
+                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cp, i) : dsum;
+                    if (rd_acc) {
+                        const AT ai = el<AT, VZ>(ca, i);
+                        set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + tot : ai - tot);
+                    }
+                    if (wr_part) set_el<float, VZ>(pn, i, (float)tot);
                 }
                 if (use_accb) {
-                    const AT bi = el<AT, VZ>(cab, i);
-                    set_el<AT, VZ>(abn, i, a.acc_face > 0 ? bi + (AT)fb : bi - (AT)fb);
+                    const AT totb = rd_partb ? (AT)fb + (AT)el<float, VZ>(cpb, i) : (AT)fb;
+                    if (rd_accb) {
+                        const AT bi = el<AT, VZ>(cab, i);
+                        set_el<AT, VZ>(abn, i, a.acc_face > 0 ? bi + totb : bi - totb);
+                    }
+                    if (wr_partb) set_el<float, VZ>(pbn, i, (float)totb);
                 }
             }
             __builtin_nontemporal_store(un, (vec*)(unew + xo + roff + z));
-            if (use_acc) __builtin_nontemporal_store(an, (avec*)(acc + xo + roff + z));
-            if (use_accb) __builtin_nontemporal_store(abn, (avec*)(accb + xo + roff + z));
+            if (rd_acc) __builtin_nontemporal_store(an, (avec*)(acc + xo + roff + z));
+            if (rd_accb) __builtin_nontemporal_store(abn, (avec*)(accb + xo + roff + z));
+            if (wr_part) __builtin_nontemporal_store(pn, (pvec*)(part + xo + roff + z));
+            if (wr_partb) __builtin_nontemporal_store(pbn, (pvec*)(partb + xo + roff + z));
         }
 
         // rotate to plane x + 1
@@ -237,8 +271,10 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
             qb[0] = qb[1]; qb[1] = qb[2]; qb[2] = nqb;
             cu = ncu;
             cm = ncm;
-            if (use_acc) ca = nca;
-            if (use_accb) cab = ncab;
+            if (rd_acc) ca = nca;
+            if (rd_accb) cab = ncab;
+            if (rd_part) cp = ncp;
+            if (rd_partb) cpb = ncpb;
 #pragma unroll
             for (int i = 0; i < NHY; ++i) { chyu[i] = nhyu[i]; chyb[i] = nhyb[i]; }
 #pragma unroll

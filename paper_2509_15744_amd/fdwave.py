@@ -61,7 +61,8 @@ class fd_opts(ctypes.Structure):
                 ("timing", ctypes.POINTER(fd_timing)), ("chunk", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32),
-                ("variant_plain", ctypes.c_int32), ("chunk_plain", ctypes.c_int32)]
+                ("variant_plain", ctypes.c_int32), ("chunk_plain", ctypes.c_int32),
+                ("no_partials", ctypes.c_int32)]
 
 
 class fd_state(ctypes.Structure):
@@ -238,8 +239,10 @@ class Acquisition:
 
 
 def make_opts(acc_dtype=None, variant=0, timing=None, chunk=0, max_group=0, graph=False,
-              persistent=False, barrier_timeout_us=0, variant_plain=0, chunk_plain=0) -> fd_opts:
+              persistent=False, barrier_timeout_us=0, variant_plain=0, chunk_plain=0,
+              no_partials=False) -> fd_opts:
     o = fd_opts()
+    o.no_partials = int(bool(no_partials))
     o.variant_plain = int(variant_plain)
     o.chunk_plain = int(chunk_plain)
     o.persistent = int(bool(persistent))
