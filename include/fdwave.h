@@ -221,6 +221,24 @@ int fd_adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq
                            double* J_host, void* traces_or_null, const fd_opts* opts,
                            void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): fd_adjoint_sensitivity with the same
+ * arguments and results, whose scratch (wavefields, accumulator, partial sums,
+ * residual rows, padded copies, event tables, reduction partials) is carved out of a
+ * fixed device array of FD_NOALLOC_BYTES that every GPU the library runs on holds
+ * from the library's load until the process ends.  The call performs no device
+ * allocation or release.  A problem whose scratch bound exceeds the array returns
+ * FD_E_ARG with the two sizes in fd_last_error() before any device work.  The array
+ * keeps the last call's contents; the call clears what must start at zero.  Calls on
+ * one GPU share its array: the library serialises them (a per-device lock held until
+ * the call's work on `stream` has finished), so this call always synchronises
+ * `stream`; the current device must be `stream`'s device. */
+#define FD_NOALLOC_BYTES ((size_t)64 << 20)
+int fd_adjoint_sensitivity_noalloc(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
+                                   int32_t nt, const void* observed, double k, void* grad_c,
+                                   double* J_host, void* traces_or_null, const fd_opts* opts,
+                                   void* stream);
+
 /* Exact discrete gradient by re-simulation (the alternative to the superposition that the
  * paper's introduction cites; no stored history, no factor k): a forward sweep with cost
  * and adjoint force but no kernel accumulation, then one backward sweep that steps u

@@ -444,7 +444,7 @@ int exact_gradient(const fd_grid* grid, const void* c, const fd_acq* acq, double
 
 // Upper bound of the device scratch of one gradient call on grid G (checked, rows not yet
 // padded): `total` as the stream-ordered pool sees it (counting no reuse of freed pieces), and
-// `arena` when every piece is a new one (scratch carved out of one fixed array).
+// `arena` when every piece is a new one (the no-allocation entry point).
 struct WorkBytes {
     size_t total = 0, arena = 0;
 };
@@ -511,6 +511,44 @@ int adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq, d
     if ((rc = sens_forward(grid, c, acq, dt, nt, observed, &st, traces_or_null, J_host, opts, s, true, &sc, &sh)))
         return rc;
     return sens_backward(grid, c, acq, dt, nt, k, &st, 1.0, grad_c, opts, s, true, &sc, &sh);
+}
+
+// ---------------------------------------------------------------------------
+// no-allocation form of the gradient: scratch in a fixed device array per GPU
+// ---------------------------------------------------------------------------
+
+constexpr size_t kNoAllocBytes = FD_NOALLOC_BYTES;
+static_assert(kNoAllocBytes % 256 == 0, "the array keeps 256-byte pieces aligned");
+
+// Every GPU the library runs on holds its own copy of this array from the library's
+// load until the process ends.  Host code never names it beyond the one
+// hipGetSymbolAddress per device: kernels get the address kept for their device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+    void* ptr = nullptr;        // device address of this device's array
+    std::mutex call;            // held for a whole call: calls on one device never overlap
+};
+std::mutex g_noalloc_mu;
+std::map<int, std::unique_ptr<NoAllocDevice>> g_noalloc;
+
+// The current device's array (its address looked up once, with that device current).
+int noalloc_device(NoAllocDevice** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc.find(dev);
+    if (it == g_noalloc.end()) {
+        auto d = std::make_unique<NoAllocDevice>();
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(FD_E_DEVICE, "no device address for the scratch array");
+        d->ptr = p;
+        it = g_noalloc.emplace(dev, std::move(d)).first;
+    }
+    *out = it->second.get();
+    return FD_OK;
 }
 
 }  // namespace
@@ -622,6 +660,40 @@ int fd_adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq
     g_err.clear();
     return adjoint_sensitivity(grid, c, acq, dt, nt, observed, k, grad_c, J_host, traces_or_null, opts,
                                (hipStream_t)stream, nullptr);
+}
+
+int fd_adjoint_sensitivity_noalloc(const fd_grid* grid, const void* c, const fd_acq* acq, double dt,
+                                   int32_t nt, const void* observed, double k, void* grad_c,
+                                   double* J_host, void* traces_or_null, const fd_opts* opts, void* stream)
+{
+    g_err.clear();
+    hipStream_t s = (hipStream_t)stream;
+    Geo G;
+    int rc = check_grid(grid, opts, &G);
+    if (rc) return rc;
+    if ((rc = check_time(dt, nt))) return rc;
+    if (!acq) return fail(FD_E_ARG, "acq is null");
+    if (acq->nsrc < 0 || acq->nrec < 0) return fail(FD_E_ARG, "source or receiver count is negative");
+    if (acq->nshot < 0) return fail(FD_E_ARG, "nshot is negative");
+    const size_t need = workspace_bytes(G, acq, nt, nshots(acq)).arena;
+    if (need > kNoAllocBytes) {
+        char buf[240];
+        snprintf(buf, sizeof buf,
+                 "this problem needs up to %zu bytes of scratch; the no-allocation entry point holds at "
+                 "most %zu (FD_NOALLOC_BYTES): use fd_adjoint_sensitivity",
+                 need, kNoAllocBytes);
+        return fail(FD_E_ARG, buf);
+    }
+    NoAllocDevice* d = nullptr;
+    if ((rc = noalloc_device(&d))) return rc;
+    std::lock_guard<std::mutex> lk(d->call);
+    Scratch arena(s, d->ptr, kNoAllocBytes);
+    rc = adjoint_sensitivity(grid, c, acq, dt, nt, observed, k, grad_c, J_host, traces_or_null, opts, s, &arena);
+    // the array is free for the next call only once this call's work has finished
+    const hipError_t e = hipStreamSynchronize(s);
+    if (rc) return rc;
+    HIPCHK(e);
+    return FD_OK;
 }
 
 int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int32_t nt,

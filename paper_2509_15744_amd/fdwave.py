@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libfdwave.so")
 
 FD_OK, FD_E_ARG, FD_E_CFL, FD_E_NOMEM, FD_E_DEVICE, FD_E_NONFINITE = 0, 1, 2, 3, 4, 5
 FD_F32, FD_F64 = 0, 1
+FD_NOALLOC_BYTES = 64 << 20   # the fixed scratch array of the no-allocation entry point
 _CODES = {1: "FD_E_ARG", 2: "FD_E_CFL", 3: "FD_E_NOMEM", 4: "FD_E_DEVICE", 5: "FD_E_NONFINITE"}
 
 
@@ -102,6 +103,7 @@ def _load():
         "fd_forward": ([G, P, A, D, I, P, O, P], ctypes.c_int),
         "fd_misfit": ([I, I, I, D, P, P, P, DP, P], ctypes.c_int),
         "fd_adjoint_sensitivity": ([G, P, A, D, I, P, D, P, DP, P, O, P], ctypes.c_int),
+        "fd_adjoint_sensitivity_noalloc": ([G, P, A, D, I, P, D, P, DP, P, O, P], ctypes.c_int),
         "fd_adjoint_exact": ([G, P, A, D, I, P, P, DP, P, O, P], ctypes.c_int),
         "fd_vd_forward": ([G, P, P, A, D, I, P, O, P], ctypes.c_int),
         "fd_vd_adjoint_sensitivity": ([G, P, P, A, D, I, P, D, P, P, DP, P, O, P], ctypes.c_int),
@@ -336,6 +338,15 @@ def fd_adjoint_sensitivity(c, dx, order, src, wavelet, rec, dt, nt, observed, k,
     """(grad_c, J) of the memory-efficient method at factor ``k``."""
     return _sensitivity(_lib.fd_adjoint_sensitivity, c, dx, order, src, wavelet, rec, dt, nt, observed, k,
                         grad, traces, shots, opts)
+
+
+def fd_adjoint_sensitivity_noalloc(c, dx, order, src, wavelet, rec, dt, nt, observed, k, grad=None,
+                                   traces=None, shots=None, **opts):
+    """``fd_adjoint_sensitivity`` with the library's scratch in its fixed per-device
+    array (no device allocation inside the call; pass ``grad`` to allocate nothing at
+    all).  Problems beyond ``FD_NOALLOC_BYTES`` of scratch raise FD_E_ARG."""
+    return _sensitivity(_lib.fd_adjoint_sensitivity_noalloc, c, dx, order, src, wavelet, rec, dt, nt, observed,
+                        k, grad, traces, shots, opts)
 
 
 def fd_adjoint_exact(c, dx, order, src, wavelet, rec, dt, nt, observed, grad=None, traces=None,

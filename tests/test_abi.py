@@ -244,3 +244,15 @@ def test_batch_plan_argument_checks(fdw):
     assert lib.fd_batch_timing(None, ctypes.byref(t)) == fdw.FD_E_ARG
     assert lib.fd_batch_plan_destroy(None, None) == fdw.FD_OK
 
+
+def test_noalloc_refuses_oversize_problems_on_the_host(fdw):
+    """The no-allocation gradient refuses, before any device work, a problem whose
+    scratch bound exceeds its fixed array, naming both sizes."""
+    g = fdw.make_grid((512, 512, 512), 1.0, 8, fdw.FD_F32)
+    a = fdw.fd_acq()
+    J = ctypes.c_double()
+    rc = fdw.lib().fd_adjoint_sensitivity_noalloc(ctypes.byref(g), None, ctypes.byref(a), 0.1, 10, None, 0.1,
+                                                  None, ctypes.byref(J), None, None, None)
+    assert rc == fdw.FD_E_ARG
+    msg = fdw.lib().fd_last_error().decode()
+    assert "FD_NOALLOC_BYTES" in msg and str(fdw.FD_NOALLOC_BYTES) in msg
