@@ -105,6 +105,30 @@ def gradient_bytes(nt, group, acc, partials=None):
     return sweep_bytes(nt, group, acc, partials, nt) + sweep_bytes(nt, group, acc, partials, nt - 1)
 
 
+def pair_gradient_bytes(nt, acc, partials):
+    """Algorithmic bytes per cell of the launches of one gradient that runs two steps per
+    launch (--pairs): a two-step launch reads u^{n-1}, u^n and c (12 B) and writes two
+    levels (8 B) plus the kernel terms of the one-step schedule's accumulating step it
+    covers (the later of its two steps adds both intervals, or the earlier one its
+    own alone); a last odd step runs as a one-step launch.  Returns (bytes, launches)."""
+    total = launches = 0
+    for nsteps in (nt, nt - 1):   # forward steps n = 0..nt-1, backward l = 0..nt-2
+        l = 0
+        while l + 1 < nsteps:
+            ta, tb = acc_terms(l, nt - 1), acc_terms(l + 1, nt - 1)
+            at = l + 1 if tb == 3 else (l if ta else None)
+            mode = None if at is None else (part_mode(at, nt - 1) if partials else "direct")
+            total += 20 + acc_extra(acc, mode)
+            launches += 1
+            l += 2
+        if l < nsteps:
+            terms = acc_terms(l, nt - 1)
+            mode = None if not terms else (part_mode(l, nt - 1) if partials else "direct")
+            total += launch_bytes(1, acc, mode)
+            launches += 1
+    return total, launches
+
+
 def cycle_mode(i, total):
     """Partial-sum mode of the i-th of `total` accumulating launches of a sweep."""
     j = i % PARTIAL_CYCLE
@@ -332,7 +356,7 @@ def run_single(args, np, torch, fdw, wl):
     acq = fdw.Acquisition(src, w, rec, *(shots if shots else (None, None, 0)))
     opts = dict(acc_dtype=args.acc, variant=best["variant"], chunk=best["chunk"],
                 max_group=best["max_group"], variant_plain=best["variant_plain"],
-                chunk_plain=best["chunk_plain"], no_partials=args.no_partials)
+                chunk_plain=best["chunk_plain"], no_partials=args.no_partials, pairs=args.pairs)
 
     def exact_step(record):
         t = fdw.fd_timing()
@@ -353,6 +377,7 @@ def run_single(args, np, torch, fdw, wl):
                              timing=tb, **opts)
         if record:
             timings.append((tf.fwd_ms, tf.fwd_launches, tb.bwd_ms, tb.bwd_launches))
+            holder["pair_launches"] = tf.fwd_pair_launches + tb.bwd_pair_launches
 
     exact = args.method == "exact"
     elapsed = timed(args, torch, exact_step if exact else one_step)
@@ -372,10 +397,13 @@ def run_single(args, np, torch, fdw, wl):
         group = best["max_group"] or 1
         ngroups = math.ceil(nshot / group)
         per_cell = gradient_bytes(p.nt, group, args.acc, args.acc == "f64" and not args.no_partials)
+        if holder.get("pair_launches"):
+            per_cell, _ = pair_gradient_bytes(p.nt, args.acc, args.acc == "f64" and not args.no_partials)
         bytes_all = ncell * ngroups * per_cell * args.steps
         bpu = per_cell / (2 * p.nt - 1) / group
     cfg = {"workload": desc, "grid": list(p.shape), "nt": p.nt, "order": p.order, "shots": nshot,
            "receivers": len(rec), "accumulator": args.acc, "partial_sums": args.acc == "f64" and not args.no_partials,
+           "two_step_launches": holder.get("pair_launches", 0),
            "method": args.method, "k": holder["k"],
            "J": holder["J"], "launch_shape": best, "cell_updates_per_step": upd}
     acc_info = None
@@ -860,6 +888,8 @@ def main():
                     help="single-medium workloads: the gradient that is timed")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the accuracy section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pairs", type=int, default=0, choices=[-1, 0, 1],
+                    help="1: two time steps per launch (3D, one shot); 0: library choice; -1: never")
     ap.add_argument("--no-partials", action="store_true",
                     help="every accumulating step reads and writes the f64 accumulator (no f32 partial sums)")
     args = ap.parse_args()
@@ -911,7 +941,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args, cfg.get("launch_shape")),
-            "kernel": {"problems2d": "fdw::step_multi_kernel", "vd3d": "fdw::vd_step_kernel",
+            "kernel": "fdw::pair_kernel" if cfg.get("two_step_launches") else
+                      {"problems2d": "fdw::step_multi_kernel", "vd3d": "fdw::vd_step_kernel",
                        "tato2d": "fdw::vd_step_kernel", "fwi3d": "fdw::vd_step_kernel"}.get(
                 args.workload, "fdw::step_kernel"),
             "avg_launch_ms": round(avg_ms, 4),

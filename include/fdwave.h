@@ -103,6 +103,8 @@ typedef struct fd_timing {
     int32_t fwd_launches;   /* forward step launches in that interval */
     double bwd_ms;          /* the same for the backward sweep (superposed or re-simulation) */
     int32_t bwd_launches;
+    int32_t fwd_pair_launches;  /* of the launches: those that advanced two steps (fd_opts.pairs) */
+    int32_t bwd_pair_launches;
 } fd_timing;
 
 typedef struct fd_opts {
@@ -127,6 +129,12 @@ typedef struct fd_opts {
                            keep f32 partial sums of the kernel terms, folded into the
                            accumulator every 16th accumulating step (4 instead of 8 bytes
                            of accumulator traffic per cell update on average) */
+    int32_t pairs;         /* 1: the constant-density 3D sweeps of one shot advance two time
+                           steps per launch (levels n+1 and n+2 from n-1 and n; 28 instead
+                           of 40 bytes per cell for two steps with partial sums; results
+                           equal those of one step per launch) where every extent is at
+                           least the order; 0: library choice (one step per launch);
+                           -1: never.  Takes two more wavefields of scratch */
 } fd_opts;
 
 /* Caller-owned device state that carries one gradient from its forward sweep

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfdwave.so")
-SOURCES = ["fdw_step.hip", "fdw_batch.hip", "fdw_vd.hip", "fdw_design.hip", "fdw_kernels.hip", "fdw_host.cpp",
+SOURCES = ["fdw_step.hip", "fdw_pair.hip", "fdw_batch.hip", "fdw_vd.hip", "fdw_design.hip", "fdw_kernels.hip", "fdw_host.cpp",
            "fdw_api.cpp", "fdw_tune.cpp", "fdw_batch_api.cpp", "fdw_design_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -28,8 +28,17 @@ namespace {
 struct Shared {
     const void* cp = nullptr;
     void* part = nullptr;
+    PairPlan pp;
+    PairSweep pw;
     bool made = false;
 };
+
+// The two-step launch plan of a half (or the fused call's), when its sweeps use them.
+int pair_setup(const Geo& G, const fd_acq* acq, hipStream_t s, Scratch& sc, PairPlan* pp, PairSweep* pw)
+{
+    if (!use_pairs(G, acq)) return FD_OK;
+    return make_pair_sweep(G, acq, s, sc, pp, pw);
+}
 
 // `own_state`: the state arrays were allocated by the library itself in this call.
 // `ext`: take scratch from this (arena) instead of the stream-ordered pool.
@@ -57,8 +66,12 @@ int sens_forward(const fd_grid* grid, const void* c, const fd_acq* acq, double d
     if ((rc = vd_work(G, st, nullptr, ns, own_state, false, sc, s, &w))) return rc;
     void* part = sh && sh->made ? sh->part : nullptr;
     if (!(sh && sh->made) && (rc = partial_buffer(G, sc, &part))) return rc;
+    PairPlan pp_own;
+    PairSweep pw_own;
+    if (!(sh && sh->made) && (rc = pair_setup(G, acq, s, sc, &pp_own, &pw_own))) return rc;
+    const PairSweep* pw = sh && sh->made ? &sh->pw : &pw_own;
     if ((rc = forward_sweep(G, P, cp, acq, dt, nt, observed, w.st.u_a, w.st.u_b, w.st.acc, st->residual,
-                            traces, s, VdFields(), part)))
+                            traces, s, VdFields(), part, pw)))
         return rc;
     if ((rc = work_out(G, w, st, nullptr, ns, s))) return rc;   // back to the caller's dense layout
     if (J_host) {
@@ -93,8 +106,12 @@ int sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, double 
     if ((rc = vd_work(G, st, nullptr, nshots(acq), own_state, true, sc, s, &w))) return rc;
     void* part = sh && sh->made ? sh->part : nullptr;
     if (!(sh && sh->made) && (rc = partial_buffer(G, sc, &part))) return rc;
+    PairPlan pp_own;
+    PairSweep pw_own;
+    if (!(sh && sh->made) && (rc = pair_setup(G, acq, s, sc, &pp_own, &pw_own))) return rc;
+    const PairSweep* pw = sh && sh->made ? &sh->pw : &pw_own;
     if ((rc = backward_sweep(G, P, cp, acq, dt, nt, k, w.st.u_a, w.st.u_b, w.st.acc, st->residual, s,
-                             VdFields(), part)))
+                             VdFields(), part, pw)))
         return rc;
     if (G.pitch == G.n2) {
         HIPCHK(fdw::launch_finalize(G.dtype, G.acc_dtype, G.ncell, w.st.acc, c, grad_scale / k, grad, s));
@@ -507,6 +524,8 @@ int adjoint_sensitivity(const fd_grid* grid, const void* c, const fd_acq* acq, d
     if ((rc = check_dev(c, G.ncell * dsize(G.dtype), "c"))) return rc;
     Shared sh;
     if ((rc = padded_field(G, c, sc, s, &sh.cp)) || (rc = partial_buffer(G, sc, &sh.part))) return rc;
+    // the two-step plan reads the acquisition's cells: check them first
+    if ((rc = check_acq(acq, G, nt)) || (rc = pair_setup(G, acq, s, sc, &sh.pp, &sh.pw))) return rc;
     sh.made = true;
     if ((rc = sens_forward(grid, c, acq, dt, nt, observed, &st, traces_or_null, J_host, opts, s, true, &sc, &sh)))
         return rc;

@@ -99,6 +99,8 @@ int check_grid(const fd_grid* g, const fd_opts* o, Geo* out)
         G.variant_plain = o->variant_plain;
         G.chunk_plain = o->chunk_plain;
         G.no_partials = o->no_partials != 0;
+        if (o->pairs < -1 || o->pairs > 1) return fail(FD_E_ARG, "pairs must be -1, 0 or 1");
+        G.pairs = o->pairs;
     }
     if (G.dtype == FD_F64) G.acc_dtype = FD_F64;
     G.n0 = (int)n[0];
@@ -484,6 +486,203 @@ int check_time(double dt, int nt)
     return FD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// two steps per launch
+// ---------------------------------------------------------------------------
+
+bool use_pairs(const Geo& G, const fd_acq* acq)
+{
+    if (G.pairs <= 0 || G.ndim != 3 || (acq && nshots(acq) != 1)) return false;
+    return G.n0 >= 2 * G.r && G.n1 >= 2 * G.r && G.n2 >= 2 * G.r;
+}
+
+namespace {
+
+int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Positions along one axis (in [-r, n + r)) that stand for cell c: the cell itself and
+// its mirror images past the walls.
+int mirror_positions(int c, int n, int r, int* pos)
+{
+    int k = 0;
+    pos[k++] = c;
+    if (-1 - c >= -r) pos[k++] = -1 - c;
+    if (2 * n - 1 - c < n + r) pos[k++] = 2 * n - 1 - c;
+    return k;
+}
+
+}  // namespace
+
+int make_pair_sweep(const Geo& G, const fd_acq* acq, hipStream_t s, Scratch& sc, PairPlan* PP, PairSweep* ws)
+{
+    constexpr int TZ = fdw::kPairTZ, TY = fdw::kPairTY;
+    const int R = G.r;
+    Geo T = G;
+    T.variant = 1;   // the pair kernel's tile: 64 x 8, one cell per lane
+    T.auto_variant = false;
+    T.max_group = 1;
+    T.variant_plain = 0;
+    T.chunk = 0;   // the library's split of axis 0 (chunks of at least 16 r planes in 3D:
+                   // the ring adds 2r planes of level n+1 and 2r of queue per chunk)
+    int rc = make_plan(T, acq, false, s, sc, &PP->tile);
+    if (rc) return rc;
+    const Plan& P = PP->tile;
+    const int nty = P.nty, ntz = P.ntz, nch = P.nch, C = P.chunk;
+    const int nstrip = 2 * R * TZ;
+    // ring events: every position of every block's ring of level n+1 that stands for an
+    // event's cell, with the plane and lane the kernel walks
+    struct Item { int64_t key; fdw::Event e; };
+    std::vector<Item> items;
+    auto add_cell = [&](int64_t cell, int kind, int idx) {
+        const int64_t plane = (int64_t)G.n1 * G.n2;
+        const int cx = (int)(cell / plane);
+        const int64_t rem = cell - (int64_t)cx * plane;
+        const int cy = (int)(rem / G.n2), cz = (int)(rem - (int64_t)cy * G.n2);
+        int px[3], py[3], pz[3];
+        const int nx = mirror_positions(cx, G.n0, R, px);
+        const int ny = mirror_positions(cy, G.n1, R, py);
+        const int nz = mirror_positions(cz, G.n2, R, pz);
+        for (int ix = 0; ix < nx; ++ix)
+            for (int iy = 0; iy < ny; ++iy)
+                for (int iz = 0; iz < nz; ++iz) {
+                    const int x = px[ix], y = py[iy], z = pz[iz];
+                    auto emit = [&](int tyb, int tzb, int lane) {
+                        for (int ch = floordiv(x, C) - 1; ch <= floordiv(x, C) + 1; ++ch) {
+                            if (ch < 0 || ch >= nch) continue;
+                            const int x0 = ch * C, x1 = std::min(x0 + C, G.n0);
+                            if (x < x0 - R || x >= x1 + R) continue;
+                            fdw::Event e;
+                            e.plane = x;
+                            e.lane = lane;
+                            e.kind = kind;
+                            e.idx = idx;
+                            items.push_back({((int64_t)ch * nty + tyb) * ntz + tzb, e});
+                        }
+                    };
+                    const bool yin = y >= 0 && y < nty * TY, zin = z >= 0 && z < ntz * TZ;
+                    if (yin && zin) {   // a tile cell
+                        const int tyb = y / TY, tzb = z / TZ;
+                        emit(tyb, tzb, (y - tyb * TY) * TZ + (z - tzb * TZ));
+                    }
+                    if (zin) {          // ring rows above and below tiles
+                        const int tzb = z / TZ;
+                        for (int tyb = floordiv(y, TY) - 1; tyb <= floordiv(y, TY) + 1; ++tyb) {
+                            if (tyb < 0 || tyb >= nty) continue;
+                            const int y0 = tyb * TY;
+                            int sr = -1;
+                            if (y >= y0 - R && y < y0) sr = y - (y0 - R);
+                            else if (y >= y0 + TY && y < y0 + TY + R) sr = R + (y - (y0 + TY));
+                            if (sr >= 0) emit(tyb, tzb, TY * TZ + sr * TZ + (z - tzb * TZ));
+                        }
+                    }
+                    if (yin) {          // ring columns left and right of tiles
+                        const int tyb = y / TY;
+                        for (int tzb = floordiv(z, TZ) - 1; tzb <= floordiv(z, TZ) + 1; ++tzb) {
+                            if (tzb < 0 || tzb >= ntz) continue;
+                            const int z0 = tzb * TZ;
+                            int side = -1, col = 0;
+                            if (z >= z0 - R && z < z0) { side = 0; col = z - (z0 - R); }
+                            else if (z >= z0 + TZ && z < z0 + TZ + R) { side = 1; col = z - (z0 + TZ); }
+                            if (side >= 0)
+                                emit(tyb, tzb, TY * TZ + nstrip + side * (R * TY) + (y - tyb * TY) * R + col);
+                        }
+                    }
+                }
+    };
+    const int nsrc = acq ? acq->nsrc : 0;
+    const int nrec = acq ? acq->nrec : 0;
+    for (int i = 0; i < nsrc; ++i) add_cell(acq->src_cell[i], fdw::EV_SRC, i);
+    for (int i = 0; i < nrec; ++i) add_cell(acq->rec_cell[i], fdw::EV_REC, i);
+    std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+        if (a.key != b.key) return a.key < b.key;
+        if (a.e.plane != b.e.plane) return a.e.plane < b.e.plane;
+        if (a.e.lane != b.e.lane) return a.e.lane < b.e.lane;
+        if (a.e.kind != b.e.kind) return a.e.kind < b.e.kind;
+        return a.e.idx < b.e.idx;
+    });
+    std::vector<int32_t> off(P.nblk + 1, 0);
+    std::vector<fdw::EvPlane> grp;
+    std::vector<fdw::Event> ev(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+        ev[i] = items[i].e;
+        if (i == 0 || items[i].key != items[i - 1].key || ev[i].plane != ev[i - 1].plane) {
+            fdw::EvPlane g;
+            g.plane = ev[i].plane;
+            g.begin = g.end = (int32_t)i;
+            g.pad = 0;
+            grp.push_back(g);
+            off[items[i].key + 1]++;
+        }
+        grp.back().end = (int32_t)i + 1;
+    }
+    for (int b = 0; b < P.nblk; ++b) off[b + 1] += off[b];
+    // every block's groups lie on planes its walk visits, in increasing order, with
+    // ranges inside the event table (the kernel reads the table where these say)
+    for (int b = 0; b < P.nblk; ++b) {
+        const int ch = b / (ntz * nty);
+        const int x0 = ch * C, x1 = std::min(x0 + C, G.n0);
+        for (int g = off[b]; g < off[b + 1]; ++g) {
+            const fdw::EvPlane& q = grp[g];
+            if (q.plane < x0 - R || q.plane >= x1 + R || (g > off[b] && q.plane <= grp[g - 1].plane) ||
+                q.begin < 0 || q.end <= q.begin || q.end > (int32_t)ev.size())
+                return fail(FD_E_DEVICE, "internal error: inconsistent ring event table");
+        }
+    }
+    HIPCHK(sc.get((void**)&PP->d_off_a, sizeof(int32_t) * off.size()));
+    HIPCHK(sc.get((void**)&PP->d_grp_a, sizeof(fdw::EvPlane) * std::max<size_t>(1, grp.size())));
+    HIPCHK(sc.get((void**)&PP->d_ev_a, sizeof(fdw::Event) * std::max<size_t>(1, ev.size())));
+    HIPCHK(hipMemcpyAsync(PP->d_off_a, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, s));
+    if (!grp.empty())
+        HIPCHK(hipMemcpyAsync(PP->d_grp_a, grp.data(), sizeof(fdw::EvPlane) * grp.size(), hipMemcpyHostToDevice, s));
+    if (!ev.empty())
+        HIPCHK(hipMemcpyAsync(PP->d_ev_a, ev.data(), sizeof(fdw::Event) * ev.size(), hipMemcpyHostToDevice, s));
+    if (ws) {
+        ws->pp = PP;
+        const size_t fb = G.ncell_pad * dsize(G.dtype);
+        HIPCHK(sc.get(&ws->xa, fb));
+        HIPCHK(sc.get(&ws->xb, fb));
+    }
+    HIPCHK(hipStreamSynchronize(s));   // the host tables die with this frame
+    return FD_OK;
+}
+
+namespace {
+
+// Kernel terms of the two-step launch over steps l, l + 1 of a run of `count`
+// accumulating steps: both intervals when step l + 1 adds two in the one-step schedule,
+// the first alone when step l is the run's last accumulating step; the partial-sum
+// mode of that step.
+void set_pair_acc(fdw::PairArgs& p, int l, int count, int sign)
+{
+    const int ta = acc_terms(l, count), tb = acc_terms(l + 1, count);
+    int terms = 0, at = 0;
+    if (tb == 3) { terms = 3; at = l + 1; }
+    else if (ta != 0) { terms = 1; at = l; }
+    p.terms = terms;
+    p.s.acc_sign = terms ? sign : 0;
+    p.s.acc_prev = 0;
+    p.s.part_mode = (terms && p.s.part) ? part_mode(at, count) : fdw::PM_DIRECT;
+}
+
+fdw::PairArgs pair_args(const Geo& G, const PairPlan& PP, const void* c, double dt, const fd_acq* acq)
+{
+    fdw::PairArgs p;
+    std::memset(&p, 0, sizeof(p));
+    p.s = base_args(G, PP.tile, c, dt);
+    p.s.blk_off = PP.tile.groups[0].d_off;
+    p.s.grp = PP.tile.groups[0].d_grp;
+    p.s.ev = PP.tile.groups[0].d_ev;
+    p.s.wavelet = acq->wavelet;
+    p.s.nsrc = acq->nsrc;
+    p.s.nrec = acq->nrec;
+    p.blk_off_a = PP.d_off_a;
+    p.grp_a = PP.d_grp_a;
+    p.ev_a = PP.d_ev_a;
+    return p;
+}
+
+}  // namespace
+
 // Validation shared by the sweeps: grid, acquisition, time axis, speed, CFL.
 int prepare(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, int nt,
             const fd_opts* opts, hipStream_t s, Scratch& sc, Geo* G, bool stats)
@@ -506,7 +705,7 @@ int prepare(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, in
 // partial sums vd.part_b when given).
 int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
                   const void* obs, void* ua, void* ub, void* acc, void* resid, void* traces,
-                  hipStream_t s, const VdFields& vd, void* part)
+                  hipStream_t s, const VdFields& vd, void* part, const PairSweep* pw)
 {
     const size_t fb = G.ncell_pad * dsize(G.dtype) * nshots(acq);
     HIPCHK(hipMemsetAsync(ua, 0, fb, s));
@@ -530,6 +729,56 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
     const size_t es = dsize(G.dtype);
     SweepTimer tm(G.timing != nullptr, s);
     tm.start();
+    int pair_launches = 0;
+    if (pw && pw->pp && !vd.stiff) {
+        // two steps per launch, alternating between the pairs (ua, ub) and (xa, xb); a
+        // last odd step runs as one step in place
+        fdw::PairArgs p = pair_args(G, *pw->pp, c, dt, acq);
+        p.s.acc = acc;
+        p.s.part = part;
+        p.s.sample = 1;
+        p.s.traces = traces;
+        p.s.resid = resid;
+        p.s.obs = obs;
+        void* bufs[2][2] = {{ua, ub}, {pw->xa, pw->xb}};
+        int k = 0, n = 0;
+        for (; n + 1 < nt; n += 2, k ^= 1) {
+            p.s.unew = bufs[k][0];
+            p.s.ucur = bufs[k][1];
+            p.out1 = bufs[k ^ 1][0];
+            p.out2 = bufs[k ^ 1][1];
+            p.s.row_src = p.s.row_rec = n;
+            p.row_src2 = p.row_rec2 = n + 1;
+            if (acc) set_pair_acc(p, n, nt - 1, 1);
+            else p.terms = 0;
+            HIPCHK(fdw::launch_pair(G.r, G.dtype, G.acc_dtype, pw->pp->tile.nblk, p, s));
+            ++pair_launches;
+        }
+        void* prev = bufs[k][0];
+        void* cur = bufs[k][1];
+        if (n < nt) {
+            a.ucur = cur;
+            a.unew = prev;
+            if (acc) set_acc_at(a, n, nt - 1, 1);
+            else set_acc(a, 0, 1);
+            a.row_src = a.row_rec = n;
+            int rc = step(G, P, 0, a, s);
+            if (rc) return rc;
+        }
+        // after an odd number of two-step launches the levels sit in (xa, xb): move them
+        // to where final_levels names them
+        if (k == 1) {
+            HIPCHK(hipMemcpyAsync(ua, pw->xa, G.ncell_pad * es, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(ub, pw->xb, G.ncell_pad * es, hipMemcpyDeviceToDevice, s));
+        }
+        tm.stop();
+        if (G.timing) {
+            G.timing->fwd_ms = tm.ms();
+            G.timing->fwd_launches = pair_launches + (nt & 1);
+            G.timing->fwd_pair_launches = pair_launches;
+        }
+        return FD_OK;
+    }
     for (int gi = 0; gi < (int)P.groups.size(); ++gi) {
         const Group& gr = P.groups[gi];
         char* prev = (char*)ua + (size_t)gr.g0 * G.ncell_pad * es;   // level n-1
@@ -552,6 +801,7 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
     if (G.timing) {
         G.timing->fwd_ms = tm.ms();
         G.timing->fwd_launches = nt * (int)P.groups.size();
+        G.timing->fwd_pair_launches = 0;
     }
     return FD_OK;
 }
@@ -565,7 +815,7 @@ void final_levels(void* ua, void* ub, int nt, void** prev, void** cur)
 
 int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
                    double k, void* ua, void* ub, void* acc, void* resid, hipStream_t s,
-                   const VdFields& vd, void* part)
+                   const VdFields& vd, void* part, const PairSweep* pw)
 {
     void* up = nullptr;   // u^{nt-1} -> v^{nt-1}
     void* ul = nullptr;   // u^nt = v^nt
@@ -597,6 +847,48 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
                                         (const char*)resid + (size_t)(nt - 1) * acq->nrec * es,
                                         rec_scale, s));
         if (gi == 0) tm.start();
+        if (pw && pw->pp && !vd.stiff) {
+            // steps j, j - 1 per launch (l = nt - 1 - j even), a last odd step in place
+            fdw::PairArgs p = pair_args(G, *pw->pp, c, dt, acq);
+            p.s.acc = acc;
+            p.s.part = part;
+            p.s.inject_rec = 1;
+            p.s.resid = resid;
+            p.s.rec_scale = rec_scale;
+            void* bufs[2][2] = {{vn, vj}, {pw->xa, pw->xb}};   // (level j+1, level j)
+            int kk = 0, l = 0, pairs = 0;
+            for (; l + 1 < nt - 1; l += 2, kk ^= 1) {
+                const int j = nt - 1 - l;
+                p.s.unew = bufs[kk][0];
+                p.s.ucur = bufs[kk][1];
+                p.out1 = bufs[kk ^ 1][0];
+                p.out2 = bufs[kk ^ 1][1];
+                p.s.row_src = j;
+                p.s.row_rec = j - 1;
+                p.row_src2 = j - 1;
+                p.row_rec2 = j - 2;
+                set_pair_acc(p, l, nt - 1, -1);
+                HIPCHK(fdw::launch_pair(G.r, G.dtype, G.acc_dtype, pw->pp->tile.nblk, p, s));
+                ++pairs;
+            }
+            if (l < nt - 1) {
+                const int j = nt - 1 - l;
+                a.ucur = bufs[kk][1];
+                a.unew = bufs[kk][0];
+                a.row_src = j;
+                a.row_rec = j - 1;
+                set_acc_at(a, l, nt - 1, -1);
+                int rc = step(G, P, (int)gi, a, s);
+                if (rc) return rc;
+            }
+            tm.stop();
+            if (G.timing) {
+                G.timing->bwd_ms = tm.ms();
+                G.timing->bwd_launches = pairs + ((nt - 1) & 1);
+                G.timing->bwd_pair_launches = pairs;
+            }
+            return FD_OK;
+        }
         for (int j = nt - 1; j >= 1; --j) {
             a.ucur = vj;
             a.unew = vn;
@@ -613,6 +905,7 @@ int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq
     if (G.timing) {
         G.timing->bwd_ms = tm.ms();
         G.timing->bwd_launches = (nt - 1) * (int)P.groups.size();
+        G.timing->bwd_pair_launches = 0;
     }
     return FD_OK;
 }

@@ -15,6 +15,7 @@
 
 #include "../../include/fdwave.h"
 #include "fdw_internal.h"
+#include "fdw_pair.h"
 
 namespace fdh {
 
@@ -50,6 +51,7 @@ struct Geo {
     int variant_plain = 0;      // launches without accumulator access: tile variant (0: variant)
     int chunk_plain = 0;        //   and planes per block (0: library choice)
     bool no_partials = false;   // the caller asked for no f32 partial sums of the kernel terms
+    int pairs = 0;              // two steps per launch: 1 where they fit, 0 library choice, -1 never
     int n0, n1, n2;      // internal extents (2D: n1 = 1)
     int64_t ncell;
     int pitch = 0;       // row stride of the library's own arrays (>= n2; see vd_setup)
@@ -121,6 +123,27 @@ struct Plan {
     int32_t* d_uoff = nullptr;
     int32_t* d_uidx = nullptr;
     int32_t* d_ushot = nullptr;
+};
+
+// Block decomposition and events of the two-step launches (fdw_pair.hip): the tiles of
+// step variant 1 (64 x 8, one cell per lane) in chunks along axis 0.  `tile` carries the
+// tile events (its shot group 0); d_off_a / d_grp_a / d_ev_a list, per block and plane,
+// the events in the block's ring of level n+1 (the tile and R cells around it in the
+// in-plane directions, planes x0 - R .. x1 + R - 1, positions past a wall standing for
+// the mirrored cell).
+struct PairPlan {
+    Plan tile;
+    int32_t* d_off_a = nullptr;
+    fdw::EvPlane* d_grp_a = nullptr;
+    fdw::Event* d_ev_a = nullptr;
+};
+
+// What a sweep needs for two-step launches: the plan and a second pair of wavefields
+// (ncell_pad elements each, the launches alternate between the two pairs).
+struct PairSweep {
+    const PairPlan* pp = nullptr;
+    void* xa = nullptr;
+    void* xb = nullptr;
 };
 
 // The variable-material fields of a sweep: stiffness b and its accumulator (null for
@@ -216,13 +239,21 @@ int prepare(const fd_grid* grid, const void* c, const fd_acq* acq, double dt, in
             const fd_opts* opts, hipStream_t s, Scratch& sc, Geo* G, bool stats);
 // `part`: a partial-sum buffer of ncell_pad floats for the kernel terms (f32 fields with
 // an f64 accumulator, constant density only), or null to add them to acc directly.
+// `pw`: run the steps two per launch where pw->pp is set (constant density).
 int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
                   const void* obs, void* ua, void* ub, void* acc, void* resid, void* traces,
-                  hipStream_t s, const VdFields& vd = VdFields(), void* part = nullptr);
+                  hipStream_t s, const VdFields& vd = VdFields(), void* part = nullptr,
+                  const PairSweep* pw = nullptr);
 void final_levels(void* ua, void* ub, int nt, void** prev, void** cur);
 int backward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq, double dt, int nt,
                    double k, void* ua, void* ub, void* acc, void* resid, hipStream_t s,
-                   const VdFields& vd = VdFields(), void* part = nullptr);
+                   const VdFields& vd = VdFields(), void* part = nullptr, const PairSweep* pw = nullptr);
+// Whether the sweeps of (G, acq) run two steps per launch: 3D, one shot, every extent
+// at least twice the stencil radius, asked for (G.pairs > 0).
+bool use_pairs(const Geo& G, const fd_acq* acq);
+// The plan of the two-step launches (G with rows already padded) and, with ws, the
+// second pair of wavefields.
+int make_pair_sweep(const Geo& G, const fd_acq* acq, hipStream_t s, Scratch& sc, PairPlan* PP, PairSweep* ws);
 // Fixed-order sum of (x - y)^2 (x^2 when y is null) into *out (host); synchronises.
 int misfit_sum(int dtype, const void* x, const void* y, void* diff, int64_t n, hipStream_t s,
                Scratch& sc, double* out);

@@ -134,7 +134,19 @@ struct EventStage {
 };
 
 // A block's walk over its plane groups (all fields block-uniform).  The next group
-// is read one plane group ahead; plane x's events are ev[ea, e).
+// is read one plane group ahead; plane x's events are ev[ea, e).  Planes may be
+// negative (the two-step launches walk mirrored planes past the wall at x = 0), so an
+// exhausted walk holds kNoPlane, which no plane equals, and an empty range.
+constexpr int kNoPlane = -2147483647 - 1;
+
+__device__ __forceinline__ EvPlane no_plane()
+{
+    EvPlane g;
+    g.plane = kNoPlane;
+    g.begin = g.end = g.pad = 0;
+    return g;
+}
+
 struct PlaneEvents {
     int gi, g_end;
     EvPlane next;
@@ -146,8 +158,7 @@ __device__ __forceinline__ void events_begin(PlaneEvents& pe, const StepArgs& a,
 {
     pe.gi = a.blk_off[b];
     pe.g_end = a.blk_off[b + 1];
-    pe.next.plane = -1;
-    if (pe.gi < pe.g_end) pe.next = a.grp[pe.gi];
+    pe.next = pe.gi < pe.g_end ? a.grp[pe.gi] : no_plane();
 }
 
 // Finds plane x's events and, when they fit, stages them with their values (all
@@ -164,8 +175,7 @@ __device__ __forceinline__ void events_at_plane(PlaneEvents& pe, const StepArgs&
     if (!pe.has) return;
     pe.ea = pe.next.begin;
     pe.e = pe.next.end;
-    pe.next.plane = -1;
-    if (++pe.gi < pe.g_end) pe.next = a.grp[pe.gi];
+    pe.next = ++pe.gi < pe.g_end ? a.grp[pe.gi] : no_plane();
     pe.staged = pe.e - pe.ea <= kStagedEvents;
     if (!pe.staged) return;
     for (int t = tid; t < pe.e - pe.ea; t += NT) {
@@ -455,7 +465,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                         if (s & 1) dsum += dpair * d + dpair_p * dp;
                         else { dpair = d; dpair_p = dp; }
                     } else {
-                        dsum += d * d + dp * dp;
+                        // one explicit rounding order, which the two-step launches repeat
+                        dsum += fma(d, d, dp * dp);
                     }
                     if (a.sample && pe.has) sample_receivers(pe, a, est, lane0[k] + i, s, uni);
                 }

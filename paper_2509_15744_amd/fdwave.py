@@ -54,7 +54,8 @@ class fd_acq(ctypes.Structure):
 
 class fd_timing(ctypes.Structure):
     _fields_ = [("fwd_ms", ctypes.c_double), ("fwd_launches", ctypes.c_int32),
-                ("bwd_ms", ctypes.c_double), ("bwd_launches", ctypes.c_int32)]
+                ("bwd_ms", ctypes.c_double), ("bwd_launches", ctypes.c_int32),
+                ("fwd_pair_launches", ctypes.c_int32), ("bwd_pair_launches", ctypes.c_int32)]
 
 
 class fd_opts(ctypes.Structure):
@@ -63,7 +64,7 @@ class fd_opts(ctypes.Structure):
                 ("max_group", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32),
                 ("variant_plain", ctypes.c_int32), ("chunk_plain", ctypes.c_int32),
-                ("no_partials", ctypes.c_int32)]
+                ("no_partials", ctypes.c_int32), ("pairs", ctypes.c_int32)]
 
 
 class fd_state(ctypes.Structure):
@@ -242,9 +243,10 @@ class Acquisition:
 
 def make_opts(acc_dtype=None, variant=0, timing=None, chunk=0, max_group=0, graph=False,
               persistent=False, barrier_timeout_us=0, variant_plain=0, chunk_plain=0,
-              no_partials=False) -> fd_opts:
+              no_partials=False, pairs=0) -> fd_opts:
     o = fd_opts()
     o.no_partials = int(bool(no_partials))
+    o.pairs = int(pairs)
     o.variant_plain = int(variant_plain)
     o.chunk_plain = int(chunk_plain)
     o.persistent = int(bool(persistent))
