@@ -722,7 +722,7 @@ def run_problems(args, np, torch, fdw, wl):
     # one batch plan (host work once), run per step on the current stream; with --graph
     # the run is captured once and each step replays the graph
     plan = fdw.BatchPlan(items, persistent=args.persistent, timing=fdw.fd_timing(), variant=args.variant or 1,
-                         acc_dtype=args.acc)
+                         acc_dtype=args.acc, chunk=args.chunk)
     J = torch.zeros(len(items), dtype=torch.float64, device="cuda")
     graph = None
     if args.graph:
@@ -750,6 +750,7 @@ def run_problems(args, np, torch, fdw, wl):
     per_cell = gradient_bytes(nt, 1, args.acc)
     bytes_all = ncell_all * per_cell * args.steps
     cfg = {"workload": desc, "sides": sides, "nt": nt, "order": 8, "problems": 16, "variant": args.variant or 1,
+           "chunk": args.chunk or "library",
            "accumulator": args.acc, "graph": bool(args.graph), "persistent": bool(args.persistent),
            "cell_updates_per_step": upd, "plan": "one fd_batch_plan; steps run it"
            + (" as a captured graph replay" if args.graph else " directly")}

@@ -1,10 +1,11 @@
 // Multi-problem step kernels of fdwave: several independent problems advance one
-// step in one launch (step_multi_kernel), or walk a whole sweep in one cooperative
-// launch with a bounded grid barrier between steps (step_persistent_kernel).  The
-// per-tile work is step_body in fdw_step_body.h.
+// step in one launch (step_multi_kernel), or walk a whole sweep in one launch whose
+// running blocks own fixed sets of tiles and wait only for the neighbouring tiles
+// (step_persistent_kernel).  The per-tile work is step_body in fdw_step_body.h.
 
 #include <algorithm>
 
+#include "fdw_batch.h"
 #include "fdw_step_body.h"
 
 namespace fdw {
@@ -31,59 +32,144 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_multi_kernel(const StepArgs
     step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, 1>(a, g - block_start[lo], lds);
 }
 
-// Grid-wide barrier with a bounded wait.  bar[0] counts arrivals, bar[1] is the
-// generation, bar[2] an error flag.  A block that waits longer than `timeout`
-// wall-clock ticks sets the flag and gives up; every block checks the flag after
-// each barrier and leaves, so the launch always ends even if some blocks could not
-// be resident at once.  Returns false when the caller must leave.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, long long timeout)
+// Progress of a persistent sweep, tile by tile.  done[g] counts the steps tile g has
+// finished in this launch; a tile starts step st once each tile its stencil reaches
+// has finished step st - 1: those tiles wrote the level it reads, and read the level
+// it overwrites.  The neighbours are the tiles one over along each axis: the in-plane
+// halo reaches one tile left/right (and, in 3D, above/below), the axis-0 queue one
+// chunk back and ahead (tiles are at least r wide and chunks at least r long, so a
+// mirrored cell past a wall lies in the tile itself or in such a neighbour).
+//
+// Waits are bounded: a tile that waits longer than `timeout` wall-clock ticks sets
+// err, and every wait gives up once err is set, so the launch ends whatever happens.
+struct Progress {
+    unsigned* done;
+    unsigned* err;
+    long long timeout;
+};
+
+// Publishes that tile `g` finished step `st` (every thread of the block calls it).
+// Each wave waits until its stores have reached the L2; after the barrier one agent-
+// scope release (an L2 write-back) covers the whole block's writes.  One write-back
+// per tile and step, not one per wave: each walks the XCD's L2.
+__device__ __forceinline__ void publish_step(const Progress& pr, int g, int st)
 {
-    __shared__ int leave;
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        int err = 0;
-        const unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned arrived = atomicAdd(bar, 1u) + 1u;
-        if (arrived == nblocks) {
-            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const long long t0 = wall_clock64();
-            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-                if (wall_clock64() - t0 > timeout) {
-                    atomicExch(bar + 2, 1u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        __threadfence();
-        err = __hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-        leave = err;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(pr.done + g, (unsigned)(st + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    return !leave;
 }
 
-// A whole sweep of several problems in one launch: the resident blocks walk the
-// sweep's steps; within a step each block takes the logical blocks slot, slot + G,
-// ... (slot remapped so consecutive tiles share an XCD), and a bounded grid barrier
-// separates the steps.  Launched cooperatively with a grid sized well inside the
-// resident capacity; the bounded barrier is the exit condition if residency fails.
+// Waits until the neighbours of tile b (of the problem whose tiles start at done0)
+// have finished step st - 1.  Block-uniform result: false when the launch must end.
+__device__ __forceinline__ bool wait_neighbours(const Progress& pr, const StepArgs& a, const unsigned* done0,
+                                                int b, int st, int ndim)
+{
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    const int tzb = b % a.ntz, rest = b / a.ntz, tyb = rest % a.nty, chb = rest / a.nty;
+    const int nch = a.nblk / (a.ntz * a.nty);
+    // lane i < 6 watches neighbour i: -z, +z, -x, +x, -y, +y
+    int nb = -1;
+    if (tid < 2 * ndim) {
+        const int ax = tid >> 1, dir = (tid & 1) ? 1 : -1;
+        if (ax == 0 && tzb + dir >= 0 && tzb + dir < a.ntz) nb = b + dir;
+        if (ax == 1 && chb + dir >= 0 && chb + dir < nch) nb = b + dir * a.ntz * a.nty;
+        if (ax == 2 && tyb + dir >= 0 && tyb + dir < a.nty) nb = b + dir * a.ntz;
+    }
+    if (nb >= 0) {
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(done0 + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)st) {
+            if (__hip_atomic_load(pr.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                bad = 1;
+                break;
+            }
+            if (wall_clock64() - t0 > pr.timeout) {
+                atomicExch(pr.err, 1u);
+                bad = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        // the neighbour's writes: one invalidation of this CU's L1 and the XCD's L2
+        // serves the block, whose waves all run on this CU and read after the barrier
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return bad == 0;
+}
+
+// The blocks of a persistent launch that take part: every block counts itself in on
+// arrival (arrival order idx); the last of the G blocks to arrive fixes the count at G,
+// and if that does not happen within `window` ticks (the device holds fewer blocks at
+// once than the grid has), the first block to notice fixes it at the arrivals so far.
+// A block whose idx is below the fixed count is running, so the static tile
+// assignment among those blocks cannot wait on a block that never starts; later
+// blocks leave.  Returns the count (block-uniform) and sets *idx.
+__device__ __forceinline__ int join_persistent(unsigned* bar, long long window, int* idx)
+{
+    __shared__ int s_idx, s_part;
+    if (threadIdx.x == 0) {
+        unsigned* arrivals = bar + 4;
+        unsigned* fixed = bar + 5;
+        const unsigned G = gridDim.x;
+        const unsigned me = __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (me + 1u == G) {
+            unsigned expect = 0u;
+            __hip_atomic_compare_exchange_strong(fixed, &expect, G, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const long long t0 = wall_clock64();
+        unsigned part;
+        while ((part = __hip_atomic_load(fixed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0u) {
+            if (wall_clock64() - t0 > window) {
+                unsigned expect = 0u;
+                const unsigned now = __hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_compare_exchange_strong(fixed, &expect, now, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_idx = (int)me;
+        s_part = (int)part;
+    }
+    __syncthreads();
+    *idx = s_idx;
+    return s_part;
+}
+
+// A whole sweep of several problems in one launch.  The P taking part blocks
+// (join_persistent) walk the steps; within a step each block takes the tiles slot,
+// slot + P, ... (with all G blocks taking part, slot is remapped so that consecutive
+// tiles share an XCD; otherwise it is the arrival order).  There is no grid-wide
+// barrier: a tile waits for its neighbours' previous step only (Progress), so blocks
+// drift apart by up to a step and none idles at the end of a step.  Every block
+// handles its tiles in (step, tile) order, each tile always in the same block, and a
+// step's work depends on the previous step's only, so the waits cannot form a cycle
+// among running blocks; the bounded waits end the launch whatever happens.
 template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
 __global__ __launch_bounds__(TZ*(TY / RY)) void step_persistent_kernel(
     const StepArgs* __restrict__ table, const int32_t* __restrict__ block_start, int nprob,
-    int total, int nsteps, unsigned* bar, long long timeout)
+    int total, int nsteps, unsigned* bar, long long timeout, long long window)
 {
     typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, 1> SH;
     __shared__ __attribute__((aligned(16))) T lds[SH::LDS];
+    int idx = 0;
+    const int P = join_persistent(bar, window, &idx);
+    if (idx >= P) return;
     const int G = gridDim.x;
-    const int slot = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
+    const int slot = P == G ? (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : idx;   // G: a multiple of 8
+    Progress pr;
+    pr.done = bar + kProgressWords;
+    pr.err = bar + 2;
+    pr.timeout = timeout;
     for (int st = 0; st < nsteps; ++st) {
         const StepArgs* t = table + (size_t)st * nprob;
-        for (int g = slot; g < total; g += G) {
+        for (int g = slot; g < total; g += P) {
             int lo = 0, hi = nprob;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -91,11 +177,13 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_persistent_kernel(
                 else hi = mid;
             }
             const StepArgs a = t[lo];
-            if (!a.active) continue;
-            __syncthreads();   // the previous tile's last LDS reads are done
-            step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, 1>(a, g - block_start[lo], lds);
+            const int b = g - block_start[lo];
+            if (a.active) {
+                if (st > 0 && !wait_neighbours(pr, a, pr.done + block_start[lo], b, st, NDIM)) return;
+                step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, 1>(a, b, lds);
+            }
+            publish_step(pr, g, st);   // also orders this tile's LDS reads before the next tile's writes
         }
-        if (!grid_barrier(bar, (unsigned)G, timeout)) return;
     }
 }
 
@@ -129,10 +217,16 @@ static hipError_t launch_multi_rt(int ndim, int variant, const StepArgs* t, cons
     return hipErrorInvalidValue;
 }
 
-// Resident blocks per CU of the persistent grid: the smallest of what the occupancy
-// calculator allows for the kernel's registers and LDS, the device's limit of resident
-// blocks per CU, and kPersistentBlocksPerCU.
-constexpr int kPersistentBlocksPerCU = 8;
+// Blocks of the persistent grid: the occupancy calculator's blocks per CU for this
+// kernel's registers, LDS and block size (waves per SIMD from the VGPR count within the
+// 8 a SIMD holds, blocks from those waves and from the LDS per CU), times the CUs,
+// rounded down to a multiple of 8.  The figure sizes the grid and the tiles (about one
+// tile per block and step); the blocks that actually run together are counted at run
+// time (join_persistent), so a calculator that counts more blocks than the device
+// holds at once costs a short wait, not a deadlock.  (The device attribute of
+// resident blocks per multiprocessor reports threads per CU over the largest block,
+// 2048 / 1024 = 2, not a limit for smaller blocks.)
+constexpr long long kJoinWindowTicks = 20000;   // 200 us of the 100 MHz wall clock
 template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
 static hipError_t launch_persistent_one(const StepArgs* t, const int32_t* bs, int nprob, int total,
                                         int nsteps, unsigned* bar, long long timeout, hipStream_t s,
@@ -140,23 +234,21 @@ static hipError_t launch_persistent_one(const StepArgs* t, const int32_t* bs, in
 {
     auto kern = step_persistent_kernel<R, T, AT, NDIM, TZ, TY, RY, VZ>;
     const int threads = TZ * (TY / RY);
-    int per_cu = 0, dev = 0, cus = 0, slots = 0;
+    int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
     if (e != hipSuccess) return e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&slots, hipDeviceAttributeMaxBlocksPerMultiProcessor, dev)) != hipSuccess)
-        return e;
-    if (slots > 0) per_cu = std::min(per_cu, slots);
-    per_cu = std::min(per_cu, kPersistentBlocksPerCU);
-    int grid = per_cu * cus;
-    grid = std::min(grid, ((total + 7) / 8) * 8);
-    grid = (grid / 8) * 8;
-    if (grid < 8) return hipErrorInvalidConfiguration;
+    const int capacity = std::max(8, (per_cu * cus / 8) * 8);
+    if (!t) {   // capacity query
+        *grid_used = capacity;
+        return hipSuccess;
+    }
+    const int grid = std::min(capacity, ((total + 7) / 8) * 8);
     *grid_used = grid;
-    void* args[] = {(void*)&t, (void*)&bs, (void*)&nprob, (void*)&total, (void*)&nsteps,
-                    (void*)&bar, (void*)&timeout};
-    return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(threads), args, 0, s);
+    const long long window = kJoinWindowTicks;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, s, t, bs, nprob, total, nsteps, bar, timeout, window);
+    return hipGetLastError();
 }
 
 template <int R, typename T, typename AT>
@@ -201,6 +293,12 @@ hipError_t launch_step_persistent(int ndim, int r, int dtype, int acc_dtype, int
     case 4: return launch_persistent_r<4>(ndim, dtype, acc_dtype, variant, d_table, d_block_start, nprob, total_blocks, nsteps, d_barrier, timeout_ticks, s, grid_used);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t persistent_capacity(int ndim, int r, int dtype, int acc_dtype, int variant, int* blocks)
+{
+    return launch_step_persistent(ndim, r, dtype, acc_dtype, variant, nullptr, nullptr, 0, 0, 0, nullptr, 0,
+                                  nullptr, blocks);
 }
 
 template <int R>

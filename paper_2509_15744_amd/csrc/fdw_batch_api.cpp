@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "fdw_batch.h"
 #include "fdw_host.h"
 
 using namespace fdh;
@@ -34,7 +35,8 @@ struct fd_batch_plan {
     fdw::StepArgs* d_tab = nullptr;  // (nfw + nbw) rows of nprob step arguments
     int32_t* d_bstart = nullptr;     // first block of each problem in a launch
     double* d_part = nullptr;        // reduction partials
-    unsigned* d_bar = nullptr;       // persistent launches: arrivals, generation, error flag
+    unsigned* d_bar = nullptr;       // persistent launches: error flag, then per-tile progress
+    int capacity = 0;                // persistent launches: blocks of the grid
     long long timeout_ticks = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sweep timing (opts.timing)
     bool timed = false;
@@ -42,6 +44,45 @@ struct fd_batch_plan {
 };
 
 namespace {
+
+// Axis-0 chunks of a persistent plan: the shortest common chunk length L at which the
+// union of the problems' tiles fits the grid, so that a block marches about one tile
+// per step (tiles of L rows, except a problem's last chunk and problems shorter than
+// L).  Short chunks would make each block march many tiles per step, each paying its
+// queue fill and its wait for the neighbouring tiles.  A caller's chunk stays if it is
+// at least r rows long (a tile's queue then reaches only the adjacent chunks).
+int persistent_chunks(std::vector<Geo>& G, int cap)
+{
+    const fdw::Variant v = fdw::variant_shape(G[0].ndim, G[0].variant);
+    int hi = 1;
+    for (const Geo& g : G) {
+        if (g.chunk > 0 && g.chunk < g.r && g.chunk < g.n0)
+            return fail(FD_E_ARG, "persistent launches need chunks of at least r rows");
+        hi = std::max(hi, g.n0);
+    }
+    auto tiles_at = [&](int L) {
+        int64_t n = 0;
+        for (const Geo& g : G) {
+            const int64_t plane = (int64_t)((g.n2 + v.tz - 1) / v.tz) * ((g.n1 + v.ty - 1) / v.ty);
+            const int c = std::min(g.chunk > 0 ? g.chunk : L, g.n0);
+            n += plane * ((g.n0 + c - 1) / c);
+        }
+        return n;
+    };
+    int lo = std::min(G[0].r, hi);
+    if (tiles_at(hi) > cap) {
+        lo = hi;   // even whole-axis chunks exceed the grid: blocks take several tiles
+    } else {
+        while (lo < hi) {   // smallest L with tiles_at(L) <= cap (tiles_at falls as L grows)
+            const int mid = lo + (hi - lo) / 2;
+            if (tiles_at(mid) <= cap) hi = mid;
+            else lo = mid + 1;
+        }
+    }
+    for (Geo& g : G)
+        if (g.chunk <= 0) g.chunk = std::min(lo, g.n0);
+    return FD_OK;
+}
 
 int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStream_t s, fd_batch_plan** out)
 {
@@ -87,6 +128,11 @@ int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStre
         const int v = G[0].variant;
         const bool ok = v == 1 || v == 2 || (G[0].ndim == 2 && (v == 4 || v == 5));
         if (!ok) return fail(FD_E_ARG, "batched calls run tile variants 1 and 2 (2D also 4 and 5)");
+    }
+    if (B.G0.persistent) {
+        HIPCHK(fdw::persistent_capacity(G[0].ndim, G[0].r, G[0].dtype, G[0].acc_dtype, G[0].variant, &B.capacity));
+        if (B.capacity < 8) return fail(FD_E_DEVICE, "persistent launch: the step kernel does not fit the device");
+        if ((rc = persistent_chunks(G, B.capacity))) return rc;
     }
     {
         std::vector<const Geo*> gs;
@@ -191,8 +237,9 @@ int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStre
     HIPCHK(hipMemcpyAsync(B.d_tab, tab.data(), sizeof(fdw::StepArgs) * tab.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(B.d_bstart, bstart.data(), sizeof(int32_t) * bstart.size(), hipMemcpyHostToDevice, s));
     if (B.G0.persistent) {
-        // barrier words, zeroed by every run; the bounded wait in device wall-clock ticks
-        HIPCHK(sc.get((void**)&B.d_bar, 4 * sizeof(unsigned)));
+        // error flag and per-tile progress, zeroed by kernels in every run; the bounded
+        // wait in device wall-clock ticks
+        HIPCHK(sc.get((void**)&B.d_bar, sizeof(unsigned) * ((size_t)fdw::kProgressWords + B.total)));
         int dev = 0, khz = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
@@ -217,6 +264,9 @@ int plan_sweep(const fd_batch_plan& B, int first, int count, hipStream_t s)
     const fdw::StepArgs* rows = B.d_tab + (size_t)first * B.nprob;
     if (G0.persistent) {
         int grid = 0;
+        // the arrival count, the number of blocks taking part and the tiles' progress
+        // start at zero in every sweep (the error flag, word 2, spans the run)
+        HIPCHK(fdw::launch_zero(B.d_bar + 4, sizeof(unsigned) * ((size_t)fdw::kProgressWords - 4 + B.total), s));
         HIPCHK(fdw::launch_step_persistent(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant, rows, B.d_bstart,
                                            B.nprob, B.total, count, B.d_bar, B.timeout_ticks, s, &grid));
         return FD_OK;
@@ -245,7 +295,7 @@ int plan_run(fd_batch_plan* B, double* J_dev, hipStream_t s)
             HIPCHK(fdw::launch_copy_rows(B->cpad[p], G.pitch, B->probs[p].c, G.n2, dsize(G.dtype),
                                          (int64_t)G.n0 * G.n1, G.n2, s));
     }
-    if (B->d_bar) HIPCHK(fdw::launch_zero(B->d_bar, 4 * sizeof(unsigned), s));
+    if (B->d_bar) HIPCHK(fdw::launch_zero(B->d_bar, sizeof(unsigned) * fdw::kProgressWords, s));
     if (B->timed) HIPCHK(hipEventRecord(B->ev[0], s));
     if ((rc = plan_sweep(*B, 0, B->nfw, s))) return rc;
     if (B->timed) HIPCHK(hipEventRecord(B->ev[1], s));
@@ -344,24 +394,17 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         HIPCHK(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
         const int rc2 = plan_run(B, J_dev, ws);
         hipError_t e = hipStreamEndCapture(ws, &graph);
-        if ((rc2 || e != hipSuccess) && B->G0.persistent) {
-            // this runtime cannot capture a cooperative launch: run the plan directly
-            if (graph) (void)hipGraphDestroy(graph);
-            (void)hipGetLastError();
-            g_err.clear();
-        } else {
-            if (rc2) { if (graph) (void)hipGraphDestroy(graph); return rc2; }
-            HIPCHK(e);
-            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) { (void)hipGraphDestroy(graph); HIPCHK(e); }
-            e = hipGraphLaunch(exec, ws);
-            const hipError_t e2 = hipStreamSynchronize(ws);
-            (void)hipGraphExecDestroy(exec);
-            (void)hipGraphDestroy(graph);
-            HIPCHK(e);
-            HIPCHK(e2);
-            ran = true;
-        }
+        if (rc2) { if (graph) (void)hipGraphDestroy(graph); return rc2; }
+        HIPCHK(e);
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { (void)hipGraphDestroy(graph); HIPCHK(e); }
+        e = hipGraphLaunch(exec, ws);
+        const hipError_t e2 = hipStreamSynchronize(ws);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(e);
+        HIPCHK(e2);
+        ran = true;
     }
     if (!ran && (rc = plan_run(B, J_dev, ws))) return rc;
     if (B->timed && (rc = plan_timing(B, B->G0.timing))) return rc;
@@ -370,8 +413,9 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         HIPCHK(hipMemcpyAsync(&flag, B->d_bar + 2, sizeof(flag), hipMemcpyDeviceToHost, ws));
         HIPCHK(hipStreamSynchronize(ws));
         if (flag != 0)
-            return fail(FD_E_DEVICE, "persistent launch: a grid barrier wait timed out (not all blocks "
-                                     "could be resident); the results are invalid");
+            return fail(FD_E_DEVICE, "persistent launch: a wait for neighbouring tiles timed out "
+                                     "(barrier_timeout_us is shorter than a tile's step); the "
+                                     "results are invalid");
     }
     HIPCHK(hipMemcpyAsync(J_host, J_dev, sizeof(double) * nprob, hipMemcpyDeviceToHost, ws));
     HIPCHK(hipStreamSynchronize(ws));

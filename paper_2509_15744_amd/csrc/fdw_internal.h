@@ -107,22 +107,6 @@ Variant variant_shape(int ndim, int variant);  // variant in 1..count
 hipError_t launch_step(int ndim, int r, int dtype, int acc_dtype, int variant, int shots,
                        int nblk, const StepArgs& a, hipStream_t s);
 
-// One step of several problems in one launch: table[p] holds problem p's
-// arguments, block_start[p] its first block (block_start[nprob] = total).
-hipError_t launch_step_multi(int ndim, int r, int dtype, int acc_dtype, int variant,
-                             const StepArgs* d_table, const int32_t* d_block_start, int nprob,
-                             int total_blocks, hipStream_t s);
-
-// `nsteps` consecutive steps (table rows of nprob entries each) of several problems in
-// one cooperative launch with a bounded grid barrier between steps.  d_barrier: three
-// zeroed unsigned words (arrivals, generation, error flag); a barrier wait longer than
-// timeout_ticks (device wall clock) sets the error flag and ends the launch early.
-// *grid_used receives the number of blocks launched.
-hipError_t launch_step_persistent(int ndim, int r, int dtype, int acc_dtype, int variant,
-                                  const StepArgs* d_table, const int32_t* d_block_start, int nprob,
-                                  int total_blocks, int nsteps, unsigned* d_barrier,
-                                  long long timeout_ticks, hipStream_t s, int* grid_used);
-
 // One step of the variable-material second-order scheme (one wavefield; tile shapes of
 // step variants 1 and 2).  a.c is the mass coefficient, a.stiff the stiffness.
 hipError_t launch_vd_step(int ndim, int dtype, int acc_dtype, int variant, int nblk, const StepArgs& a,

@@ -46,6 +46,9 @@
 
 #include "fdw_internal.h"
 
+// qualifier of pointers into device (global) memory
+#define GLOBAL_AS __attribute__((address_space(1)))
+
 namespace fdw {
 
 
@@ -89,8 +92,8 @@ __device__ __forceinline__ typename Vec<T, V>::type reversed(const typename Vec<
 // aligned vector that holds its mirrored ghost cells and, when MIRROR, reverses it:
 // cell z + i maps to 2 n2 - 1 - z - i.  Without MIRROR such lanes get in-bounds values
 // they never use.
-template <typename T, int V, bool STREAM, bool MIRROR>
-__device__ __forceinline__ typename Vec<T, V>::type load_row(const T* row, int z, int n2)
+template <typename T, int V, bool STREAM, bool MIRROR, typename PTR>
+__device__ __forceinline__ typename Vec<T, V>::type load_row(PTR row, int z, int n2)
 {
     typedef typename Vec<T, V>::type vec;
     const bool past = z >= n2;
@@ -147,6 +150,28 @@ __device__ __forceinline__ EvPlane no_plane()
     return g;
 }
 
+// Group i and event i of the tables in device memory (global loads, field by field).
+__device__ __forceinline__ EvPlane read_group(const EvPlane* grp, int i)
+{
+    const GLOBAL_AS int32_t* q = (const GLOBAL_AS int32_t*)(grp + i);
+    EvPlane g;
+    g.plane = q[0];
+    g.begin = q[1];
+    g.end = q[2];
+    g.pad = q[3];
+    return g;
+}
+__device__ __forceinline__ Event read_event(const Event* ev, int i)
+{
+    const GLOBAL_AS int32_t* q = (const GLOBAL_AS int32_t*)(ev + i);
+    Event e;
+    e.plane = q[0];
+    e.lane = q[1];
+    e.kind = q[2];
+    e.idx = q[3];
+    return e;
+}
+
 struct PlaneEvents {
     int gi, g_end;
     EvPlane next;
@@ -156,9 +181,9 @@ struct PlaneEvents {
 
 __device__ __forceinline__ void events_begin(PlaneEvents& pe, const StepArgs& a, int b)
 {
-    pe.gi = a.blk_off[b];
-    pe.g_end = a.blk_off[b + 1];
-    pe.next = pe.gi < pe.g_end ? a.grp[pe.gi] : no_plane();
+    pe.gi = ((const GLOBAL_AS int32_t*)a.blk_off)[b];
+    pe.g_end = ((const GLOBAL_AS int32_t*)a.blk_off)[b + 1];
+    pe.next = pe.gi < pe.g_end ? read_group(a.grp, pe.gi) : no_plane();
 }
 
 // Finds plane x's events and, when they fit, stages them with their values (all
@@ -175,18 +200,18 @@ __device__ __forceinline__ void events_at_plane(PlaneEvents& pe, const StepArgs&
     if (!pe.has) return;
     pe.ea = pe.next.begin;
     pe.e = pe.next.end;
-    pe.next = ++pe.gi < pe.g_end ? a.grp[pe.gi] : no_plane();
+    pe.next = ++pe.gi < pe.g_end ? read_group(a.grp, pe.gi) : no_plane();
     pe.staged = pe.e - pe.ea <= kStagedEvents;
     if (!pe.staged) return;
     for (int t = tid; t < pe.e - pe.ea; t += NT) {
-        const Event ev = a.ev[pe.ea + t];
+        const Event ev = read_event(a.ev, pe.ea + t);
         T v = (T)0, o = (T)0;
         if (ev_kind(ev.kind) == EV_SRC) {
-            v = ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
+            v = ((const GLOBAL_AS T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
         } else {
             const int64_t r = (int64_t)a.row_rec * a.nrec + ev.idx;
-            if (a.inject_rec) v = (T)a.rec_scale * ((const T*)a.resid)[r];
-            if (a.sample && a.resid) o = ((const T*)a.obs)[r];
+            if (a.inject_rec) v = (T)a.rec_scale * ((const GLOBAL_AS T*)a.resid)[r];
+            if (a.sample && a.resid) o = ((const GLOBAL_AS T*)a.obs)[r];
         }
         st.key[pe.eb][t] = (ev.lane << 8) | ev.kind;
         st.idx[pe.eb][t] = ev.idx;
@@ -210,12 +235,12 @@ __device__ __forceinline__ T point_force(const PlaneEvents& pe, const StepArgs& 
         }
     } else {
         for (int v = pe.ea; v < pe.e; ++v) {
-            const Event ev = a.ev[v];
+            const Event ev = read_event(a.ev, v);
             if (ev.lane != lane || ev_shot(ev.kind) != s) continue;
             if (ev_kind(ev.kind) == EV_SRC)
-                f += ((const T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
+                f += ((const GLOBAL_AS T*)a.wavelet)[(int64_t)a.row_src * a.nsrc + ev.idx] * (T)a.inv_vol;
             else if (a.inject_rec)
-                f += (T)a.rec_scale * ((const T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
+                f += (T)a.rec_scale * ((const GLOBAL_AS T*)a.resid)[(int64_t)a.row_rec * a.nrec + ev.idx];
         }
     }
     return f;
@@ -231,16 +256,16 @@ __device__ __forceinline__ void sample_receivers(const PlaneEvents& pe, const St
         for (int t = 0; t < pe.e - pe.ea; ++t) {
             if (st.key[pe.eb][t] != want) continue;
             const int64_t o = (int64_t)a.row_rec * a.nrec + st.idx[pe.eb][t];
-            if (a.traces) ((T*)a.traces)[o] = uni;
-            if (a.resid) ((T*)a.resid)[o] = uni - st.obs[pe.eb][t];
+            if (a.traces) ((GLOBAL_AS T*)a.traces)[o] = uni;
+            if (a.resid) ((GLOBAL_AS T*)a.resid)[o] = uni - st.obs[pe.eb][t];
         }
     } else {
         for (int v = pe.ea; v < pe.e; ++v) {
-            const Event ev = a.ev[v];
+            const Event ev = read_event(a.ev, v);
             if (ev.lane != lane || ev.kind != (EV_REC | (s << 1))) continue;
             const int64_t o = (int64_t)a.row_rec * a.nrec + ev.idx;
-            if (a.traces) ((T*)a.traces)[o] = uni;
-            if (a.resid) ((T*)a.resid)[o] = uni - ((const T*)a.obs)[o];
+            if (a.traces) ((GLOBAL_AS T*)a.traces)[o] = uni;
+            if (a.resid) ((GLOBAL_AS T*)a.resid)[o] = uni - ((const GLOBAL_AS T*)a.obs)[o];
         }
     }
 }
@@ -278,14 +303,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
     const int64_t ps = (int64_t)n1 * pitch;
     const int64_t sst = a.shot_stride;
 
-    const T* __restrict__ ucur = (const T*)a.ucur;
-    T* __restrict__ unew = (T*)a.unew;
-    const T* __restrict__ cc = (const T*)a.c;
-    AT* __restrict__ acc = (AT*)a.acc;
+    // the buffers are device memory: pointers in the global address space give global
+    // loads even when `a` was read from a table in memory (generic pointers would give
+    // flat loads, whose waits also wait for the LDS traffic and serialise the
+    // plane-ahead loads with the plane's LDS work)
+    const GLOBAL_AS T* __restrict__ ucur = (const GLOBAL_AS T*)a.ucur;
+    GLOBAL_AS T* __restrict__ unew = (GLOBAL_AS T*)a.unew;
+    const GLOBAL_AS T* __restrict__ cc = (const GLOBAL_AS T*)a.c;
+    GLOBAL_AS AT* __restrict__ acc = (GLOBAL_AS AT*)a.acc;
     const bool use_acc = ACC && a.acc_sign != 0;
     // f32 partial sums of the kernel terms exist for f32 fields with an f64 accumulator
     constexpr bool PARTS = ACC && sizeof(T) == 4 && sizeof(AT) == 8;
-    float* __restrict__ part = (float*)a.part;
+    GLOBAL_AS float* __restrict__ part = (GLOBAL_AS float*)a.part;
     const int pmode = (PARTS && use_acc) ? a.part_mode : PM_DIRECT;
     const bool rd_acc = use_acc && (pmode == PM_DIRECT || pmode == PM_FLUSH);
     const bool rd_part = PARTS && use_acc && (pmode == PM_ADD || pmode == PM_FLUSH);
@@ -343,31 +372,42 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                 q[s][k][d] = load_row<T, VZ, false, true>(
                     ucur + s * sst + (int64_t)ghost(x0 - R + d, n0) * ps + roff[k], z, n2);
 
-    // plane-x operands, loaded one plane ahead
-    vec cu[S][RY], cv[RY], chy[S][NHY1];
-    avec ca[RY];
-    pvec cpt[RY];
-    T chz[S][NHZ];
-    {
-        const int64_t xo = (int64_t)x0 * ps;
+    // operands of one plane xp: the queue entry u^n(xp + R), u^{n-1}, c, accumulator
+    // and partial sums of the own cells, and the in-plane halo of u^n
+    struct PlaneOps {
+        vec q[S][RY], u[S][RY], v[RY], hy[S][NHY1];
+        avec a[RY];
+        pvec pt[RY];
+        T hz[S][NHZ];
+    };
+    auto load_ops = [&](PlaneOps& o, int xp, bool with_q) {
+        const int64_t xn = (int64_t)xp * ps;
+        const int64_t xq = (int64_t)ghost(xp + R, n0) * ps;
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                cu[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xo + roff[k], z, n2);
-            cv[k] = load_row<T, VZ, true, false>(cc + xo + roff[k], z, n2);
-            if (rd_acc) ca[k] = load_row<AT, VZ, true, false>(acc + xo + roff[k], z, n2);
-            if (rd_part) cpt[k] = load_row<float, VZ, true, false>(part + xo + roff[k], z, n2);
+            for (int s = 0; s < S; ++s) {
+                if (with_q) o.q[s][k] = load_row<T, VZ, false, true>(ucur + s * sst + xq + roff[k], z, n2);
+                o.u[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xn + roff[k], z, n2);
+            }
+            o.v[k] = load_row<T, VZ, true, false>(cc + xn + roff[k], z, n2);
+            if (rd_acc) o.a[k] = load_row<AT, VZ, true, false>(acc + xn + roff[k], z, n2);
+            if (rd_part) o.pt[k] = load_row<float, VZ, true, false>(part + xn + roff[k], z, n2);
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
 #pragma unroll
             for (int i = 0; i < NHY; ++i)
-                if (hyl[i] >= 0) chy[s][i] = load_row<T, VZ, false, true>(ucur + s * sst + xo + hyr[i], hyz[i], n2);
+                if (hyl[i] >= 0) o.hy[s][i] = load_row<T, VZ, false, true>(ucur + s * sst + xn + hyr[i], hyz[i], n2);
 #pragma unroll
-            for (int i = 0; i < NHZ; ++i) chz[s][i] = hzl[i] >= 0 ? ucur[s * sst + xo + hzg[i]] : (T)0;
+            for (int i = 0; i < NHZ; ++i) o.hz[s][i] = hzl[i] >= 0 ? ucur[s * sst + xn + hzg[i]] : (T)0;
         }
-    }
+    };
+
+    // plane-x operands (its queue entry is already in q); those of plane x + 1 load
+    // while plane x computes
+    PlaneOps cur, next;
+    load_ops(cur, x0, false);
 
     // events: a plane's sources and receivers (and their wavelet, adjoint force and
     // observed values) are staged in LDS, so lanes scan them without global loads
@@ -377,35 +417,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
 
     for (int x = x0; x < x1; ++x) {
         const int64_t xo = (int64_t)x * ps;
-        // issue the loads of plane x + 1
-        vec nq[S][RY], nu[S][RY], nv[RY], nhy[S][NHY1];
-        avec na[RY];
-        pvec npt[RY];
-        T nhz[S][NHZ];
         const bool more = x + 1 < x1;
-        if (more) {
-            const int64_t xn = xo + ps;
-            const int64_t xq = (int64_t)ghost(x + 1 + R, n0) * ps;
-#pragma unroll
-            for (int k = 0; k < RY; ++k) {
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    nq[s][k] = load_row<T, VZ, false, true>(ucur + s * sst + xq + roff[k], z, n2);
-                    nu[s][k] = load_row<T, VZ, true, false>(unew + s * sst + xn + roff[k], z, n2);
-                }
-                nv[k] = load_row<T, VZ, true, false>(cc + xn + roff[k], z, n2);
-                if (rd_acc) na[k] = load_row<AT, VZ, true, false>(acc + xn + roff[k], z, n2);
-                if (rd_part) npt[k] = load_row<float, VZ, true, false>(part + xn + roff[k], z, n2);
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-#pragma unroll
-                for (int i = 0; i < NHY; ++i)
-                    if (hyl[i] >= 0) nhy[s][i] = load_row<T, VZ, false, true>(ucur + s * sst + xn + hyr[i], hyz[i], n2);
-#pragma unroll
-                for (int i = 0; i < NHZ; ++i) nhz[s][i] = hzl[i] >= 0 ? ucur[s * sst + xn + hzg[i]] : (T)0;
-            }
-        }
+        if (more) load_ops(next, x + 1, true);
 
         // stage plane x of every shot
 #pragma unroll
@@ -415,10 +428,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
             for (int k = 0; k < RY; ++k) *(vec*)(L + lofs[k]) = q[s][k][R];
 #pragma unroll
             for (int i = 0; i < NHY; ++i)
-                if (hyl[i] >= 0) *(vec*)(L + hyl[i]) = chy[s][i];
+                if (hyl[i] >= 0) *(vec*)(L + hyl[i]) = cur.hy[s][i];
 #pragma unroll
             for (int i = 0; i < NHZ; ++i)
-                if (hzl[i] >= 0) L[hzl[i]] = chz[s][i];
+                if (hzl[i] >= 0) L[hzl[i]] = cur.hz[s][i];
         }
         events_at_plane<T, NT>(pe, a, est, x, tid);
         __syncthreads();
@@ -433,7 +446,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
             const T* L0 = lds + (x & 1) * S * LSZ;
 #pragma unroll
             for (int i = 0; i < VZ; ++i) {
-                const T cvi = el<T, VZ>(cv[k], i);
+                const T cvi = el<T, VZ>(cur.v[k], i);
                 const T coef = a.coef_direct ? cvi : dt2 * cvi * cvi;
                 AT dsum = (AT)0, dpair = (AT)0, dpair_p = (AT)0;
 #pragma unroll
@@ -455,12 +468,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
 
                     if (pe.has) lap += point_force(pe, a, est, lane0[k] + i, s);
 
-                    const T uni = (u0 + u0) - el<T, VZ>(cu[s][k], i) + coef * lap;
+                    const T uni = (u0 + u0) - el<T, VZ>(cur.u[s][k], i) + coef * lap;
                     set_el<T, VZ>(un[s], i, uni);
                     // kernel terms: the interval this launch completes and, with acc_prev,
                     // the one before it (its two ends are already in registers)
                     const AT d = (AT)(uni - u0);
-                    const AT dp = a.acc_prev ? (AT)(u0 - el<T, VZ>(cu[s][k], i)) : (AT)0;
+                    const AT dp = a.acc_prev ? (AT)(u0 - el<T, VZ>(cur.u[s][k], i)) : (AT)0;
                     if (a.acc_cross) {   // exact re-simulation: slots (2p, 2p+1) hold (u, mu)
                         if (s & 1) dsum += dpair * d + dpair_p * dp;
                         else { dpair = d; dpair_p = dp; }
@@ -471,12 +484,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     if (a.sample && pe.has) sample_receivers(pe, a, est, lane0[k] + i, s, uni);
                 }
                 if (rd_acc) {
-                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cpt[k], i) : dsum;
-                    const AT ai = el<AT, VZ>(ca[k], i);
+                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cur.pt[k], i) : dsum;
+                    const AT ai = el<AT, VZ>(cur.a[k], i);
                     set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + tot : ai - tot);
                 }
                 if (wr_part) {
-                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cpt[k], i) : dsum;
+                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cur.pt[k], i) : dsum;
                     set_el<float, VZ>(pn, i, (float)tot);
                 }
             }
@@ -490,25 +503,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
         // rotate to plane x + 1
         if (more) {
 #pragma unroll
-            for (int k = 0; k < RY; ++k) {
+            for (int k = 0; k < RY; ++k)
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
 #pragma unroll
                     for (int d = 0; d < 2 * R; ++d) q[s][k][d] = q[s][k][d + 1];
-                    q[s][k][2 * R] = nq[s][k];
-                    cu[s][k] = nu[s][k];
+                    q[s][k][2 * R] = next.q[s][k];
                 }
-                cv[k] = nv[k];
-                if (rd_acc) ca[k] = na[k];
-                if (rd_part) cpt[k] = npt[k];
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-#pragma unroll
-                for (int i = 0; i < NHY; ++i) chy[s][i] = nhy[s][i];
-#pragma unroll
-                for (int i = 0; i < NHZ; ++i) chz[s][i] = nhz[s][i];
-            }
+            cur = next;
         }
     }
 }

@@ -159,9 +159,10 @@ def test_autotune_picks_a_valid_shape_and_persists(fdw, tmp_path, monkeypatch):
     assert rel(g.cpu().numpy(), g_o) < 1e-4
 
 
-def test_persistent_barrier_timeout_is_reported(fdw):
-    """A barrier wait limit of 1 microsecond (forced from the host) expires while other
-    blocks still work on their tiles: every block leaves the launch and the call
+def test_persistent_wait_timeout_is_reported(fdw):
+    """A wait limit of 1 microsecond (forced from the host) expires: the 10-row last
+    chunk of the 310-row problem finishes its first step long before the 300-row chunk
+    next to it and then waits for it.  Every block leaves the launch and the call
     returns FD_E_DEVICE instead of waiting."""
     f32 = torch.float32
     items = []
@@ -170,7 +171,7 @@ def test_persistent_barrier_timeout_is_reported(fdw):
         c, w = to_dev(q.c, f32), to_dev(q.wavelet, f32)
         obs = torch.zeros((q.nt, len(q.rec)), dtype=f32, device="cuda")
         items.append(fdw.Problem(c, 1.0, 8, q.src, w, q.rec, q.dt, q.nt, obs, 0.1))
-    say("persistent barrier timeout")
+    say("persistent wait timeout")
     with pytest.raises(fdw.FdError) as e:
         fdw.fd_adjoint_sensitivity_batched(items, persistent=True, barrier_timeout_us=1, chunk=300)
     assert e.value.code == fdw.FD_E_DEVICE and "timed out" in str(e.value)
@@ -179,6 +180,24 @@ def test_persistent_barrier_timeout_is_reported(fdw):
     grads = [it.grad.clone() for it in items]
     Js2 = fdw.fd_adjoint_sensitivity_batched(items, persistent=False, chunk=300)
     assert Js == Js2 and all(torch.equal(g, it.grad) for g, it in zip(grads, items))
+
+
+def test_persistent_blocks_take_several_tiles(fdw):
+    """With 4-row chunks a 2048 x 2048 problem has far more tiles than the grid has
+    blocks, so each block marches many tiles per step and tiles wait for neighbours
+    that other blocks reach later in the step; the result equals the per-step launches
+    bitwise."""
+    f32 = torch.float32
+    q = wl.small_random((2048, 2048), order=8, nt=8, dtype="f32", seed=77, nsrc=3, nrec=40)
+    c, w = to_dev(q.c, f32), to_dev(q.wavelet, f32)
+    obs = torch.zeros((q.nt, len(q.rec)), dtype=f32, device="cuda")
+    items = [fdw.Problem(c, 1.0, 8, q.src, w, q.rec, q.dt, q.nt, obs, 0.1)]
+    say("persistent several tiles per block")
+    Js = fdw.fd_adjoint_sensitivity_batched(items, persistent=True, chunk=4)
+    g = items[0].grad.clone()
+    Js2 = fdw.fd_adjoint_sensitivity_batched(items, persistent=False, chunk=4)
+    assert Js == Js2 and torch.equal(g, items[0].grad)
+    assert torch.isfinite(g).all()
 
 
 def test_batched_rejects_mixed_orders(fdw):
@@ -214,12 +233,14 @@ def _check_plan_result(items, J, refs):
         assert abs(Jh[p] - J_o) < 1e-12 * J_o, p
 
 
-@pytest.mark.parametrize("ndim", [2, 3])
-def test_batch_plan_graph_replay(fdw, ndim):
+@pytest.mark.parametrize("ndim,persistent", [(2, False), (3, False), (2, True), (3, True)])
+def test_batch_plan_graph_replay(fdw, ndim, persistent):
     """A batch plan's run captured once in a graph and replayed three times, with every
     problem's speed field changed in place between replays (and eager runs of the same
     plan in between): each replay equals the oracle's Alg. 1 for the speeds it ran with
-    (f64: gradient 1e-9, J 1e-12) and the eager run of the same speeds bitwise."""
+    (f64: gradient 1e-9, J 1e-12) and the eager run of the same speeds bitwise.  The
+    persistent form (one launch per sweep, its item counter and progress words zeroed
+    by kernels) replays the same way."""
     probs = _uneven_problems(ndim, 5, "f64", seed=10 + ndim)
     f64 = torch.float64
     items, obs = [], []
@@ -228,8 +249,8 @@ def test_batch_plan_graph_replay(fdw, ndim):
         obs.append(o)
         items.append(fdw.Problem(to_dev(q.c, f64), 1.0, 8, q.src, to_dev(q.wavelet, f64), q.rec, q.dt, q.nt,
                                  to_dev(o, f64), q.meta["k"]))
-    say("batch plan", ndim, [q.shape for q in probs])
-    plan = fdw.BatchPlan(items)
+    say("batch plan", ndim, "persistent", persistent, [q.shape for q in probs])
+    plan = fdw.BatchPlan(items, persistent=persistent)
     J = torch.zeros(len(items), dtype=f64, device="cuda")
     plan.run(J)
     torch.cuda.synchronize()
@@ -259,7 +280,7 @@ def test_batch_plan_graph_replay(fdw, ndim):
 
 
 def test_batch_plan_persistent_and_timing(fdw):
-    """The persistent form of a plan (one cooperative launch per sweep) gives the per-step
+    """The persistent form of a plan (one launch per sweep) gives the per-step
     form's gradients and J bitwise, run after run with c changed in between; a timed plan
     reports both sweeps."""
     probs = _uneven_problems(2, 4, "f64", seed=21)
