@@ -772,28 +772,51 @@ def step_kernel_sha():
     return h.hexdigest()
 
 
-def measured_traffic(args, shape):
-    """HBM bytes per step launch from the committed rocprofv3 counter record of the
-    default workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated), or None
-    when this run is another workload, runs other launch shapes than the record, or
-    the kernel source changed since."""
+def gradient_launch_kinds(nt, partials):
+    """How many step launches of each kind one gradient (one step per launch) runs:
+    None for the launches without kernel terms, else the partial-sum mode
+    ('start', 'add', 'flush', 'direct')."""
+    kinds = {}
+    for nlaunch in (nt, nt - 1):
+        for l in range(nlaunch):
+            terms = acc_terms(l, nt - 1)
+            k = None if not terms else (part_mode(l, nt - 1) if partials else "direct")
+            kinds[k] = kinds.get(k, 0) + 1
+    return kinds
+
+
+def measured_traffic(args, shape, nt):
+    """HBM bytes per step launch of one gradient from the committed rocprofv3 counter
+    record of the default workload (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated,
+    per launch kind and shape), averaged over this gradient's launches; None when this
+    run is another workload, runs a launch kind or shape the record lacks, or the kernel
+    source changed since."""
     if (args.workload != "layered3d" or args.n not in (0, 1024) or args.acc != "f64"
-            or args.method != "superposition" or not shape):
+            or args.method != "superposition" or not shape or args.pairs > 0):
         return None
     rec = os.path.join(ROOT, "profiles", "step_kernel_layered3d_1024_traffic.md")
     try:
-        fields = dict(ln.split(": ", 1) for ln in open(rec).read().splitlines()
-                      if ln.startswith(("traffic_bytes_per_launch:", "source_sha256:", "launch_shapes")))
+        lines = open(rec).read().splitlines()
         sha = step_kernel_sha()
-    except (OSError, ValueError):
+    except OSError:
         return None
-    if fields.get("source_sha256", "").strip() != sha:
+    recorded_sha = next((ln.split(": ", 1)[1].strip() for ln in lines if ln.startswith("source_sha256: ")), "")
+    if recorded_sha != sha:
         return None
-    ran = [shape.get(k) for k in ("variant", "chunk", "variant_plain", "chunk_plain")]
-    recorded = [int(v) for v in fields.get("launch_shapes (variant chunk variant_plain chunk_plain)", "").split()]
-    if ran != recorded:
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    table = {}
+    for ln in lines:   # traffic_kind: <kind> <variant> <chunk> <bytes per launch>
+        if ln.startswith("traffic_kind: "):
+            kind, variant, chunk, nbytes = ln.split(": ", 1)[1].split()
+            table[(kind, int(variant), int(chunk))] = float(nbytes)
+    total = count = 0.0
+    for kind, n in gradient_launch_kinds(nt, True).items():
+        key = ("plain", shape["variant_plain"], shape["chunk_plain"]) if kind is None else \
+            (kind, shape["variant"], shape["chunk"])
+        if key not in table:
+            return None
+        total += n * table[key]
+        count += n
+    return total / count
 
 
 # The paper's own figure for the same workload and metric, where it has one (Tab.
@@ -941,7 +964,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args, cfg.get("launch_shape")),
+            "traffic": measured_traffic(args, cfg.get("launch_shape"), cfg.get("nt", 0)),
             "kernel": "fdw::pair_kernel" if cfg.get("two_step_launches") else
                       {"problems2d": "fdw::step_multi_kernel", "vd3d": "fdw::vd_step_kernel",
                        "tato2d": "fdw::vd_step_kernel", "fwi3d": "fdw::vd_step_kernel"}.get(
