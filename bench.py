@@ -456,7 +456,7 @@ def run_vd(args, np, torch, fdw, wl):
             f"{len(q['rec'])} receivers each")
     log("workload:", desc, f"dt={q['dt']:.5g}")
     w = torch.as_tensor(q["wavelet"], dtype=torch.float32, device="cuda")
-    variant = args.variant or 1
+    variant = args.variant   # 0: the library's default tile shape
     opts = dict(acc_dtype=args.acc, variant=variant, chunk=args.chunk, no_partials=args.no_partials)
     obs = fdw.fd_vd_forward(q["m_ref"], q["b_ref"], q["dx"], q["src"], w, q["rec"], q["dt"], nt, **opts)
     tr = fdw.fd_vd_forward(q["m"], q["b"], q["dx"], q["src"], w, q["rec"], q["dt"], nt, **opts)
@@ -484,7 +484,7 @@ def run_vd(args, np, torch, fdw, wl):
     bytes_all = ncell * per_cell * args.steps
     cfg = {"workload": desc, "grid": [n, n, n], "nt": nt, "order": 2, "shots": 1, "receivers": len(q["rec"]),
            "accumulator": args.acc, "method": "superposition", "k": k, "J": holder["J"],
-           "launch_shape": {"variant": variant, "chunk": args.chunk}, "cell_updates_per_step": upd}
+           "launch_shape": {"variant": variant or "library default (3D: 5)", "chunk": args.chunk}, "cell_updates_per_step": upd}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, variable material) ...")
         cfg["_cpu_baseline"] = cpu_baseline_vd(q, q["m"], q["b"], wl)

@@ -284,7 +284,7 @@ int fd_adjoint_exact(const fd_grid* grid, const void* c, const fd_acq* acq, doub
  * wavefields and both accumulators; stream-ordered scratch of up to about six grid
  * arrays beyond the unpadded case), which keeps every row load on 256-byte
  * boundaries; callers' arrays stay dense.  Time axis, sources, receivers, shots
- * and misfit as for the constant-density calls.  fd_opts.variant: 0, 1 or 2 (2D also 4 or 5);
+ * and misfit as for the constant-density calls.  fd_opts.variant: 0, 1, 2 or 5 (3D also 7, 2D also 4);
  * max_group is ignored (one wavefield per launch). */
 int fd_vd_forward(const fd_grid* grid, const void* m, const void* b, const fd_acq* acq, double dt,
                   int32_t nt, void* traces, const fd_opts* opts, void* stream);

@@ -32,13 +32,18 @@ namespace fdw {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-template <typename T, typename AT, int NDIM, int TZ, int TY, int VZ, bool ACC>
+// One block's share of one step.  A thread owns RY rows of the tile (rows ly,
+// ly + TY / RY, ...), each with its own queues, so its loads of the next plane cover
+// RY rows and fewer, larger blocks share one barrier per plane.
+template <typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, bool ACC>
 __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __restrict__ lds)
 {
     typedef typename Vec<T, VZ>::type vec;
     typedef typename Vec<AT, VZ>::type avec;
     typedef typename Vec<float, VZ>::type pvec;
-    constexpr int NT = TZ * TY;
+    static_assert(TY % RY == 0, "rows per thread divide the tile rows");
+    constexpr int TYT = TY / RY;                   // thread rows
+    constexpr int NT = TZ * TYT;
     constexpr int WZ = TZ * VZ;
     constexpr int RYH = (NDIM == 3) ? 1 : 0;
     constexpr int PADL = VZ;                       // one halo cell, rows kept VZ-aligned
@@ -60,29 +65,35 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
     const int x1 = min(x0 + a.chunk_len, n0);
     const int tid = threadIdx.x;
     const int lz = tid % TZ;
-    const int ly = tid / TZ;
+    const int lyt = tid / TZ;
     const int z = z0 + lz * VZ;
-    const int y = y0 + ly;
-    const bool live = z < n2 && y < n1;
     const int pitch = a.pitch;                  // row stride (rows may be padded)
     const int64_t ps = (int64_t)n1 * pitch;
-    const int roff = ghost(y, n1) * pitch;
-    const int lofs = (ly + RYH) * LZ + PADL + lz * VZ;
-    const int lane0 = ly * WZ + lz * VZ;
+    int roff[RY], lofs[RY], lane0[RY];
+    bool live[RY];
+#pragma unroll
+    for (int k = 0; k < RY; ++k) {
+        const int ly = lyt + k * TYT;
+        const int y = y0 + ly;
+        live[k] = z < n2 && y < n1;
+        roff[k] = ghost(y, n1) * pitch;
+        lofs[k] = (ly + RYH) * LZ + PADL + lz * VZ;
+        lane0[k] = ly * WZ + lz * VZ;
+    }
 
-    const T* __restrict__ ucur = (const T*)a.ucur;
-    T* __restrict__ unew = (T*)a.unew;
-    const T* __restrict__ mass = (const T*)a.c;
-    const T* __restrict__ stiff = (const T*)a.stiff;
-    AT* __restrict__ acc = (AT*)a.acc;
-    AT* __restrict__ accb = (AT*)a.acc_b;
+    const GLOBAL_AS T* __restrict__ ucur = (const GLOBAL_AS T*)a.ucur;
+    GLOBAL_AS T* __restrict__ unew = (GLOBAL_AS T*)a.unew;
+    const GLOBAL_AS T* __restrict__ mass = (const GLOBAL_AS T*)a.c;
+    const GLOBAL_AS T* __restrict__ stiff = (const GLOBAL_AS T*)a.stiff;
+    GLOBAL_AS AT* __restrict__ acc = (GLOBAL_AS AT*)a.acc;
+    GLOBAL_AS AT* __restrict__ accb = (GLOBAL_AS AT*)a.acc_b;
     const bool use_acc = ACC && a.acc_sign != 0;
     const bool use_accb = ACC && a.acc_face != 0;
     // f32 partial sums of both kernel terms (f32 fields with f64 accumulators): what each
     // accumulating launch reads and writes (modes as in the constant-density step)
     constexpr bool PARTS = ACC && sizeof(T) == 4 && sizeof(AT) == 8;
-    float* __restrict__ part = (float*)a.part;
-    float* __restrict__ partb = (float*)a.part_b;
+    GLOBAL_AS float* __restrict__ part = (GLOBAL_AS float*)a.part;
+    GLOBAL_AS float* __restrict__ partb = (GLOBAL_AS float*)a.part_b;
     const int pm = (PARTS && use_acc) ? a.part_mode : PM_DIRECT;
     const int pmb = (PARTS && use_accb) ? a.part_b_mode : PM_DIRECT;
     const bool rd_acc = use_acc && (pm == PM_DIRECT || pm == PM_FLUSH);
@@ -116,27 +127,32 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
         hzg[i] = ghost(y0 + (h < HZ ? row : 0), n1) * pitch + ghost(z0 + sz - PADL, n2);
     }
 
-    // register queues along axis 0: planes x-1, x, x+1 of u^n and of b
-    vec qu[3], qb[3];
+    // register queues along axis 0: planes x-1, x, x+1 of u^n and of b, per own row
+    vec qu[RY][3], qb[RY][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int64_t xo = (int64_t)ghost(x0 - 1 + d, n0) * ps + roff;
-        qu[d] = load_row<T, VZ, false, true>(ucur + xo, z, n2);
-        qb[d] = load_row<T, VZ, false, true>(stiff + xo, z, n2);
-    }
+    for (int k = 0; k < RY; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int64_t xo = (int64_t)ghost(x0 - 1 + d, n0) * ps + roff[k];
+            qu[k][d] = load_row<T, VZ, false, true>(ucur + xo, z, n2);
+            qb[k][d] = load_row<T, VZ, false, true>(stiff + xo, z, n2);
+        }
     // plane-x operands, loaded one plane ahead
-    vec cu, cm, chyu[NHY1], chyb[NHY1];
-    avec ca, cab;
-    pvec cp, cpb;
+    vec cu[RY], cm[RY], chyu[NHY1], chyb[NHY1];
+    avec ca[RY], cab[RY];
+    pvec cp[RY], cpb[RY];
     T chzu[NHZ], chzb[NHZ];
     {
         const int64_t xo = (int64_t)x0 * ps;
-        cu = load_row<T, VZ, true, false>(unew + xo + roff, z, n2);
-        cm = load_row<T, VZ, true, false>(mass + xo + roff, z, n2);
-        if (rd_acc) ca = load_row<AT, VZ, true, false>(acc + xo + roff, z, n2);
-        if (rd_accb) cab = load_row<AT, VZ, true, false>(accb + xo + roff, z, n2);
-        if (rd_part) cp = load_row<float, VZ, true, false>(part + xo + roff, z, n2);
-        if (rd_partb) cpb = load_row<float, VZ, true, false>(partb + xo + roff, z, n2);
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            cu[k] = load_row<T, VZ, true, false>(unew + xo + roff[k], z, n2);
+            cm[k] = load_row<T, VZ, true, false>(mass + xo + roff[k], z, n2);
+            if (rd_acc) ca[k] = load_row<AT, VZ, true, false>(acc + xo + roff[k], z, n2);
+            if (rd_accb) cab[k] = load_row<AT, VZ, true, false>(accb + xo + roff[k], z, n2);
+            if (rd_part) cp[k] = load_row<float, VZ, true, false>(part + xo + roff[k], z, n2);
+            if (rd_partb) cpb[k] = load_row<float, VZ, true, false>(partb + xo + roff[k], z, n2);
+        }
 #pragma unroll
         for (int i = 0; i < NHY; ++i)
             if (hyl[i] >= 0) {
@@ -157,22 +173,25 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
     for (int x = x0; x < x1; ++x) {
         const int64_t xo = (int64_t)x * ps;
         // issue the loads of plane x + 1
-        vec nqu, nqb, ncu, ncm, nhyu[NHY1], nhyb[NHY1];
-        avec nca, ncab;
-        pvec ncp, ncpb;
+        vec nqu[RY], nqb[RY], ncu[RY], ncm[RY], nhyu[NHY1], nhyb[NHY1];
+        avec nca[RY], ncab[RY];
+        pvec ncp[RY], ncpb[RY];
         T nhzu[NHZ], nhzb[NHZ];
         const bool more = x + 1 < x1;
         if (more) {
             const int64_t xn = xo + ps;
-            const int64_t xq = (int64_t)ghost(x + 2, n0) * ps + roff;
-            nqu = load_row<T, VZ, false, true>(ucur + xq, z, n2);
-            nqb = load_row<T, VZ, false, true>(stiff + xq, z, n2);
-            ncu = load_row<T, VZ, true, false>(unew + xn + roff, z, n2);
-            ncm = load_row<T, VZ, true, false>(mass + xn + roff, z, n2);
-            if (rd_acc) nca = load_row<AT, VZ, true, false>(acc + xn + roff, z, n2);
-            if (rd_accb) ncab = load_row<AT, VZ, true, false>(accb + xn + roff, z, n2);
-            if (rd_part) ncp = load_row<float, VZ, true, false>(part + xn + roff, z, n2);
-            if (rd_partb) ncpb = load_row<float, VZ, true, false>(partb + xn + roff, z, n2);
+            const int64_t xq = (int64_t)ghost(x + 2, n0) * ps;
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                nqu[k] = load_row<T, VZ, false, true>(ucur + xq + roff[k], z, n2);
+                nqb[k] = load_row<T, VZ, false, true>(stiff + xq + roff[k], z, n2);
+                ncu[k] = load_row<T, VZ, true, false>(unew + xn + roff[k], z, n2);
+                ncm[k] = load_row<T, VZ, true, false>(mass + xn + roff[k], z, n2);
+                if (rd_acc) nca[k] = load_row<AT, VZ, true, false>(acc + xn + roff[k], z, n2);
+                if (rd_accb) ncab[k] = load_row<AT, VZ, true, false>(accb + xn + roff[k], z, n2);
+                if (rd_part) ncp[k] = load_row<float, VZ, true, false>(part + xn + roff[k], z, n2);
+                if (rd_partb) ncpb[k] = load_row<float, VZ, true, false>(partb + xn + roff[k], z, n2);
+            }
 #pragma unroll
             for (int i = 0; i < NHY; ++i)
                 if (hyl[i] >= 0) {
@@ -189,8 +208,11 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
         // stage plane x of u and of b
         T* Lu = lds + (x & 1) * 2 * LSZ;
         T* Lb = Lu + LSZ;
-        *(vec*)(Lu + lofs) = qu[1];
-        *(vec*)(Lb + lofs) = qb[1];
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            *(vec*)(Lu + lofs[k]) = qu[k][1];
+            *(vec*)(Lb + lofs[k]) = qb[k][1];
+        }
 #pragma unroll
         for (int i = 0; i < NHY; ++i)
             if (hyl[i] >= 0) {
@@ -206,14 +228,17 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
         events_at_plane<T, NT>(pe, a, est, x, tid);
         __syncthreads();
 
-        if (live) {
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            if (!live[k]) continue;
+            const int lo = lofs[k];
             vec un;
             avec an, abn;
             pvec pn, pbn;
 #pragma unroll
             for (int i = 0; i < VZ; ++i) {
-                const T u0 = el<T, VZ>(qu[1], i);
-                const T b0 = el<T, VZ>(qb[1], i);
+                const T u0 = el<T, VZ>(qu[k][1], i);
+                const T b0 = el<T, VZ>(qb[k][1], i);
                 T lap = (T)0;
                 T fb = (T)0;   // this level's stiffness terms, added to the accumulator in AT
                 auto face = [&](T uj, T bj) {
@@ -223,58 +248,62 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
                     lap += (b0 * (t + t)) * d;
                     if (use_accb) fb += ((t + t) * t) * (d * d);
                 };
-                face(el<T, VZ>(qu[0], i), el<T, VZ>(qb[0], i));
-                face(el<T, VZ>(qu[2], i), el<T, VZ>(qb[2], i));
+                face(el<T, VZ>(qu[k][0], i), el<T, VZ>(qb[k][0], i));
+                face(el<T, VZ>(qu[k][2], i), el<T, VZ>(qb[k][2], i));
                 if (NDIM == 3) {
-                    face(Lu[lofs + i - LZ], Lb[lofs + i - LZ]);
-                    face(Lu[lofs + i + LZ], Lb[lofs + i + LZ]);
+                    face(Lu[lo + i - LZ], Lb[lo + i - LZ]);
+                    face(Lu[lo + i + LZ], Lb[lo + i + LZ]);
                 }
-                face(Lu[lofs + i - 1], Lb[lofs + i - 1]);
-                face(Lu[lofs + i + 1], Lb[lofs + i + 1]);
+                face(Lu[lo + i - 1], Lb[lo + i - 1]);
+                face(Lu[lo + i + 1], Lb[lo + i + 1]);
                 lap *= inv_dx2;
-                if (pe.has) lap += point_force(pe, a, est, lane0 + i, 0);
-                const T cui = el<T, VZ>(cu, i);
-                const T coef = dt2 * recip(el<T, VZ>(cm, i));
+                if (pe.has) lap += point_force(pe, a, est, lane0[k] + i, 0);
+                const T cui = el<T, VZ>(cu[k], i);
+                const T coef = dt2 * recip(el<T, VZ>(cm[k], i));
                 const T uni = (u0 + u0) - cui + coef * lap;
                 set_el<T, VZ>(un, i, uni);
-                if (a.sample && pe.has) sample_receivers(pe, a, est, lane0 + i, 0, uni);
+                if (a.sample && pe.has) sample_receivers(pe, a, est, lane0[k] + i, 0, uni);
                 if (use_acc) {
                     const AT d = (AT)(uni - u0);
                     const AT dp = a.acc_prev ? (AT)(u0 - cui) : (AT)0;
                     const AT dsum = d * d + dp * dp;
-                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cp, i) : dsum;
+                    const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cp[k], i) : dsum;
                     if (rd_acc) {
-                        const AT ai = el<AT, VZ>(ca, i);
+                        const AT ai = el<AT, VZ>(ca[k], i);
                         set_el<AT, VZ>(an, i, a.acc_sign > 0 ? ai + tot : ai - tot);
                     }
                     if (wr_part) set_el<float, VZ>(pn, i, (float)tot);
                 }
                 if (use_accb) {
-                    const AT totb = rd_partb ? (AT)fb + (AT)el<float, VZ>(cpb, i) : (AT)fb;
+                    const AT totb = rd_partb ? (AT)fb + (AT)el<float, VZ>(cpb[k], i) : (AT)fb;
                     if (rd_accb) {
-                        const AT bi = el<AT, VZ>(cab, i);
+                        const AT bi = el<AT, VZ>(cab[k], i);
                         set_el<AT, VZ>(abn, i, a.acc_face > 0 ? bi + totb : bi - totb);
                     }
                     if (wr_partb) set_el<float, VZ>(pbn, i, (float)totb);
                 }
             }
-            __builtin_nontemporal_store(un, (vec*)(unew + xo + roff + z));
-            if (rd_acc) __builtin_nontemporal_store(an, (avec*)(acc + xo + roff + z));
-            if (rd_accb) __builtin_nontemporal_store(abn, (avec*)(accb + xo + roff + z));
-            if (wr_part) __builtin_nontemporal_store(pn, (pvec*)(part + xo + roff + z));
-            if (wr_partb) __builtin_nontemporal_store(pbn, (pvec*)(partb + xo + roff + z));
+            const int64_t o = xo + roff[k] + z;
+            __builtin_nontemporal_store(un, (vec*)(unew + o));
+            if (rd_acc) __builtin_nontemporal_store(an, (avec*)(acc + o));
+            if (rd_accb) __builtin_nontemporal_store(abn, (avec*)(accb + o));
+            if (wr_part) __builtin_nontemporal_store(pn, (pvec*)(part + o));
+            if (wr_partb) __builtin_nontemporal_store(pbn, (pvec*)(partb + o));
         }
 
         // rotate to plane x + 1
         if (more) {
-            qu[0] = qu[1]; qu[1] = qu[2]; qu[2] = nqu;
-            qb[0] = qb[1]; qb[1] = qb[2]; qb[2] = nqb;
-            cu = ncu;
-            cm = ncm;
-            if (rd_acc) ca = nca;
-            if (rd_accb) cab = ncab;
-            if (rd_part) cp = ncp;
-            if (rd_partb) cpb = ncpb;
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                qu[k][0] = qu[k][1]; qu[k][1] = qu[k][2]; qu[k][2] = nqu[k];
+                qb[k][0] = qb[k][1]; qb[k][1] = qb[k][2]; qb[k][2] = nqb[k];
+                cu[k] = ncu[k];
+                cm[k] = ncm[k];
+                if (rd_acc) ca[k] = nca[k];
+                if (rd_accb) cab[k] = ncab[k];
+                if (rd_part) cp[k] = ncp[k];
+                if (rd_partb) cpb[k] = ncpb[k];
+            }
 #pragma unroll
             for (int i = 0; i < NHY; ++i) { chyu[i] = nhyu[i]; chyb[i] = nhyb[i]; }
 #pragma unroll
@@ -283,45 +312,48 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
     }
 }
 
-template <typename T, typename AT, int NDIM, int TZ, int TY, int VZ, bool ACC>
-__global__ __launch_bounds__(TZ * TY) void vd_step_kernel(StepArgs a)
+template <typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ, bool ACC>
+__global__ __launch_bounds__(TZ * (TY / RY)) void vd_step_kernel(StepArgs a)
 {
     constexpr int LZ = 2 * VZ + TZ * VZ;
     constexpr int LSZ = (TY + ((NDIM == 3) ? 2 : 0)) * LZ;
     __shared__ __attribute__((aligned(16))) T lds[2 * 2 * LSZ];
     const int b = logical_block(a.nblk);
     if (b >= a.nblk) return;
-    vd_body<T, AT, NDIM, TZ, TY, VZ, ACC>(a, b, lds);
+    vd_body<T, AT, NDIM, TZ, TY, RY, VZ, ACC>(a, b, lds);
 }
 
-template <typename T, typename AT, int NDIM, int TZ, int TY, int VZ>
+template <typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
 static hipError_t launch_vd_one(int nblk, const StepArgs& a, hipStream_t s)
 {
     const int grid = ((nblk + 7) / 8) * 8;
     if (a.acc_sign != 0 || a.acc_face != 0)
-        hipLaunchKernelGGL((vd_step_kernel<T, AT, NDIM, TZ, TY, VZ, true>), dim3(grid), dim3(TZ * TY), 0,
-                           s, a);
+        hipLaunchKernelGGL((vd_step_kernel<T, AT, NDIM, TZ, TY, RY, VZ, true>), dim3(grid),
+                           dim3(TZ * (TY / RY)), 0, s, a);
     else
-        hipLaunchKernelGGL((vd_step_kernel<T, AT, NDIM, TZ, TY, VZ, false>), dim3(grid), dim3(TZ * TY),
-                           0, s, a);
+        hipLaunchKernelGGL((vd_step_kernel<T, AT, NDIM, TZ, TY, RY, VZ, false>), dim3(grid),
+                           dim3(TZ * (TY / RY)), 0, s, a);
     return hipGetLastError();
 }
 
-// The tile shapes of the step variants (3D: 1 and 2, one or two cells per lane; 2D
-// also 4 and 5, rows of 128 x 2 and 256 cells, which keep more waves resident per
+// The tile shapes of the step variants (3D: 1 and 2, one or two cells per lane, 5, a
+// 64 x 4 tile with two cells per lane, and 7, a 64 x 8 tile with two rows per thread;
+// 2D also 4 and 5, rows of 128 x 2 and 256 cells, which keep more waves resident per
 // block than one 64-lane wavefront), so the block decomposition and event lists of a
 // plan serve both kernels.
 template <typename T, typename AT>
 static hipError_t launch_vd_rt(int ndim, int variant, int nblk, const StepArgs& a, hipStream_t s)
 {
     if (ndim == 3) {
-        if (variant == 1) return launch_vd_one<T, AT, 3, 64, 8, 1>(nblk, a, s);
-        if (variant == 2) return launch_vd_one<T, AT, 3, 64, 8, 2>(nblk, a, s);
+        if (variant == 1) return launch_vd_one<T, AT, 3, 64, 8, 1, 1>(nblk, a, s);
+        if (variant == 2) return launch_vd_one<T, AT, 3, 64, 8, 1, 2>(nblk, a, s);
+        if (variant == 5) return launch_vd_one<T, AT, 3, 64, 4, 1, 2>(nblk, a, s);
+        if (variant == 7) return launch_vd_one<T, AT, 3, 64, 8, 2, 1>(nblk, a, s);
     } else {
-        if (variant == 1) return launch_vd_one<T, AT, 2, 64, 1, 1>(nblk, a, s);
-        if (variant == 2) return launch_vd_one<T, AT, 2, 64, 1, 2>(nblk, a, s);
-        if (variant == 4) return launch_vd_one<T, AT, 2, 128, 1, 2>(nblk, a, s);
-        if (variant == 5) return launch_vd_one<T, AT, 2, 256, 1, 1>(nblk, a, s);
+        if (variant == 1) return launch_vd_one<T, AT, 2, 64, 1, 1, 1>(nblk, a, s);
+        if (variant == 2) return launch_vd_one<T, AT, 2, 64, 1, 1, 2>(nblk, a, s);
+        if (variant == 4) return launch_vd_one<T, AT, 2, 128, 1, 1, 2>(nblk, a, s);
+        if (variant == 5) return launch_vd_one<T, AT, 2, 256, 1, 1, 1>(nblk, a, s);
     }
     return hipErrorInvalidValue;
 }

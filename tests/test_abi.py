@@ -127,8 +127,8 @@ def test_exact_validation(fdw):
 
 
 def test_vd_rejects_other_orders_and_variants(fdw):
-    """The variable-material scheme is second order and runs tile variants 1 and 2 (2D
-    also 4 and 5); both are checked before any device work."""
+    """The variable-material scheme is second order and runs tile variants 1, 2 and 5 (3D
+    also 7, 2D also 4); both are checked before any device work."""
     a = fdw.fd_acq()
     J = ctypes.c_double()
     f = fdw.lib().fd_vd_adjoint_sensitivity
@@ -140,7 +140,11 @@ def test_vd_rejects_other_orders_and_variants(fdw):
     o = fdw.make_opts(variant=3)
     assert f(ctypes.byref(g2), None, None, ctypes.byref(a), 0.1, 10, None, 0.1, None, None,
              ctypes.byref(J), None, ctypes.byref(o), None) == fdw.FD_E_ARG
-    assert "variants 1 and 2" in fdw.lib().fd_last_error().decode()
+    assert "variants 1, 2 and 5" in fdw.lib().fd_last_error().decode()
+    g3 = fdw.make_grid((16, 16, 16), 1.0, 2, fdw.FD_F64)
+    o = fdw.make_opts(variant=4)
+    assert f(ctypes.byref(g3), None, None, ctypes.byref(a), 0.1, 10, None, 0.1, None, None,
+             ctypes.byref(J), None, ctypes.byref(o), None) == fdw.FD_E_ARG
     assert fdw.lib().fd_vd_forward(ctypes.byref(g2), None, None, None, 0.1, 10, None, None,
                                    None) == fdw.FD_E_ARG
 

@@ -67,8 +67,9 @@ def test_vd_matches_oracle_f64(fdw, shape, nt, seed, dx):
     dt *= dx
     k = 0.03
     om, ob, oJ, otr = oracle.vd_superposition_gradient(m, b, dx, dt, nt, src, w, rec, obs, k)
-    for variant in ((0, 1, 2) if len(shape) == 3 else (0, 1, 2, 4, 5)):
-        if shape[-1] % (2 if variant in (2, 4) else 1):
+    # 3D 5: 64 x 4 tiles, two cells per lane; 3D 7: 64 x 8 tiles, two rows per thread
+    for variant in ((0, 1, 2, 5, 7) if len(shape) == 3 else (0, 1, 2, 4, 5)):
+        if shape[-1] % (2 if variant in (2, 4) or (variant == 5 and len(shape) == 3) else 1):
             continue
         say("vd f64", shape, nt, "variant", variant)
         gm, gb, J, tr = _run(fdw, m, b, dt, nt, src, w, rec, obs, k, torch.float64, dx=dx, variant=variant)
@@ -91,14 +92,15 @@ def test_vd_gap_matches_closed_forms(fdw):
     assert rel(gb - eb, 0.5 * k * dt * dt * s2b) < 1e-6
 
 
-@pytest.mark.parametrize("acc,shape", [("f64", (40, 24, 128)), ("f32", (40, 24, 128)), ("f64", (40, 24, 100))])
-def test_vd_f32(fdw, acc, shape):
+@pytest.mark.parametrize("acc,shape,variant", [("f64", (40, 24, 128), 0), ("f32", (40, 24, 128), 0),
+                                               ("f64", (40, 24, 100), 0), ("f64", (40, 24, 128), 7)])
+def test_vd_f32(fdw, acc, shape, variant):
     nt = 300
     m, b, dt, src, rec, w, obs = _medium(shape, 9, nt, nrec=16, layered=True)
     k = 0.05
     om, ob, oJ, otr = oracle.vd_superposition_gradient(m, b, 1.0, dt, nt, src, w, rec, obs, k)
-    say("vd f32, acc", acc, shape)
-    gm, gb, J, tr = _run(fdw, m, b, dt, nt, src, w, rec, obs, k, torch.float32, acc_dtype=acc)
+    say("vd f32, acc", acc, shape, "variant", variant)
+    gm, gb, J, tr = _run(fdw, m, b, dt, nt, src, w, rec, obs, k, torch.float32, acc_dtype=acc, variant=variant)
     assert rel(tr, otr) < 1e-4
     assert abs(J - oJ) < 1e-4 * oJ
     tol = 1e-4 if acc == "f64" else 1e-3
