@@ -215,13 +215,19 @@ int autotune(const fd_grid* grid, int nshot, const fd_opts* opts, int steps, fd_
     for (int variant = 1; variant <= fdw::variant_count(G.ndim); ++variant) {
         const fdw::Variant v = fdw::variant_shape(G.ndim, variant);
         if (G.n2 % v.vz != 0) continue;
+        // 2D rows of four cells per lane time well in isolation but ran real 2048^2
+        // sweeps at 120 against 208 Gcell-updates/s for two cells per lane: not a 2D
+        // candidate
+        if (G.ndim == 2 && v.vz == 4) continue;
         std::vector<int> chunks = {0, G.n0, G.n0 / 2, G.n0 / 4, G.n0 / 8, 256, 128, 64};
+        // 2D marches serialise their rows: short chunks keep the most blocks in flight
+        if (G.ndim == 2) chunks.insert(chunks.end(), {2, 4, 8});
         std::sort(chunks.begin(), chunks.end());
         chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
         for (int group : groups) {
             if (group > v.max_shots) continue;
             for (int chunk : chunks) {
-                if (chunk != 0 && (chunk < 2 * G.r || chunk > G.n0)) continue;
+                if (chunk != 0 && (chunk < (G.ndim == 2 ? 2 : 2 * G.r) || chunk > G.n0)) continue;
                 Geo T = G;
                 T.variant = variant;
                 T.auto_variant = false;
