@@ -360,8 +360,9 @@ def run_single(args, np, torch, fdw, wl):
 
     def exact_step(record):
         t = fdw.fd_timing()
+        shape = {"variant": args.variant, "chunk": args.chunk} if args.variant else {}
         _, J = fdw.fd_adjoint_exact(c, p.dx, p.order, acq, None, None, p.dt, p.nt, obs, grad=grad,
-                                    timing=t, acc_dtype=args.acc)
+                                    timing=t, acc_dtype=args.acc, **shape)
         holder.setdefault("k", None)
         holder.setdefault("J", J)
         if record:
