@@ -719,7 +719,7 @@ def run_problems(args, np, torch, fdw, wl):
         ncell_all += n * n
     desc = f"problems2d: 16 layered problems, sides {sides[0]}..{sides[-1]}, f32 order-8 nt={nt}"
     log("workload:", desc)
-    timings = []
+    timings, holder = [], {}
     # one batch plan (host work once), run per step on the current stream; with --graph
     # the run is captured once and each step replays the graph
     plan = fdw.BatchPlan(items, persistent=args.persistent, timing=fdw.fd_timing(), variant=args.variant or 1,
@@ -741,6 +741,7 @@ def run_problems(args, np, torch, fdw, wl):
         if record:
             t = plan.timing()
             timings.append((t.fwd_ms, t.fwd_launches, t.bwd_ms, t.bwd_launches))
+            holder["persistent_blocks"] = t.persistent_blocks
 
     elapsed = timed(args, torch, one_step)
     if not bool(torch.isfinite(J).all()):
@@ -753,7 +754,8 @@ def run_problems(args, np, torch, fdw, wl):
     cfg = {"workload": desc, "sides": sides, "nt": nt, "order": 8, "problems": 16, "variant": args.variant or 1,
            "chunk": args.chunk or "library",
            "accumulator": args.acc, "graph": bool(args.graph), "persistent": bool(args.persistent),
-           "cell_updates_per_step": upd, "plan": "one fd_batch_plan; steps run it"
+           "cell_updates_per_step": upd, "persistent_blocks": holder.get("persistent_blocks"),
+           "plan": "one fd_batch_plan; steps run it"
            + (" as a captured graph replay" if args.graph else " directly")}
     plan.close()
     return (upd, elapsed, cfg, (bytes_all / launches, kern_ms / launches, per_cell / (2 * nt - 1)),

@@ -105,6 +105,8 @@ typedef struct fd_timing {
     int32_t bwd_launches;
     int32_t fwd_pair_launches;  /* of the launches: those that advanced two steps (fd_opts.pairs) */
     int32_t bwd_pair_launches;
+    int32_t persistent_blocks;  /* batch plans with persistent launches: blocks that took part in
+                                   the last sweep (fd_batch_timing; 0 otherwise) */
 } fd_timing;
 
 typedef struct fd_opts {

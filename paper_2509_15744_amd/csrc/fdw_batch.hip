@@ -32,15 +32,17 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_multi_kernel(const StepArgs
     step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, 1>(a, g - block_start[lo], lds);
 }
 
-// Progress of a persistent sweep, tile by tile.  done[g] counts the steps tile g has
-// finished in this launch; a tile starts step st once each tile its stencil reaches
-// has finished step st - 1: those tiles wrote the level it reads, and read the level
-// it overwrites.  The neighbours are the tiles one over along each axis: the in-plane
-// halo reaches one tile left/right (and, in 3D, above/below), the axis-0 queue one
-// chunk back and ahead (tiles are at least r wide and chunks at least r long, so a
-// mirrored cell past a wall lies in the tile itself or in such a neighbour).
+// Progress of a persistent sweep, group by group.  A group is a column of K
+// consecutive chunks of one tile column (the chunks the per-step launches use, each
+// marched with its own queue fill), and done[g] counts the steps group g has finished
+// in this launch.  A group starts step st once each group its stencil reaches has
+// finished step st - 1: those groups wrote the level it reads, and read the level it
+// overwrites.  The neighbours are the groups one over along each axis: the in-plane
+// halo reaches one tile column left/right (and, in 3D, above/below), the axis-0 queues
+// the groups before and after (a group spans at least r planes, so a mirrored cell
+// past a wall lies in the group itself or in such a neighbour).
 //
-// Waits are bounded: a tile that waits longer than `timeout` wall-clock ticks sets
+// Waits are bounded: a group that waits longer than `timeout` wall-clock ticks sets
 // err, and every wait gives up once err is set, so the launch ends whatever happens.
 struct Progress {
     unsigned* done;
@@ -62,24 +64,23 @@ __device__ __forceinline__ void publish_step(const Progress& pr, int g, int st)
     }
 }
 
-// Waits until the neighbours of tile b (of the problem whose tiles start at done0)
-// have finished step st - 1.  Block-uniform result: false when the launch must end.
-__device__ __forceinline__ bool wait_neighbours(const Progress& pr, const StepArgs& a, const unsigned* done0,
-                                                int b, int st, int ndim)
+// Waits until the neighbours of group gl (of the problem whose groups start at done0;
+// coordinates tzb < ntz, tyb < nty, gi < ngr) have finished step st - 1.  Block-uniform
+// result: false when the launch must end.
+__device__ __forceinline__ bool wait_neighbours(const Progress& pr, const unsigned* done0, int gl, int tzb,
+                                                int ntz, int tyb, int nty, int gi, int ngr, int st, int ndim)
 {
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = 0;
     __syncthreads();
-    const int tzb = b % a.ntz, rest = b / a.ntz, tyb = rest % a.nty, chb = rest / a.nty;
-    const int nch = a.nblk / (a.ntz * a.nty);
     // lane i < 6 watches neighbour i: -z, +z, -x, +x, -y, +y
     int nb = -1;
     if (tid < 2 * ndim) {
         const int ax = tid >> 1, dir = (tid & 1) ? 1 : -1;
-        if (ax == 0 && tzb + dir >= 0 && tzb + dir < a.ntz) nb = b + dir;
-        if (ax == 1 && chb + dir >= 0 && chb + dir < nch) nb = b + dir * a.ntz * a.nty;
-        if (ax == 2 && tyb + dir >= 0 && tyb + dir < a.nty) nb = b + dir * a.ntz;
+        if (ax == 0 && tzb + dir >= 0 && tzb + dir < ntz) nb = gl + dir;
+        if (ax == 1 && gi + dir >= 0 && gi + dir < ngr) nb = gl + dir * ntz * nty;
+        if (ax == 2 && tyb + dir >= 0 && tyb + dir < nty) nb = gl + dir * ntz;
     }
     if (nb >= 0) {
         const long long t0 = wall_clock64();
@@ -143,18 +144,20 @@ __device__ __forceinline__ int join_persistent(unsigned* bar, long long window, 
 }
 
 // A whole sweep of several problems in one launch.  The P taking part blocks
-// (join_persistent) walk the steps; within a step each block takes the tiles slot,
+// (join_persistent) walk the steps; within a step each block takes the groups slot,
 // slot + P, ... (with all G blocks taking part, slot is remapped so that consecutive
-// tiles share an XCD; otherwise it is the arrival order).  There is no grid-wide
-// barrier: a tile waits for its neighbours' previous step only (Progress), so blocks
-// drift apart by up to a step and none idles at the end of a step.  Every block
-// handles its tiles in (step, tile) order, each tile always in the same block, and a
-// step's work depends on the previous step's only, so the waits cannot form a cycle
-// among running blocks; the bounded waits end the launch whatever happens.
+// groups share an XCD; otherwise it is the arrival order) and marches each chunk of a
+// group in turn, so every chunk starts with its own queue fill, whose loads are in
+// flight together, as in the per-step launches.  There is no grid-wide barrier: a
+// group waits for its neighbours' previous step only (Progress), so blocks drift apart
+// by up to a step and none idles at the end of a step.  Every block handles its groups
+// in (step, group) order, each group always in the same block, and a step's work
+// depends on the previous step's only, so the waits cannot form a cycle among running
+// blocks; the bounded waits end the launch whatever happens.
 template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
 __global__ __launch_bounds__(TZ*(TY / RY)) void step_persistent_kernel(
-    const StepArgs* __restrict__ table, const int32_t* __restrict__ block_start, int nprob,
-    int total, int nsteps, unsigned* bar, long long timeout, long long window)
+    const StepArgs* __restrict__ table, const int32_t* __restrict__ group_start, int nprob,
+    int total, int nsteps, int K, unsigned* bar, long long timeout, long long window)
 {
     typedef Shape<R, T, NDIM, TZ, TY, RY, VZ, 1> SH;
     __shared__ __attribute__((aligned(16))) T lds[SH::LDS];
@@ -173,16 +176,26 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_persistent_kernel(
             int lo = 0, hi = nprob;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (block_start[mid] <= g) lo = mid;
+                if (group_start[mid] <= g) lo = mid;
                 else hi = mid;
             }
             const StepArgs a = t[lo];
-            const int b = g - block_start[lo];
+            const int gl = g - group_start[lo];
             if (a.active) {
-                if (st > 0 && !wait_neighbours(pr, a, pr.done + block_start[lo], b, st, NDIM)) return;
-                step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, 1>(a, b, lds);
+                const int ntz = a.ntz, nty = a.nty;
+                const int nch = a.nblk / (ntz * nty);
+                const int ngr = (nch + K - 1) / K;
+                const int tzb = gl % ntz, rest = gl / ntz, tyb = rest % nty, gi = rest / nty;
+                if (st > 0 && !wait_neighbours(pr, pr.done + group_start[lo], gl, tzb, ntz, tyb, nty, gi, ngr,
+                                               st, NDIM))
+                    return;
+                const int c1 = min(gi * K + K, nch);
+                for (int c = gi * K; c < c1; ++c) {
+                    __syncthreads();   // the previous chunk's last LDS reads are done
+                    step_body<R, T, AT, NDIM, TZ, TY, RY, VZ, 1>(a, (c * nty + tyb) * ntz + tzb, lds);
+                }
             }
-            publish_step(pr, g, st);   // also orders this tile's LDS reads before the next tile's writes
+            publish_step(pr, g, st);   // also orders this group's LDS reads before the next group's writes
         }
     }
 }
@@ -229,7 +242,7 @@ static hipError_t launch_multi_rt(int ndim, int variant, const StepArgs* t, cons
 constexpr long long kJoinWindowTicks = 20000;   // 200 us of the 100 MHz wall clock
 template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
 static hipError_t launch_persistent_one(const StepArgs* t, const int32_t* bs, int nprob, int total,
-                                        int nsteps, unsigned* bar, long long timeout, hipStream_t s,
+                                        int nsteps, int K, unsigned* bar, long long timeout, hipStream_t s,
                                         int* grid_used)
 {
     auto kern = step_persistent_kernel<R, T, AT, NDIM, TZ, TY, RY, VZ>;
@@ -247,26 +260,27 @@ static hipError_t launch_persistent_one(const StepArgs* t, const int32_t* bs, in
     const int grid = std::min(capacity, ((total + 7) / 8) * 8);
     *grid_used = grid;
     const long long window = kJoinWindowTicks;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, s, t, bs, nprob, total, nsteps, bar, timeout, window);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, s, t, bs, nprob, total, nsteps, K, bar, timeout,
+                       window);
     return hipGetLastError();
 }
 
 template <int R, typename T, typename AT>
 static hipError_t launch_persistent_rt(int ndim, int variant, const StepArgs* t, const int32_t* bs,
-                                       int nprob, int total, int nsteps, unsigned* bar, long long to,
+                                       int nprob, int total, int nsteps, int K, unsigned* bar, long long to,
                                        hipStream_t s, int* g)
 {
     if (ndim == 3) {
         switch (variant) {
-        case 1: return launch_persistent_one<R, T, AT, 3, 64, 8, 1, 1>(t, bs, nprob, total, nsteps, bar, to, s, g);
-        case 2: return launch_persistent_one<R, T, AT, 3, 64, 8, 1, 2>(t, bs, nprob, total, nsteps, bar, to, s, g);
+        case 1: return launch_persistent_one<R, T, AT, 3, 64, 8, 1, 1>(t, bs, nprob, total, nsteps, K, bar, to, s, g);
+        case 2: return launch_persistent_one<R, T, AT, 3, 64, 8, 1, 2>(t, bs, nprob, total, nsteps, K, bar, to, s, g);
         }
     } else {
         switch (variant) {
-        case 1: return launch_persistent_one<R, T, AT, 2, 64, 1, 1, 1>(t, bs, nprob, total, nsteps, bar, to, s, g);
-        case 2: return launch_persistent_one<R, T, AT, 2, 64, 1, 1, 2>(t, bs, nprob, total, nsteps, bar, to, s, g);
-        case 4: return launch_persistent_one<R, T, AT, 2, 128, 1, 1, 2>(t, bs, nprob, total, nsteps, bar, to, s, g);
-        case 5: return launch_persistent_one<R, T, AT, 2, 256, 1, 1, 1>(t, bs, nprob, total, nsteps, bar, to, s, g);
+        case 1: return launch_persistent_one<R, T, AT, 2, 64, 1, 1, 1>(t, bs, nprob, total, nsteps, K, bar, to, s, g);
+        case 2: return launch_persistent_one<R, T, AT, 2, 64, 1, 1, 2>(t, bs, nprob, total, nsteps, K, bar, to, s, g);
+        case 4: return launch_persistent_one<R, T, AT, 2, 128, 1, 1, 2>(t, bs, nprob, total, nsteps, K, bar, to, s, g);
+        case 5: return launch_persistent_one<R, T, AT, 2, 256, 1, 1, 1>(t, bs, nprob, total, nsteps, K, bar, to, s, g);
         }
     }
     return hipErrorInvalidValue;
@@ -274,30 +288,30 @@ static hipError_t launch_persistent_rt(int ndim, int variant, const StepArgs* t,
 
 template <int R>
 static hipError_t launch_persistent_r(int ndim, int dtype, int acc_dtype, int variant, const StepArgs* t,
-                                      const int32_t* bs, int nprob, int total, int nsteps, unsigned* bar,
+                                      const int32_t* bs, int nprob, int total, int nsteps, int K, unsigned* bar,
                                       long long to, hipStream_t s, int* g)
 {
-    if (dtype == 1) return launch_persistent_rt<R, double, double>(ndim, variant, t, bs, nprob, total, nsteps, bar, to, s, g);
-    if (acc_dtype == 1) return launch_persistent_rt<R, float, double>(ndim, variant, t, bs, nprob, total, nsteps, bar, to, s, g);
-    return launch_persistent_rt<R, float, float>(ndim, variant, t, bs, nprob, total, nsteps, bar, to, s, g);
+    if (dtype == 1) return launch_persistent_rt<R, double, double>(ndim, variant, t, bs, nprob, total, nsteps, K, bar, to, s, g);
+    if (acc_dtype == 1) return launch_persistent_rt<R, float, double>(ndim, variant, t, bs, nprob, total, nsteps, K, bar, to, s, g);
+    return launch_persistent_rt<R, float, float>(ndim, variant, t, bs, nprob, total, nsteps, K, bar, to, s, g);
 }
 
 hipError_t launch_step_persistent(int ndim, int r, int dtype, int acc_dtype, int variant,
-                                  const StepArgs* d_table, const int32_t* d_block_start, int nprob,
-                                  int total_blocks, int nsteps, unsigned* d_barrier,
+                                  const StepArgs* d_table, const int32_t* d_group_start, int nprob,
+                                  int total_groups, int nsteps, int chunks_per_group, unsigned* d_barrier,
                                   long long timeout_ticks, hipStream_t s, int* grid_used)
 {
     switch (r) {
-    case 1: return launch_persistent_r<1>(ndim, dtype, acc_dtype, variant, d_table, d_block_start, nprob, total_blocks, nsteps, d_barrier, timeout_ticks, s, grid_used);
-    case 2: return launch_persistent_r<2>(ndim, dtype, acc_dtype, variant, d_table, d_block_start, nprob, total_blocks, nsteps, d_barrier, timeout_ticks, s, grid_used);
-    case 4: return launch_persistent_r<4>(ndim, dtype, acc_dtype, variant, d_table, d_block_start, nprob, total_blocks, nsteps, d_barrier, timeout_ticks, s, grid_used);
+    case 1: return launch_persistent_r<1>(ndim, dtype, acc_dtype, variant, d_table, d_group_start, nprob, total_groups, nsteps, chunks_per_group, d_barrier, timeout_ticks, s, grid_used);
+    case 2: return launch_persistent_r<2>(ndim, dtype, acc_dtype, variant, d_table, d_group_start, nprob, total_groups, nsteps, chunks_per_group, d_barrier, timeout_ticks, s, grid_used);
+    case 4: return launch_persistent_r<4>(ndim, dtype, acc_dtype, variant, d_table, d_group_start, nprob, total_groups, nsteps, chunks_per_group, d_barrier, timeout_ticks, s, grid_used);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t persistent_capacity(int ndim, int r, int dtype, int acc_dtype, int variant, int* blocks)
 {
-    return launch_step_persistent(ndim, r, dtype, acc_dtype, variant, nullptr, nullptr, 0, 0, 0, nullptr, 0,
+    return launch_step_persistent(ndim, r, dtype, acc_dtype, variant, nullptr, nullptr, 0, 0, 0, 1, nullptr, 0,
                                   nullptr, blocks);
 }
 

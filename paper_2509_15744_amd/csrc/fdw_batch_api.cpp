@@ -37,6 +37,9 @@ struct fd_batch_plan {
     double* d_part = nullptr;        // reduction partials
     unsigned* d_bar = nullptr;       // persistent launches: error flag, then per-tile progress
     int capacity = 0;                // persistent launches: blocks of the grid
+    int group_chunks = 1;            // persistent launches: chunks per group
+    int ngroups = 0;                 // persistent launches: groups of all problems
+    int32_t* d_gstart = nullptr;     // persistent launches: first group of each problem
     long long timeout_ticks = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sweep timing (opts.timing)
     bool timed = false;
@@ -45,42 +48,37 @@ struct fd_batch_plan {
 
 namespace {
 
-// Axis-0 chunks of a persistent plan: the shortest common chunk length L at which the
-// union of the problems' tiles fits the grid, so that a block marches about one tile
-// per step (tiles of L rows, except a problem's last chunk and problems shorter than
-// L).  Short chunks would make each block march many tiles per step, each paying its
-// queue fill and its wait for the neighbouring tiles.  A caller's chunk stays if it is
-// at least r rows long (a tile's queue then reaches only the adjacent chunks).
-int persistent_chunks(std::vector<Geo>& G, int cap)
+// Groups of a persistent plan: each chunk keeps the length the per-step launches use
+// (short in 2D: every chunk's march starts with its queue fill, whose loads are in
+// flight together), and K consecutive chunks of a tile column form a group, the unit
+// a block takes per step and the unit of the waits.  K is the smallest number at
+// which the groups fit the grid (about one group per block and step; the waits and
+// the release of each group are paid once per K chunks) while a group spans at least
+// r planes (its chunks' queues then reach only the adjacent groups).
+int persistent_groups(const std::vector<Plan>& P, const std::vector<Geo>& G, int cap, int* K_out)
 {
-    const fdw::Variant v = fdw::variant_shape(G[0].ndim, G[0].variant);
-    int hi = 1;
-    for (const Geo& g : G) {
-        if (g.chunk > 0 && g.chunk < g.r && g.chunk < g.n0)
-            return fail(FD_E_ARG, "persistent launches need chunks of at least r rows");
-        hi = std::max(hi, g.n0);
+    int kmin = 1, kmax = 1;
+    for (size_t p = 0; p < P.size(); ++p) {
+        kmin = std::max(kmin, (G[p].r + P[p].chunk - 1) / P[p].chunk);
+        kmax = std::max(kmax, P[p].nch);
     }
-    auto tiles_at = [&](int L) {
+    auto groups_at = [&](int K) {
         int64_t n = 0;
-        for (const Geo& g : G) {
-            const int64_t plane = (int64_t)((g.n2 + v.tz - 1) / v.tz) * ((g.n1 + v.ty - 1) / v.ty);
-            const int c = std::min(g.chunk > 0 ? g.chunk : L, g.n0);
-            n += plane * ((g.n0 + c - 1) / c);
-        }
+        for (const Plan& q : P) n += (int64_t)q.ntz * q.nty * ((q.nch + K - 1) / K);
         return n;
     };
-    int lo = std::min(G[0].r, hi);
-    if (tiles_at(hi) > cap) {
-        lo = hi;   // even whole-axis chunks exceed the grid: blocks take several tiles
+    int lo = std::min(kmin, kmax), hi = std::max(kmin, kmax);
+    if (groups_at(hi) > cap) {
+        lo = hi;   // even whole columns exceed the grid: blocks take several groups
     } else {
-        while (lo < hi) {   // smallest L with tiles_at(L) <= cap (tiles_at falls as L grows)
+        while (lo < hi) {   // smallest K with groups_at(K) <= cap (groups_at falls as K grows)
             const int mid = lo + (hi - lo) / 2;
-            if (tiles_at(mid) <= cap) hi = mid;
+            if (groups_at(mid) <= cap) hi = mid;
             else lo = mid + 1;
         }
     }
-    for (Geo& g : G)
-        if (g.chunk <= 0) g.chunk = std::min(lo, g.n0);
+    if (groups_at(lo) > (1 << 28)) return fail(FD_E_ARG, "too many groups for a persistent launch");
+    *K_out = lo;
     return FD_OK;
 }
 
@@ -132,7 +130,6 @@ int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStre
     if (B.G0.persistent) {
         HIPCHK(fdw::persistent_capacity(G[0].ndim, G[0].r, G[0].dtype, G[0].acc_dtype, G[0].variant, &B.capacity));
         if (B.capacity < 8) return fail(FD_E_DEVICE, "persistent launch: the step kernel does not fit the device");
-        if ((rc = persistent_chunks(G, B.capacity))) return rc;
     }
     {
         std::vector<const Geo*> gs;
@@ -173,6 +170,15 @@ int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStre
         nt_max = std::max(nt_max, probs[p].nt);
     }
     B.total = bstart[nprob];
+    std::vector<int32_t> gstart(nprob + 1, 0);
+    if (B.G0.persistent) {
+        if ((rc = persistent_groups(B.P, G, B.capacity, &B.group_chunks))) return rc;
+        for (int p = 0; p < nprob; ++p) {
+            const Plan& q = B.P[p];
+            gstart[p + 1] = gstart[p] + q.ntz * q.nty * ((q.nch + B.group_chunks - 1) / B.group_chunks);
+        }
+        B.ngroups = gstart[nprob];
+    }
     // step argument tables: forward steps n = 0..nt_max-1, backward steps aligned at
     // their ends (backward step i runs j = nt_p - 1 - i of problem p while j >= 1)
     B.nfw = nt_max;
@@ -239,7 +245,9 @@ int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStre
     if (B.G0.persistent) {
         // error flag and per-tile progress, zeroed by kernels in every run; the bounded
         // wait in device wall-clock ticks
-        HIPCHK(sc.get((void**)&B.d_bar, sizeof(unsigned) * ((size_t)fdw::kProgressWords + B.total)));
+        HIPCHK(sc.get((void**)&B.d_bar, sizeof(unsigned) * ((size_t)fdw::kProgressWords + B.ngroups)));
+        HIPCHK(sc.get((void**)&B.d_gstart, sizeof(int32_t) * gstart.size()));
+        HIPCHK(hipMemcpyAsync(B.d_gstart, gstart.data(), sizeof(int32_t) * gstart.size(), hipMemcpyHostToDevice, s));
         int dev = 0, khz = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
@@ -266,9 +274,10 @@ int plan_sweep(const fd_batch_plan& B, int first, int count, hipStream_t s)
         int grid = 0;
         // the arrival count, the number of blocks taking part and the tiles' progress
         // start at zero in every sweep (the error flag, word 2, spans the run)
-        HIPCHK(fdw::launch_zero(B.d_bar + 4, sizeof(unsigned) * ((size_t)fdw::kProgressWords - 4 + B.total), s));
-        HIPCHK(fdw::launch_step_persistent(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant, rows, B.d_bstart,
-                                           B.nprob, B.total, count, B.d_bar, B.timeout_ticks, s, &grid));
+        HIPCHK(fdw::launch_zero(B.d_bar + 4, sizeof(unsigned) * ((size_t)fdw::kProgressWords - 4 + B.ngroups), s));
+        HIPCHK(fdw::launch_step_persistent(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant, rows, B.d_gstart,
+                                           B.nprob, B.ngroups, count, B.group_chunks, B.d_bar, B.timeout_ticks, s,
+                                           &grid));
         return FD_OK;
     }
     for (int i = 0; i < count; ++i)
@@ -346,6 +355,13 @@ int plan_timing(fd_batch_plan* B, fd_timing* t)
     t->fwd_launches = B->nfw;
     t->bwd_ms = b;
     t->bwd_launches = std::max(B->nbw, 0);
+    t->fwd_pair_launches = t->bwd_pair_launches = 0;
+    t->persistent_blocks = 0;
+    if (B->d_bar) {   // word 5: the blocks that took part in the last sweep
+        unsigned part = 0;
+        HIPCHK(hipMemcpy(&part, B->d_bar + 5, sizeof(part), hipMemcpyDeviceToHost));
+        t->persistent_blocks = (int32_t)part;
+    }
     return FD_OK;
 }
 

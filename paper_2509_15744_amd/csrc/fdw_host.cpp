@@ -776,6 +776,7 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
             G.timing->fwd_ms = tm.ms();
             G.timing->fwd_launches = pair_launches + (nt & 1);
             G.timing->fwd_pair_launches = pair_launches;
+            G.timing->persistent_blocks = 0;
         }
         return FD_OK;
     }
@@ -802,6 +803,7 @@ int forward_sweep(const Geo& G, const Plan& P, const void* c, const fd_acq* acq,
         G.timing->fwd_ms = tm.ms();
         G.timing->fwd_launches = nt * (int)P.groups.size();
         G.timing->fwd_pair_launches = 0;
+        G.timing->persistent_blocks = 0;
     }
     return FD_OK;
 }

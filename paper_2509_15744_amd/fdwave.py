@@ -55,7 +55,8 @@ class fd_acq(ctypes.Structure):
 class fd_timing(ctypes.Structure):
     _fields_ = [("fwd_ms", ctypes.c_double), ("fwd_launches", ctypes.c_int32),
                 ("bwd_ms", ctypes.c_double), ("bwd_launches", ctypes.c_int32),
-                ("fwd_pair_launches", ctypes.c_int32), ("bwd_pair_launches", ctypes.c_int32)]
+                ("fwd_pair_launches", ctypes.c_int32), ("bwd_pair_launches", ctypes.c_int32),
+                ("persistent_blocks", ctypes.c_int32)]
 
 
 class fd_opts(ctypes.Structure):
