@@ -117,11 +117,11 @@ typedef struct fd_opts {
     int32_t max_group;  /* shots advanced per launch: 1, 2 or 4 (0: the largest the variant has) */
     int32_t graph;      /* batched calls: 1 replays each sweep as one captured hipGraph */
     int32_t persistent; /* batched calls: 1 runs each sweep as one launch whose running blocks
-                           own fixed sets of tiles and walk all steps, a tile starting a step
-                           once its neighbouring tiles have finished the previous one; with
-                           chunk 0 the chunks are sized to about one tile per block and
-                           step */
-    int32_t barrier_timeout_us; /* persistent launches: longest wait of a tile for its
+                           own fixed sets of groups (columns of consecutive chunks, about
+                           one group per block and step) and walk all steps, a group
+                           starting a step once its neighbouring groups have finished the
+                           previous one */
+    int32_t barrier_timeout_us; /* persistent launches: longest wait of a group for its
                            neighbours before the launch gives up and the call returns
                            FD_E_DEVICE (0: 2 s) */
     int32_t variant_plain; /* tile variant of the step launches that do not touch the
@@ -342,13 +342,13 @@ int fd_sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, doub
 /* Alg. 1 for `nprob` independent problems of uneven sizes in lock-step: every time
  * step of all problems is one launch over the union of their tiles (problems that
  * have no step there skip it), the backward sweeps are aligned at their ends.  With
- * opts->persistent each sweep is one launch whose blocks walk all its steps (a tile
- * waits for its neighbouring tiles' previous step, not for the whole grid).  This is
- * a batch plan (below) created,
- * run once and destroyed: with opts->graph the run is captured into a hipGraph and
- * launched as one graph.  J_host [nprob] receives each problem's J;
- * synchronises `stream`.  Needs opts variant 0, 1 or 2 (2D also 4 and 5).  FD_E_DEVICE
- * if a persistent launch's wait for neighbouring tiles timed out. */
+ * opts->persistent each sweep is one launch whose blocks walk all its steps (a group
+ * of chunks waits for its neighbouring groups' previous step, not for the whole
+ * grid).  This is a batch plan (below) created, run once and destroyed: with
+ * opts->graph the run is captured into a hipGraph and launched as one graph.  J_host
+ * [nprob] receives each problem's J; synchronises `stream`.  Needs opts variant 0, 1
+ * or 2 (2D also 4 and 5).  FD_E_DEVICE if a persistent launch's wait for
+ * neighbouring groups timed out. */
 int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, double* J_host,
                                    const fd_opts* opts, void* stream);
 
@@ -379,7 +379,7 @@ int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, doubl
  * that may be replayed: each replay reads the values c, wavelet and observed hold
  * then.  The CFL check of fd_batch_plan_create is not repeated: a c that has become
  * unstable since gives non-finite values.  With opts.persistent every J of the run
- * is NaN if a wait for neighbouring tiles timed out.  Runs of one plan share its state: they
+ * is NaN if a wait for neighbouring groups timed out.  Runs of one plan share its state: they
  * must not overlap (one stream, or ordered by the caller).  FD_E_ARG for a null plan
  * or J; a failed launch gives FD_E_DEVICE.
  *

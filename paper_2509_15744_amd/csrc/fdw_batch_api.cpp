@@ -429,8 +429,8 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         HIPCHK(hipMemcpyAsync(&flag, B->d_bar + 2, sizeof(flag), hipMemcpyDeviceToHost, ws));
         HIPCHK(hipStreamSynchronize(ws));
         if (flag != 0)
-            return fail(FD_E_DEVICE, "persistent launch: a wait for neighbouring tiles timed out "
-                                     "(barrier_timeout_us is shorter than a tile's step); the "
+            return fail(FD_E_DEVICE, "persistent launch: a wait for neighbouring groups timed out "
+                                     "(barrier_timeout_us is shorter than a group's step); the "
                                      "results are invalid");
     }
     HIPCHK(hipMemcpyAsync(J_host, J_dev, sizeof(double) * nprob, hipMemcpyDeviceToHost, ws));
