@@ -220,6 +220,21 @@ __device__ __forceinline__ void events_at_plane(PlaneEvents& pe, const StepArgs&
     }
 }
 
+// First staged event of plane slot eb whose key is at least k: the keys ascend within
+// a plane (the events are sorted by lane, then kind), so a lane finds its own events
+// by bisection instead of scanning every event of the plane.
+template <typename T>
+__device__ __forceinline__ int first_key(const EventStage<T>& st, int eb, int n, int k)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (st.key[eb][mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Point force at tile lane `lane`, shot slot s of this plane: the sources there and,
 // when injecting, the receivers, summed in event order.
 template <typename T>
@@ -228,9 +243,11 @@ __device__ __forceinline__ T point_force(const PlaneEvents& pe, const StepArgs& 
 {
     T f = (T)0;
     if (pe.staged) {
+        const int n = pe.e - pe.ea;
         const int want = ((lane << 8) | (s << 1)) >> 1;
-        for (int t = 0; t < pe.e - pe.ea; ++t) {
+        for (int t = first_key(st, pe.eb, n, lane << 8); t < n; ++t) {
             const int key = st.key[pe.eb][t];
+            if ((key >> 8) != lane) break;
             if ((key >> 1) == want && ((key & 1) == EV_SRC || a.inject_rec)) f += st.val[pe.eb][t];
         }
     } else {
@@ -252,9 +269,10 @@ __device__ __forceinline__ void sample_receivers(const PlaneEvents& pe, const St
                                                  const EventStage<T>& st, int lane, int s, T uni)
 {
     if (pe.staged) {
+        const int n = pe.e - pe.ea;
         const int want = (lane << 8) | (s << 1) | EV_REC;
-        for (int t = 0; t < pe.e - pe.ea; ++t) {
-            if (st.key[pe.eb][t] != want) continue;
+        for (int t = first_key(st, pe.eb, n, want); t < n; ++t) {
+            if (st.key[pe.eb][t] != want) break;
             const int64_t o = (int64_t)a.row_rec * a.nrec + st.idx[pe.eb][t];
             if (a.traces) ((GLOBAL_AS T*)a.traces)[o] = uni;
             if (a.resid) ((GLOBAL_AS T*)a.resid)[o] = uni - st.obs[pe.eb][t];
