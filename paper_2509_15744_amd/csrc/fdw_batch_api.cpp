@@ -37,9 +37,10 @@ struct fd_batch_plan {
     double* d_part = nullptr;        // reduction partials
     unsigned* d_bar = nullptr;       // persistent launches: error flag, then per-tile progress
     int capacity = 0;                // persistent launches: blocks of the grid
-    int group_chunks = 1;            // persistent launches: chunks per group
-    int ngroups = 0;                 // persistent launches: groups of all problems
-    int32_t* d_gstart = nullptr;     // persistent launches: first group of each problem
+    int ncand = 0;                   // persistent launches: group plans (chunks per group)
+    int ngroups = 0;                 // persistent launches: groups of all problems, plan 0
+    int32_t* d_candk = nullptr;      // persistent launches: chunks per group of each plan
+    int32_t* d_gstart = nullptr;     // persistent launches: first group of each problem, per plan
     long long timeout_ticks = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sweep timing (opts.timing)
     bool timed = false;
@@ -48,37 +49,57 @@ struct fd_batch_plan {
 
 namespace {
 
-// Groups of a persistent plan: each chunk keeps the length the per-step launches use
-// (short in 2D: every chunk's march starts with its queue fill, whose loads are in
-// flight together), and K consecutive chunks of a tile column form a group, the unit
-// a block takes per step and the unit of the waits.  K is the smallest number at
-// which the groups fit the grid (about one group per block and step; the waits and
-// the release of each group are paid once per K chunks) while a group spans at least
-// r planes (its chunks' queues then reach only the adjacent groups).
-int persistent_groups(const std::vector<Plan>& P, const std::vector<Geo>& G, int cap, int* K_out)
+// Group plans of a persistent plan.  Each chunk keeps the length the per-step launches
+// use (short in 2D: every chunk's march starts with its queue fill, whose loads are in
+// flight together), and K consecutive chunks of a tile column form a group, the unit a
+// block takes per step and the unit of the waits; a group spans at least r planes (its
+// chunks' queues then reach only the adjacent groups).  Plan 0 takes the smallest K at
+// which the groups fit the grid (`cap` blocks), the next plans the smallest K at which
+// they fit 63/64, 62/64, ... of it, down to half.  How many blocks run together is
+// known only inside the launch; the kernel then takes the first plan whose groups do
+// not outnumber them, so each block holds one group per step instead of some holding
+// two (whose blocks the neighbours' waits would then all pace).  Fills *cand_k
+// (ascending) and *gstart (nprob + 1 group starts per plan).
+int persistent_group_plans(const std::vector<Plan>& P, const std::vector<Geo>& G, int cap,
+                           std::vector<int32_t>* cand_k, std::vector<int32_t>* gstart)
 {
     int kmin = 1, kmax = 1;
     for (size_t p = 0; p < P.size(); ++p) {
         kmin = std::max(kmin, (G[p].r + P[p].chunk - 1) / P[p].chunk);
         kmax = std::max(kmax, P[p].nch);
     }
+    kmin = std::min(kmin, kmax);
     auto groups_at = [&](int K) {
         int64_t n = 0;
         for (const Plan& q : P) n += (int64_t)q.ntz * q.nty * ((q.nch + K - 1) / K);
         return n;
     };
-    int lo = std::min(kmin, kmax), hi = std::max(kmin, kmax);
-    if (groups_at(hi) > cap) {
-        lo = hi;   // even whole columns exceed the grid: blocks take several groups
-    } else {
-        while (lo < hi) {   // smallest K with groups_at(K) <= cap (groups_at falls as K grows)
+    auto smallest_fitting = [&](int64_t target) {   // groups_at falls as K grows
+        if (groups_at(kmax) > target) return kmax;   // even whole columns exceed it
+        int lo = kmin, hi = kmax;
+        while (lo < hi) {
             const int mid = lo + (hi - lo) / 2;
-            if (groups_at(mid) <= cap) hi = mid;
+            if (groups_at(mid) <= target) hi = mid;
             else lo = mid + 1;
         }
+        return lo;
+    };
+    cand_k->clear();
+    for (int i = 0; i <= 32; ++i) {
+        const int K = smallest_fitting((int64_t)cap - (int64_t)cap * i / 64);
+        if (cand_k->empty() || K > cand_k->back()) cand_k->push_back(K);
     }
-    if (groups_at(lo) > (1 << 28)) return fail(FD_E_ARG, "too many groups for a persistent launch");
-    *K_out = lo;
+    if (groups_at(cand_k->front()) > (1 << 28)) return fail(FD_E_ARG, "too many groups for a persistent launch");
+    const size_t np = P.size();
+    gstart->assign(cand_k->size() * (np + 1), 0);
+    for (size_t j = 0; j < cand_k->size(); ++j) {
+        const int K = (*cand_k)[j];
+        int32_t* gs = gstart->data() + j * (np + 1);
+        for (size_t p = 0; p < np; ++p) {
+            const Plan& q = P[p];
+            gs[p + 1] = gs[p] + q.ntz * q.nty * ((q.nch + K - 1) / K);
+        }
+    }
     return FD_OK;
 }
 
@@ -170,13 +191,10 @@ int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStre
         nt_max = std::max(nt_max, probs[p].nt);
     }
     B.total = bstart[nprob];
-    std::vector<int32_t> gstart(nprob + 1, 0);
+    std::vector<int32_t> cand_k, gstart;
     if (B.G0.persistent) {
-        if ((rc = persistent_groups(B.P, G, B.capacity, &B.group_chunks))) return rc;
-        for (int p = 0; p < nprob; ++p) {
-            const Plan& q = B.P[p];
-            gstart[p + 1] = gstart[p] + q.ntz * q.nty * ((q.nch + B.group_chunks - 1) / B.group_chunks);
-        }
+        if ((rc = persistent_group_plans(B.P, G, B.capacity, &cand_k, &gstart))) return rc;
+        B.ncand = (int)cand_k.size();
         B.ngroups = gstart[nprob];
     }
     // step argument tables: forward steps n = 0..nt_max-1, backward steps aligned at
@@ -248,6 +266,8 @@ int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStre
         HIPCHK(sc.get((void**)&B.d_bar, sizeof(unsigned) * ((size_t)fdw::kProgressWords + B.ngroups)));
         HIPCHK(sc.get((void**)&B.d_gstart, sizeof(int32_t) * gstart.size()));
         HIPCHK(hipMemcpyAsync(B.d_gstart, gstart.data(), sizeof(int32_t) * gstart.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(sc.get((void**)&B.d_candk, sizeof(int32_t) * cand_k.size()));
+        HIPCHK(hipMemcpyAsync(B.d_candk, cand_k.data(), sizeof(int32_t) * cand_k.size(), hipMemcpyHostToDevice, s));
         int dev = 0, khz = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
@@ -275,9 +295,9 @@ int plan_sweep(const fd_batch_plan& B, int first, int count, hipStream_t s)
         // the arrival count, the number of blocks taking part and the tiles' progress
         // start at zero in every sweep (the error flag, word 2, spans the run)
         HIPCHK(fdw::launch_zero(B.d_bar + 4, sizeof(unsigned) * ((size_t)fdw::kProgressWords - 4 + B.ngroups), s));
-        HIPCHK(fdw::launch_step_persistent(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant, rows, B.d_gstart,
-                                           B.nprob, B.ngroups, count, B.group_chunks, B.d_bar, B.timeout_ticks, s,
-                                           &grid));
+        const fdw::GroupPlans gp = {B.d_candk, B.d_gstart, B.ncand, B.ngroups};
+        HIPCHK(fdw::launch_step_persistent(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant, rows, gp, B.nprob,
+                                           count, B.d_bar, B.timeout_ticks, s, &grid));
         return FD_OK;
     }
     for (int i = 0; i < count; ++i)
@@ -429,9 +449,9 @@ int batched(const fd_problem* probs, int nprob, double* J_host, const fd_opts* o
         HIPCHK(hipMemcpyAsync(&flag, B->d_bar + 2, sizeof(flag), hipMemcpyDeviceToHost, ws));
         HIPCHK(hipStreamSynchronize(ws));
         if (flag != 0)
-            return fail(FD_E_DEVICE, "persistent launch: a wait for neighbouring groups timed out "
-                                     "(barrier_timeout_us is shorter than a group's step); the "
-                                     "results are invalid");
+            return fail(FD_E_DEVICE, "persistent launch: a wait for the launch's other blocks or for "
+                                     "neighbouring groups timed out (barrier_timeout_us is shorter "
+                                     "than a group's step); the results are invalid");
     }
     HIPCHK(hipMemcpyAsync(J_host, J_dev, sizeof(double) * nprob, hipMemcpyDeviceToHost, ws));
     HIPCHK(hipStreamSynchronize(ws));

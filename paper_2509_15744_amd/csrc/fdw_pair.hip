@@ -268,7 +268,7 @@ __global__ __launch_bounds__(512) void pair_kernel(PairArgs p)
             for (int j = 1; j <= R; ++j) lap += w[j - 1] * ((L0[l0 + j * Z0] - u0) + (L0[l0 - j * Z0] - u0));
 #pragma unroll
             for (int j = 1; j <= R; ++j) lap += w[j - 1] * ((L0[l0 + j] - u0) + (L0[l0 - j] - u0));
-            if (pa.has) lap += point_force(pa, aa, est_a, lane, 0);
+            if (pa.has) lap += point_force<false>(pa, aa, est_a, lane, 0);
             const T coef = a.coef_direct ? cv : dt2 * cv * cv;
             return (u0 + u0) - um + coef * lap;
         };
@@ -293,14 +293,14 @@ __global__ __launch_bounds__(512) void pair_kernel(PairArgs p)
             for (int j = 1; j <= R; ++j) lap += w[j - 1] * ((L1[l1_t + j * Z1] - u1) + (L1[l1_t - j * Z1] - u1));
 #pragma unroll
             for (int j = 1; j <= R; ++j) lap += w[j - 1] * ((L1[l1_t + j] - u1) + (L1[l1_t - j] - u1));
-            if (pb2.has) lap += point_force(pb2, a2, est_b2, lane_t, 0);
+            if (pb2.has) lap += point_force<false>(pb2, a2, est_b2, lane_t, 0);
             const T cv = cq[0];
             const T coef = a.coef_direct ? cv : dt2 * cv * cv;
             const T u0 = qt[0];   // u^n(x2)
             const T v2 = (u1 + u1) - u0 + coef * lap;
             if (live) {
-                if (a.sample && pb1.has) sample_receivers(pb1, a, est_b1, lane_t, 0, u1);
-                if (a.sample && pb2.has) sample_receivers(pb2, a2, est_b2, lane_t, 0, v2);
+                if (a.sample && pb1.has) sample_receivers<false>(pb1, a, est_b1, lane_t, 0, u1);
+                if (a.sample && pb2.has) sample_receivers<false>(pb2, a2, est_b2, lane_t, 0, v2);
                 const int64_t xo2 = (int64_t)x2 * ps + off_t;
                 __builtin_nontemporal_store(v2, out2 + xo2);
                 if (terms) {

@@ -221,8 +221,11 @@ __device__ __forceinline__ void events_at_plane(PlaneEvents& pe, const StepArgs&
 }
 
 // First staged event of plane slot eb whose key is at least k: the keys ascend within
-// a plane (the events are sorted by lane, then kind), so a lane finds its own events
-// by bisection instead of scanning every event of the plane.
+// a plane (the events are sorted by lane, then kind), so a lane can find its own events
+// by bisection instead of scanning every event of the plane.  Measured, this pays in 2D
+// (rows that hold many shots' sources or a receiver line: +6% on 32 shots of 2048²)
+// and costs in 3D (planes with few events, where the longer code slowed the 1024³
+// sweep by 1.7%), so the 3D kernels keep the scan (BISECT = false below).
 template <typename T>
 __device__ __forceinline__ int first_key(const EventStage<T>& st, int eb, int n, int k)
 {
@@ -237,7 +240,7 @@ __device__ __forceinline__ int first_key(const EventStage<T>& st, int eb, int n,
 
 // Point force at tile lane `lane`, shot slot s of this plane: the sources there and,
 // when injecting, the receivers, summed in event order.
-template <typename T>
+template <bool BISECT, typename T>
 __device__ __forceinline__ T point_force(const PlaneEvents& pe, const StepArgs& a,
                                          const EventStage<T>& st, int lane, int s)
 {
@@ -245,9 +248,9 @@ __device__ __forceinline__ T point_force(const PlaneEvents& pe, const StepArgs& 
     if (pe.staged) {
         const int n = pe.e - pe.ea;
         const int want = ((lane << 8) | (s << 1)) >> 1;
-        for (int t = first_key(st, pe.eb, n, lane << 8); t < n; ++t) {
+        for (int t = BISECT ? first_key(st, pe.eb, n, lane << 8) : 0; t < n; ++t) {
             const int key = st.key[pe.eb][t];
-            if ((key >> 8) != lane) break;
+            if (BISECT && (key >> 8) != lane) break;
             if ((key >> 1) == want && ((key & 1) == EV_SRC || a.inject_rec)) f += st.val[pe.eb][t];
         }
     } else {
@@ -264,15 +267,18 @@ __device__ __forceinline__ T point_force(const PlaneEvents& pe, const StepArgs& 
 }
 
 // Trace and residual of the receivers at lane `lane`, shot slot s, for the new level.
-template <typename T>
+template <bool BISECT, typename T>
 __device__ __forceinline__ void sample_receivers(const PlaneEvents& pe, const StepArgs& a,
                                                  const EventStage<T>& st, int lane, int s, T uni)
 {
     if (pe.staged) {
         const int n = pe.e - pe.ea;
         const int want = (lane << 8) | (s << 1) | EV_REC;
-        for (int t = first_key(st, pe.eb, n, want); t < n; ++t) {
-            if (st.key[pe.eb][t] != want) break;
+        for (int t = BISECT ? first_key(st, pe.eb, n, want) : 0; t < n; ++t) {
+            if (st.key[pe.eb][t] != want) {
+                if (BISECT) break;
+                continue;
+            }
             const int64_t o = (int64_t)a.row_rec * a.nrec + st.idx[pe.eb][t];
             if (a.traces) ((GLOBAL_AS T*)a.traces)[o] = uni;
             if (a.resid) ((GLOBAL_AS T*)a.resid)[o] = uni - st.obs[pe.eb][t];
@@ -428,7 +434,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
     load_ops(cur, x0, false);
 
     // events: a plane's sources and receivers (and their wavelet, adjoint force and
-    // observed values) are staged in LDS, so lanes scan them without global loads
+    // observed values) are staged in LDS, so lanes find theirs without global loads
     __shared__ EventStage<T> est;
     PlaneEvents pe;
     events_begin(pe, a, b);
@@ -484,7 +490,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                     for (int j = 1; j <= R; ++j)
                         lap += w[j - 1] * ((L[s0 + i + j] - u0) + (L[s0 + i - j] - u0));
 
-                    if (pe.has) lap += point_force(pe, a, est, lane0[k] + i, s);
+                    if (pe.has) lap += point_force<NDIM == 2>(pe, a, est, lane0[k] + i, s);
 
                     const T uni = (u0 + u0) - el<T, VZ>(cur.u[s][k], i) + coef * lap;
                     set_el<T, VZ>(un[s], i, uni);
@@ -499,7 +505,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, const int b, T* __r
                         // one explicit rounding order, which the two-step launches repeat
                         dsum += fma(d, d, dp * dp);
                     }
-                    if (a.sample && pe.has) sample_receivers(pe, a, est, lane0[k] + i, s, uni);
+                    if (a.sample && pe.has) sample_receivers<NDIM == 2>(pe, a, est, lane0[k] + i, s, uni);
                 }
                 if (rd_acc) {
                     const AT tot = rd_part ? dsum + (AT)el<float, VZ>(cur.pt[k], i) : dsum;

@@ -257,12 +257,12 @@ __device__ __forceinline__ void vd_body(const StepArgs& a, const int b, T* __res
                 face(Lu[lo + i - 1], Lb[lo + i - 1]);
                 face(Lu[lo + i + 1], Lb[lo + i + 1]);
                 lap *= inv_dx2;
-                if (pe.has) lap += point_force(pe, a, est, lane0[k] + i, 0);
+                if (pe.has) lap += point_force<false>(pe, a, est, lane0[k] + i, 0);
                 const T cui = el<T, VZ>(cu[k], i);
                 const T coef = dt2 * recip(el<T, VZ>(cm[k], i));
                 const T uni = (u0 + u0) - cui + coef * lap;
                 set_el<T, VZ>(un, i, uni);
-                if (a.sample && pe.has) sample_receivers(pe, a, est, lane0[k] + i, 0, uni);
+                if (a.sample && pe.has) sample_receivers<false>(pe, a, est, lane0[k] + i, 0, uni);
                 if (use_acc) {
                     const AT d = (AT)(uni - u0);
                     const AT dp = a.acc_prev ? (AT)(u0 - cui) : (AT)0;

@@ -184,9 +184,9 @@ def test_persistent_wait_timeout_is_reported(fdw):
 
 def test_persistent_blocks_take_several_tiles(fdw):
     """With 4-row chunks a 2048 x 2048 problem has far more tiles than the grid has
-    blocks, so each block marches many tiles per step and tiles wait for neighbours
-    that other blocks reach later in the step; the result equals the per-step launches
-    bitwise."""
+    blocks, so each group holds many chunks and groups wait for neighbours that other
+    blocks (on this XCD or another) reach later in the step; the result equals the
+    per-step launches bitwise."""
     f32 = torch.float32
     q = wl.small_random((2048, 2048), order=8, nt=8, dtype="f32", seed=77, nsrc=3, nrec=40)
     c, w = to_dev(q.c, f32), to_dev(q.wavelet, f32)
@@ -198,6 +198,28 @@ def test_persistent_blocks_take_several_tiles(fdw):
     Js2 = fdw.fd_adjoint_sensitivity_batched(items, persistent=False, chunk=4)
     assert Js == Js2 and torch.equal(g, items[0].grad)
     assert torch.isfinite(g).all()
+
+
+def test_persistent_blocks_take_several_groups(fdw):
+    """3D problems whose whole tile columns (64 x 8 tiles over a 1024 x 1024 cross-
+    section: 2048 of them, plus a small second problem) outnumber the blocks of the
+    grid, so even the largest groups leave blocks holding two or more per step; the
+    result equals the per-step launches bitwise."""
+    f32 = torch.float32
+    items = []
+    for i, shape in enumerate([(24, 1024, 1024), (40, 70, 130)]):
+        q = wl.small_random(shape, order=8, nt=5, dtype="f32", seed=90 + i, nsrc=2, nrec=30)
+        c, w = to_dev(q.c, f32), to_dev(q.wavelet, f32)
+        obs = torch.zeros((q.nt, len(q.rec)), dtype=f32, device="cuda")
+        items.append(fdw.Problem(c, 1.0, 8, q.src, w, q.rec, q.dt, q.nt, obs, 0.1))
+    say("persistent several groups per block, 3D")
+    t = fdw.fd_timing()
+    Js = fdw.fd_adjoint_sensitivity_batched(items, persistent=True, chunk=8, variant=1, timing=t)
+    grads = [it.grad.clone() for it in items]
+    Js2 = fdw.fd_adjoint_sensitivity_batched(items, persistent=False, chunk=8, variant=1)
+    assert 0 < t.persistent_blocks < 2048
+    assert Js == Js2 and all(torch.equal(g, it.grad) for g, it in zip(grads, items))
+    assert all(torch.isfinite(g).all() for g in grads)
 
 
 def test_batched_rejects_mixed_orders(fdw):
