@@ -117,10 +117,11 @@ typedef struct fd_opts {
     int32_t max_group;  /* shots advanced per launch: 1, 2 or 4 (0: the largest the variant has) */
     int32_t graph;      /* batched calls: 1 replays each sweep as one captured hipGraph */
     int32_t persistent; /* batched calls: 1 runs each sweep as one launch whose running blocks
-                           own fixed sets of groups (columns of consecutive chunks, about
-                           one group per block and step) and walk all steps, a group
-                           starting a step once its neighbouring groups have finished the
-                           previous one */
+                           (counted at run time) each own one group (a column of consecutive
+                           chunks, sized so the groups do not outnumber them; a block may
+                           own several when even whole columns do) and walk all steps, a
+                           group starting a step once its neighbouring groups have finished
+                           the previous one */
     int32_t barrier_timeout_us; /* persistent launches: longest wait of a group for its
                            neighbours before the launch gives up and the call returns
                            FD_E_DEVICE (0: 2 s) */
@@ -347,8 +348,8 @@ int fd_sens_backward(const fd_grid* grid, const void* c, const fd_acq* acq, doub
  * grid).  This is a batch plan (below) created, run once and destroyed: with
  * opts->graph the run is captured into a hipGraph and launched as one graph.  J_host
  * [nprob] receives each problem's J; synchronises `stream`.  Needs opts variant 0, 1
- * or 2 (2D also 4 and 5).  FD_E_DEVICE if a persistent launch's wait for
- * neighbouring groups timed out. */
+ * or 2 (2D also 4 and 5).  FD_E_DEVICE if a persistent launch's wait for the
+ * launch's other blocks or for neighbouring groups timed out. */
 int fd_adjoint_sensitivity_batched(const fd_problem* probs, int32_t nprob, double* J_host,
                                    const fd_opts* opts, void* stream);
 
