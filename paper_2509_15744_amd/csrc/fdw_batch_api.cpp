@@ -35,7 +35,7 @@ struct fd_batch_plan {
     fdw::StepArgs* d_tab = nullptr;  // (nfw + nbw) rows of nprob step arguments
     int32_t* d_bstart = nullptr;     // first block of each problem in a launch
     double* d_part = nullptr;        // reduction partials
-    unsigned* d_bar = nullptr;       // persistent launches: error flag, then per-tile progress
+    unsigned* d_bar = nullptr;       // persistent launches: error flag, join counters, per-group progress
     int capacity = 0;                // persistent launches: blocks of the grid
     int ncand = 0;                   // persistent launches: group plans (chunks per group)
     int ngroups = 0;                 // persistent launches: groups of all problems, plan 0
@@ -261,8 +261,8 @@ int plan_create(const fd_problem* probs, int nprob, const fd_opts* opts, hipStre
     HIPCHK(hipMemcpyAsync(B.d_tab, tab.data(), sizeof(fdw::StepArgs) * tab.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(B.d_bstart, bstart.data(), sizeof(int32_t) * bstart.size(), hipMemcpyHostToDevice, s));
     if (B.G0.persistent) {
-        // error flag and per-tile progress, zeroed by kernels in every run; the bounded
-        // wait in device wall-clock ticks
+        // error flag, join counters and per-group progress, zeroed by kernels in every
+        // run; the bounded wait in device wall-clock ticks
         HIPCHK(sc.get((void**)&B.d_bar, sizeof(unsigned) * ((size_t)fdw::kProgressWords + B.ngroups)));
         HIPCHK(sc.get((void**)&B.d_gstart, sizeof(int32_t) * gstart.size()));
         HIPCHK(hipMemcpyAsync(B.d_gstart, gstart.data(), sizeof(int32_t) * gstart.size(), hipMemcpyHostToDevice, s));
@@ -292,8 +292,9 @@ int plan_sweep(const fd_batch_plan& B, int first, int count, hipStream_t s)
     const fdw::StepArgs* rows = B.d_tab + (size_t)first * B.nprob;
     if (G0.persistent) {
         int grid = 0;
-        // the arrival count, the number of blocks taking part and the tiles' progress
-        // start at zero in every sweep (the error flag, word 2, spans the run)
+        // the join's counters (arrivals, blocks taking part, ranked, per XCD) and the
+        // groups' progress start at zero in every sweep (the error flag, word 2, spans
+        // the run)
         HIPCHK(fdw::launch_zero(B.d_bar + 4, sizeof(unsigned) * ((size_t)fdw::kProgressWords - 4 + B.ngroups), s));
         const fdw::GroupPlans gp = {B.d_candk, B.d_gstart, B.ncand, B.ngroups};
         HIPCHK(fdw::launch_step_persistent(G0.ndim, G0.r, G0.dtype, G0.acc_dtype, G0.variant, rows, gp, B.nprob,
