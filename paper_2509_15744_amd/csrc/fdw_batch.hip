@@ -39,8 +39,9 @@ __global__ __launch_bounds__(TZ*(TY / RY)) void step_multi_kernel(const StepArgs
 // finished step st - 1: those groups wrote the level it reads, and read the level it
 // overwrites.  The neighbours are the groups one over along each axis: the in-plane
 // halo reaches one tile column left/right (and, in 3D, above/below), the axis-0 queues
-// the groups before and after (a group spans at least r planes, so a mirrored cell
-// past a wall lies in the group itself or in such a neighbour).
+// the groups before and after (a group spans at least r planes, except a column's
+// last, which ends at the wall, so a mirrored cell past a wall lies in the group
+// itself or in such a neighbour).
 //
 // Waits are bounded: a group that waits longer than `timeout` wall-clock ticks sets
 // err, and every wait gives up once err is set, so the launch ends whatever happens.
@@ -63,9 +64,9 @@ __device__ __forceinline__ int xcd_id()
 // (the L1 writes through), then one thread stores the progress word.  A neighbour on
 // the same XCD reads through that same L2, so the stores are already where it will
 // look; only when a neighbour runs on another XCD (`cross`) does an agent-scope
-// release (an L2 write-back) first push them to memory, beyond this XCD's L2.  These
-// write-backs are the costly part of a group's step, and the XCD-ordered ranges of
-// groups leave them to the few groups at a range's edges.
+// release (an L2 write-back) first push them to memory, beyond this XCD's L2.  Such a
+// write-back walks the XCD's whole L2; the XCD-ordered ranges of groups leave them to
+// the few groups at a range's edges.
 __device__ __forceinline__ void publish_step(const Progress& pr, int g, int st, bool cross)
 {
     __builtin_amdgcn_s_waitcnt(0);
