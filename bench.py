@@ -24,7 +24,8 @@ and on the 256^3 differentiation workload (order 8, nt 2000) the relative errors
 the device gradients against the FP64 oracle references stored in tests/golden and
 against central finite differences of the f64 misfit on sampled cells.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build measures one GPU.
+Prints one JSON line.  ``--gpus N`` with N > 1 is refused: the benchmark measures one
+GPU (the sweep is not sharded across GPUs).
 """
 from __future__ import annotations
 
@@ -923,7 +924,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (the sweep is not sharded across GPUs); --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
