@@ -198,14 +198,14 @@ __device__ __forceinline__ void join_persistent(unsigned* bar, long long window,
 // consecutive ranges, one per XCD, sized by that XCD's blocks; a block takes the
 // groups of its XCD's range at its rank, rank + count, ...  Neighbouring groups then
 // mostly share an XCD, so their halos meet in one L2 and publishing a step needs no
-// L2 write-back; only groups with a neighbour in another range pay it.  Each group is marched chunk by chunk, every chunk with its own
-// queue fill, whose loads are in flight together, as in the per-step launches.  There
-// is no grid-wide barrier: a group waits for its neighbours' previous step only
-// (Progress), so blocks drift apart by up to a step and none idles at the end of a
-// step.  Every block handles its groups in (step, group) order, each group always in
-// the same block, and a step's work depends on the previous step's only, so the waits
-// cannot form a cycle among running blocks; the bounded waits end the launch whatever
-// happens.
+// L2 write-back; only groups with a neighbour in another range pay it.  Each group is
+// marched chunk by chunk, every chunk with its own queue fill, whose loads are in
+// flight together, as in the per-step launches.  There is no grid-wide barrier: a
+// group waits for its neighbours' previous step only (Progress), so blocks drift apart
+// by up to a step and none idles at the end of a step.  Every block handles its groups
+// in (step, group) order, each group always in the same block, and a step's work
+// depends on the previous step's only, so the waits cannot form a cycle among running
+// blocks; the bounded waits end the launch whatever happens.
 template <int R, typename T, typename AT, int NDIM, int TZ, int TY, int RY, int VZ>
 __global__ __launch_bounds__(TZ*(TY / RY)) void step_persistent_kernel(
     const StepArgs* __restrict__ table, const int32_t* __restrict__ cand_k,
